@@ -1,0 +1,206 @@
+/*
+ * sj.h -- C ABI of the MI355X (gfx950) epsilon-distance similarity self-join.
+ *
+ * Given n points in d dimensions (2 <= d <= 6 is the tuned range, 1 <= d <= 8
+ * is accepted) and a distance eps, the library returns every ordered pair
+ * (i, j) of point ids with squared Euclidean distance <= eps * eps, sorted by
+ * (i, j). This is the self-join of Section III; the method is the grid
+ * index of Section IV (non-empty cells only, bounded search of the 3^d
+ * adjacent cells), the duplicate-search removal "unicomp" of Section V-B
+ * (Algorithm 2) and result batching of Section V-A.
+ *
+ * Pair membership is exact with respect to this definition, evaluated in
+ * IEEE binary64 with dimension order 0..d-1 and no fused multiply-add:
+ *     d2(i,j) = (...((x_i0-x_j0)^2 + (x_i1-x_j1)^2) + ...),  pair iff d2 <= fl(eps*eps).
+ * The FP32 option pre-tests in single precision and re-decides every pair in
+ * a proven error band around eps^2 with the FP64 formula, so the pair set is
+ * the same.
+ *
+ * Conventions for every entry point:
+ *  - Return value 0 (SJ_OK) on success or a negative SJ_E* code; the
+ *    thread-local message of the last failure is given by sj_last_error().
+ *    No C++ exception crosses this boundary.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). All
+ *    device work of a call is queued on it; calls return after the work they
+ *    queued has finished unless stated otherwise.
+ *  - Point arrays are row-major n x d binary64 (point i at pts[i*d .. i*d+d-1]),
+ *    owned by the caller and not retained after the call returns.
+ *  - Pair arrays are interleaved uint32 (i0, j0, i1, j1, ...), 8 bytes per pair.
+ *  - Ids are 0-based row indices of the input; n must be below 2^32 - 1.
+ *  - Not thread-safe on one index: calls on the same sj_index must not overlap.
+ *    Distinct indexes may be used from different threads and streams.
+ */
+#ifndef SJ_H
+#define SJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------- */
+#define SJ_OK         0
+#define SJ_EINVAL    -1   /* bad argument: d outside [1,8], eps <= 0 or not finite,
+                             NaN/Inf coordinate, NULL pointer, n too large */
+#define SJ_ENOMEM    -2   /* device or pinned-host allocation failed */
+#define SJ_EGRID     -3   /* the grid cannot be represented even after widening cells */
+#define SJ_EDEVICE   -4   /* a HIP runtime call failed */
+#define SJ_ESTATE    -5   /* call out of order (e.g. sj_join_fill before sj_join_count) */
+#define SJ_ECAPACITY -6   /* output buffer or batch capacity too small */
+
+/* ---- options ---------------------------------------------------------- */
+#define SJ_FP64      0    /* distances in binary64 */
+#define SJ_FP32_BAND 1    /* binary32 pre-test, binary64 re-decision inside the band */
+
+typedef struct sj_join_opts {
+    int32_t  unicomp;              /* 1: evaluate each unordered pair of adjacent
+                                      cells once (Section V-B); 0: all 3^d cells */
+    int32_t  precision;            /* SJ_FP64 or SJ_FP32_BAND */
+    uint64_t batch_capacity_pairs; /* max pairs per delivered batch; 0 = no limit */
+    uint32_t min_batches;          /* at least this many batches (Section V-A uses 3) */
+    int32_t  reserved;             /* must be 0 */
+} sj_join_opts;
+
+/* Fills *o with unicomp=1, precision=SJ_FP64, no capacity limit, 1 batch. */
+void sj_default_opts(sj_join_opts *o);
+
+/* ---- statistics --------------------------------------------------------- */
+typedef struct sj_stats {
+    uint64_t n;                 /* points */
+    uint32_t d;                 /* dimensions */
+    uint32_t key_bits;          /* bits of the linearised cell id */
+    uint64_t cells;             /* |G| = |B|, non-empty cells (Section IV-C) */
+    uint64_t grid_dims[8];      /* |g_j| per dimension */
+    double   eps;
+    double   cell_width;        /* w >= eps (slightly wider, see the header of the index code) */
+    uint32_t max_cell_points;   /* largest |C_h| */
+    uint32_t precision_used;    /* SJ_FP64 or SJ_FP32_BAND actually used in the last join */
+    uint64_t ranges;            /* candidate point ranges of the last join's cell search */
+    uint64_t evals;             /* distance evaluations of the last count pass */
+    uint64_t band_rechecks;     /* FP64 re-decisions in the last count pass (FP32 path) */
+    uint64_t pairs;             /* pairs of the last join */
+    uint64_t max_row_pairs;     /* longest result row of the last join */
+    uint32_t batches;           /* batches of the last join */
+    uint32_t unicomp_used;
+    double   ms_build;          /* wall time of sj_build_index */
+    double   ms_count;          /* wall time of the last sj_join_count */
+    double   ms_fill;           /* wall time of the last fill / batch loop */
+} sj_stats;
+
+/* ---- the index (Section IV-C: B, G, A, M plus the cell-ordered points) -- */
+typedef struct sj_index sj_index;
+
+/*
+ * Builds the grid index of Section IV-B/IV-C on the GPU: bounding box,
+ * cell ids, sort of points by cell (A), non-empty cell ids (B) with their
+ * point ranges (G), per-dimension occupancy masks (M) and a cell-ordered
+ * structure-of-arrays copy of the coordinates.
+ *   pts           n x d row-major binary64; device pointer if pts_on_device,
+ *                 else host memory (copied to the device).
+ *   eps           join distance, finite and > 0.
+ *   out           receives the index; release it with sj_destroy_index.
+ * n == 0 is valid (an empty index; every join returns 0 pairs).
+ */
+int sj_build_index(const double *pts, uint64_t n, uint32_t d, double eps,
+                   int pts_on_device, void *stream, sj_index **out);
+
+/* Releases the index and its device memory (NULL is ignored). */
+void sj_destroy_index(sj_index *idx);
+
+/*
+ * Count pass of the join (Algorithm 1's search and refine, Section V-B's
+ * unicomp when opts->unicomp): computes every result row's length and the
+ * row offsets, and returns the number of pairs P in *total_pairs. It must
+ * precede sj_join_fill on the same index; opts is remembered for the fill.
+ */
+int sj_join_count(sj_index *idx, const sj_join_opts *opts, void *stream,
+                  uint64_t *total_pairs);
+
+/*
+ * Fill pass: writes all P pairs, sorted by (i, j), to the device buffer
+ * `pairs_dev` (2 * P uint32, owned by the caller). capacity_pairs must be at
+ * least P (else SJ_ECAPACITY and nothing is written).
+ */
+int sj_join_fill(sj_index *idx, uint32_t *pairs_dev, uint64_t capacity_pairs,
+                 void *stream);
+
+/*
+ * Batched join (Section V-A). The result rows are split into at least
+ * opts->min_batches consecutive ranges of i, each holding at most
+ * opts->batch_capacity_pairs pairs; every batch is delivered, in order of i,
+ * to cb(user, pairs_dev, npairs, batch_id, row_begin, row_end) as a device
+ * buffer of npairs sorted pairs that stays valid until cb returns. The
+ * batches partition the result and their concatenation is sorted by (i, j).
+ * While cb runs, the next batch is already being computed. A non-zero return
+ * from cb stops the join and is returned. The library owns the buffers.
+ * SJ_ECAPACITY if one result row alone exceeds the batch capacity.
+ */
+typedef int (*sj_run_cb)(void *user, const uint32_t *pairs_dev, uint64_t npairs,
+                         uint32_t batch_id, uint64_t row_begin, uint64_t row_end);
+
+int sj_selfjoin_index(sj_index *idx, const sj_join_opts *opts, sj_run_cb cb,
+                      void *user, void *stream, uint64_t *total_pairs);
+
+/*
+ * Convenience: build, join and return all pairs sorted by (i, j) in a buffer
+ * allocated by the library -- device memory if out_on_device, else pinned
+ * host memory filled batch by batch while later batches compute. Release it
+ * with sj_free. *pairs_out is NULL when *npairs is 0.
+ */
+int sj_selfjoin(const double *pts, uint64_t n, uint32_t d, double eps,
+                const sj_join_opts *opts, int pts_on_device, int out_on_device,
+                void *stream, uint32_t **pairs_out, uint64_t *npairs);
+
+/* Frees a buffer returned by sj_selfjoin (device or pinned host; NULL ignored). */
+void sj_free(void *ptr);
+
+/* Statistics of the index and of its last join. */
+int sj_index_stats(const sj_index *idx, sj_stats *out);
+
+/*
+ * Copies an internal array of the index to host memory (tests, debugging).
+ * `bytes` must equal the array's size, which sj_index_export_size reports.
+ *   SJ_EXPORT_CELL_IDS    uint64[|G|]   B: linear ids of non-empty cells, ascending
+ *   SJ_EXPORT_CELL_START  uint32[|G|+1] G: cell h holds A[start[h] .. start[h+1]-1]
+ *   SJ_EXPORT_PERM        uint32[n]     A: point ids in cell order
+ *   SJ_EXPORT_MASKS       uint32[sum_j ceil(|g_j|/32)]  M_j occupancy bitmaps, dimension 0 first
+ *   SJ_EXPORT_RANGE_OFF   uint32[|G|+1] candidate ranges of cell h are rng[off[h] .. off[h+1]-1]
+ *   SJ_EXPORT_RANGES      uint32[2*R]   (start, end) point ranges in cell order
+ *   SJ_EXPORT_GRID        double[2*8+1] g_min[8], |g_j| as doubles [8], w
+ * The two range arrays describe the last join (or the last sj_index_search).
+ */
+#define SJ_EXPORT_CELL_IDS   1
+#define SJ_EXPORT_CELL_START 2
+#define SJ_EXPORT_PERM       3
+#define SJ_EXPORT_MASKS      4
+#define SJ_EXPORT_RANGE_OFF  5
+#define SJ_EXPORT_RANGES     6
+#define SJ_EXPORT_GRID       7
+int sj_index_export_size(const sj_index *idx, int what, uint64_t *bytes);
+int sj_index_export(const sj_index *idx, int what, void *host_dst, uint64_t bytes);
+
+/* Runs only the adjacent-cell search (Section IV-D, or the unicomp subset)
+ * so its ranges can be exported without a join. */
+int sj_index_search(sj_index *idx, int unicomp, void *stream);
+
+/*
+ * The FP32 pre-test thresholds (lo, hi) used by SJ_FP32_BAND for dimension
+ * d, distance eps and coordinate extent X = max |x - shift| over the data:
+ * an FP32 squared distance S < lo is accepted, S > hi rejected, anything
+ * else is re-decided in FP64. Returns SJ_EINVAL when the pre-test is not
+ * usable (eps too small relative to X); the join then falls back to FP64.
+ */
+int sj_band_thresholds(uint32_t d, double eps, double extent, float *lo, float *hi);
+
+/* Thread-local description of the last failure ("" if none). */
+const char *sj_last_error(void);
+
+/* Library version string. */
+const char *sj_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SJ_H */

@@ -16,7 +16,8 @@ assumes exact arithmetic:
 * g_j^min = min_j - w (the paper's one-cell padding); the number of cells
   |g_j| = floor((max_j - g_j^min) / w) + 2; a point's coordinate is
   c_j = clamp(floor((x_j - g_j^min) / w), 0, |g_j| - 1). If prod |g_j|
-  reaches 2^63 the width is doubled until it does not.
+  reaches 2^63, or some |g_j| reaches 2^31, the width is doubled until
+  neither holds (ids fit 63 bits, coordinates 31 bits).
 * Linear id (from the worked example of Section IV-D, where 30 = 2 + 7 * 4):
   dimension 0 varies fastest, id = c_0 + |g_0| * (c_1 + |g_1| * (c_2 + ...)).
 * B = ascending distinct ids of non-empty cells; G[h] = [start, end) range in
@@ -51,9 +52,11 @@ def grid_params(points, eps: float):
     w = cell_width(eps)
     while True:
         gmin = mins - w
-        dims = np.floor((maxs - gmin) / w).astype(np.int64) + 2
-        if math.prod(int(v) for v in dims) < 2 ** 63:
-            return gmin, w, dims
+        cells = np.floor((maxs - gmin) / w) + 2.0
+        if np.all(cells < 2.0 ** 31):
+            dims = cells.astype(np.int64)
+            if math.prod(int(v) for v in dims) < 2 ** 63:
+                return gmin, w, dims
         w = w * 2.0
 
 

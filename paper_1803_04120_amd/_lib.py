@@ -1,0 +1,153 @@
+"""ctypes binding of libsj.so (the C ABI declared in include/sj.h).
+
+Argument marshalling only: every step of the join runs in the HIP library.
+If the library has not been built the import of a function fails loudly;
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsj.so")
+
+SJ_OK = 0
+SJ_EINVAL = -1
+SJ_ENOMEM = -2
+SJ_EGRID = -3
+SJ_EDEVICE = -4
+SJ_ESTATE = -5
+SJ_ECAPACITY = -6
+
+SJ_FP64 = 0
+SJ_FP32_BAND = 1
+
+SJ_EXPORT_CELL_IDS = 1
+SJ_EXPORT_CELL_START = 2
+SJ_EXPORT_PERM = 3
+SJ_EXPORT_MASKS = 4
+SJ_EXPORT_RANGE_OFF = 5
+SJ_EXPORT_RANGES = 6
+SJ_EXPORT_GRID = 7
+
+_ERRNAMES = {SJ_EINVAL: "SJ_EINVAL", SJ_ENOMEM: "SJ_ENOMEM", SJ_EGRID: "SJ_EGRID",
+             SJ_EDEVICE: "SJ_EDEVICE", SJ_ESTATE: "SJ_ESTATE", SJ_ECAPACITY: "SJ_ECAPACITY"}
+
+
+class SjJoinOpts(ctypes.Structure):
+    _fields_ = [("unicomp", ctypes.c_int32),
+                ("precision", ctypes.c_int32),
+                ("batch_capacity_pairs", ctypes.c_uint64),
+                ("min_batches", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)]
+
+
+class SjStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64),
+                ("d", ctypes.c_uint32),
+                ("key_bits", ctypes.c_uint32),
+                ("cells", ctypes.c_uint64),
+                ("grid_dims", ctypes.c_uint64 * 8),
+                ("eps", ctypes.c_double),
+                ("cell_width", ctypes.c_double),
+                ("max_cell_points", ctypes.c_uint32),
+                ("precision_used", ctypes.c_uint32),
+                ("ranges", ctypes.c_uint64),
+                ("evals", ctypes.c_uint64),
+                ("band_rechecks", ctypes.c_uint64),
+                ("pairs", ctypes.c_uint64),
+                ("max_row_pairs", ctypes.c_uint64),
+                ("batches", ctypes.c_uint32),
+                ("unicomp_used", ctypes.c_uint32),
+                ("ms_build", ctypes.c_double),
+                ("ms_count", ctypes.c_double),
+                ("ms_fill", ctypes.c_double)]
+
+
+RUN_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                          ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64)
+
+_lib = None
+
+
+class SjError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load libsj.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32, i32, dbl = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                              ctypes.c_int32, ctypes.c_double)
+    pidx = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "sj_default_opts": (None, [ctypes.POINTER(SjJoinOpts)]),
+        "sj_build_index": (ctypes.c_int, [vp, u64, u32, dbl, ctypes.c_int, vp, pidx]),
+        "sj_destroy_index": (None, [vp]),
+        "sj_join_count": (ctypes.c_int, [vp, ctypes.POINTER(SjJoinOpts), vp,
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+        "sj_join_fill": (ctypes.c_int, [vp, vp, u64, vp]),
+        "sj_selfjoin_index": (ctypes.c_int, [vp, ctypes.POINTER(SjJoinOpts), RUN_CB, vp, vp,
+                                             ctypes.POINTER(ctypes.c_uint64)]),
+        "sj_selfjoin": (ctypes.c_int, [vp, u64, u32, dbl, ctypes.POINTER(SjJoinOpts), ctypes.c_int,
+                                       ctypes.c_int, vp, ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_uint64)]),
+        "sj_free": (None, [vp]),
+        "sj_index_stats": (ctypes.c_int, [vp, ctypes.POINTER(SjStats)]),
+        "sj_index_export_size": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]),
+        "sj_index_export": (ctypes.c_int, [vp, ctypes.c_int, vp, u64]),
+        "sj_index_search": (ctypes.c_int, [vp, ctypes.c_int, vp]),
+        "sj_band_thresholds": (ctypes.c_int, [u32, dbl, dbl, ctypes.POINTER(ctypes.c_float),
+                                              ctypes.POINTER(ctypes.c_float)]),
+        "sj_last_error": (ctypes.c_char_p, []),
+        "sj_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    del i32
+    _lib = L
+    return L
+
+
+def check(rc: int):
+    if rc != SJ_OK:
+        msg = load().sj_last_error().decode(errors="replace")
+        raise SjError(rc, msg)
+
+
+def opts(unicomp: bool = True, precision: str = "fp64", batch_capacity_pairs: int = 0,
+         min_batches: int = 1) -> SjJoinOpts:
+    o = SjJoinOpts()
+    load().sj_default_opts(ctypes.byref(o))
+    o.unicomp = 1 if unicomp else 0
+    if precision in ("fp64", SJ_FP64):
+        o.precision = SJ_FP64
+    elif precision in ("fp32_band", "fp32", SJ_FP32_BAND):
+        o.precision = SJ_FP32_BAND
+    else:
+        raise ValueError(f"unknown precision {precision!r}")
+    o.batch_capacity_pairs = int(batch_capacity_pairs or 0)
+    o.min_batches = int(max(1, min_batches))
+    o.reserved = 0
+    return o
+
+
+def stats_dict(st: SjStats) -> dict:
+    out = {}
+    for name, _ in SjStats._fields_:
+        v = getattr(st, name)
+        if name == "grid_dims":
+            v = [int(x) for x in v][: st.d]
+        out[name] = v
+    return out

@@ -1,0 +1,306 @@
+// Grid-index construction kernels (Section IV-B and IV-C).
+//
+//   bbox        min/max per dimension and a NaN/Inf flag (g_j^min, g_j^max)
+//   cell ids    c_j = clamp(floor((x_j - g_j^min) / w), 0, |g_j| - 1),
+//               id = c_0 + |g_0| (c_1 + |g_1| (c_2 + ...))  (dimension 0 fastest,
+//               as in the worked example of Section IV-D)
+//   cells       after the sort by id: head flags, inclusive scan -> cell of
+//               each point, B (distinct ids) and G (first point of each cell)
+//   coords/M    per-cell coordinates and the per-dimension occupancy
+//               bitmaps M_j
+//   gather      cell-ordered structure-of-arrays copy of the coordinates
+//               (X[j * n + r] = x[A[r]][j]) so the join reads each dimension
+//               of consecutive candidates from consecutive addresses, instead
+//               of the indirection D[A[k]] of Algorithm 1.
+#include <cmath>
+
+#include "sj_internal.h"
+#include "sj_device.h"
+
+namespace sj {
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *__restrict__ pts,
+                                                            uint64_t n, uint32_t d,
+                                                            double *__restrict__ part,
+                                                            uint32_t *__restrict__ bad) {
+    double mn[kMaxDim], mx[kMaxDim];
+#pragma unroll
+    for (int j = 0; j < kMaxDim; ++j) {
+        mn[j] = INFINITY;
+        mx[j] = -INFINITY;
+    }
+    uint32_t flag = 0;
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kThreads) {
+#pragma unroll
+        for (int j = 0; j < kMaxDim; ++j) {
+            if (j < static_cast<int>(d)) {
+                const double v = pts[i * d + j];
+                flag |= !isfinite(v);
+                mn[j] = fmin(mn[j], v);
+                mx[j] = fmax(mx[j], v);
+            }
+        }
+    }
+    __shared__ double smn[kThreads / 64][kMaxDim], smx[kThreads / 64][kMaxDim];
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < kMaxDim; ++j) {
+        double a = mn[j], b = mx[j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            a = fmin(a, __shfl_xor(a, off, 64));
+            b = fmax(b, __shfl_xor(b, off, 64));
+        }
+        if (lane_id() == 0) {
+            smn[wave][j] = a;
+            smx[wave][j] = b;
+        }
+    }
+    if (ballot(flag != 0) != 0 && lane_id() == 0) atomicOr(bad, 1u);
+    __syncthreads();
+    if (threadIdx.x < kMaxDim) {
+        const int j = threadIdx.x;
+        double a = smn[0][j], b = smx[0][j];
+        for (int w = 1; w < kThreads / 64; ++w) {
+            a = fmin(a, smn[w][j]);
+            b = fmax(b, smx[w][j]);
+        }
+        part[blockIdx.x * 2 * kMaxDim + j] = a;
+        part[blockIdx.x * 2 * kMaxDim + kMaxDim + j] = b;
+    }
+}
+
+__global__ void k_bbox_final(const double *__restrict__ part, uint32_t nblocks,
+                             double *__restrict__ out) {
+    const int j = threadIdx.x;
+    if (j >= kMaxDim) return;
+    double a = INFINITY, b = -INFINITY;
+    for (uint32_t k = 0; k < nblocks; ++k) {
+        a = fmin(a, part[k * 2 * kMaxDim + j]);
+        b = fmax(b, part[k * 2 * kMaxDim + kMaxDim + j]);
+    }
+    out[j] = a;
+    out[kMaxDim + j] = b;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_cell_keys(const double *__restrict__ pts, uint64_t n,
+                                                         GridParams g, K *__restrict__ keys,
+                                                         uint32_t *__restrict__ ids) {
+    const uint64_t i = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (i >= n) return;
+    uint64_t key = 0;
+    for (uint32_t j = 0; j < g.d; ++j) {
+        const double t = (pts[i * g.d + j] - g.gmin[j]) / g.w;
+        const double top = static_cast<double>(g.dims[j] - 1);
+        const double f = floor(t);
+        const uint64_t c = f <= 0.0 ? 0 : (f >= top ? g.dims[j] - 1 : static_cast<uint64_t>(f));
+        key += c * g.stride[j];
+    }
+    keys[i] = static_cast<K>(key);
+    ids[i] = static_cast<uint32_t>(i);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_head_flags(const K *__restrict__ k, uint64_t n,
+                                                          uint32_t *__restrict__ flag) {
+    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (r >= n) return;
+    flag[r] = (r == 0 || k[r] != k[r - 1]) ? 1u : 0u;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_cell_tables(const K *__restrict__ k, uint64_t n,
+                                                           uint32_t *__restrict__ cell_of,
+                                                           uint64_t *__restrict__ B,
+                                                           uint32_t *__restrict__ starts) {
+    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (r >= n) return;
+    const uint32_t h = cell_of[r] - 1u;  // inclusive scan of head flags
+    cell_of[r] = h;
+    if (r == 0 || k[r] != k[r - 1]) {
+        B[h] = static_cast<uint64_t>(k[r]);
+        starts[h] = static_cast<uint32_t>(r);
+    }
+    if (r == n - 1) starts[h + 1] = static_cast<uint32_t>(n);
+}
+
+// Per-cell coordinates decoded from the linear id; occupancy bitmaps M_j
+// (privatised in LDS when they fit); largest cell.
+constexpr uint32_t kMaskLdsWords = 8192;
+
+__global__ __launch_bounds__(kThreads) void k_cell_coords(const uint64_t *__restrict__ B,
+                                                           const uint32_t *__restrict__ starts,
+                                                           uint64_t ncells, GridParams g,
+                                                           uint32_t *__restrict__ coords,
+                                                           uint32_t *__restrict__ masks,
+                                                           const uint32_t *__restrict__ mask_off,
+                                                           uint32_t mask_words,
+                                                           uint32_t *__restrict__ max_pts) {
+    __shared__ uint32_t lmask[kMaskLdsWords];
+    const bool use_lds = masks != nullptr && mask_words <= kMaskLdsWords;
+    if (use_lds)
+        for (uint32_t i = threadIdx.x; i < mask_words; i += kThreads) lmask[i] = 0;
+    __syncthreads();
+    uint32_t mp = 0;
+    for (uint64_t h = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x; h < ncells;
+         h += static_cast<uint64_t>(gridDim.x) * kThreads) {
+        uint64_t id = B[h];
+        for (uint32_t j = 0; j < g.d; ++j) {
+            const uint32_t c = static_cast<uint32_t>(id % g.dims[j]);
+            id /= g.dims[j];
+            coords[h * g.d + j] = c;
+            if (!masks) continue;
+            const uint32_t w = mask_off[j] + (c >> 5);
+            const uint32_t bit = 1u << (c & 31u);
+            if (use_lds)
+                atomicOr(&lmask[w], bit);
+            else
+                atomicOr(&masks[w], bit);
+        }
+        const uint32_t sz = starts[h + 1] - starts[h];
+        mp = sz > mp ? sz : mp;
+    }
+    mp = wave_max(mp);
+    if (lane_id() == 0) atomicMax(max_pts, mp);
+    __syncthreads();
+    if (use_lds)
+        for (uint32_t i = threadIdx.x; i < mask_words; i += kThreads)
+            if (lmask[i]) atomicOr(&masks[i], lmask[i]);
+}
+
+__global__ void k_zero_u32(uint32_t *p, uint64_t n) {
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_gather_soa(const double *__restrict__ pts,
+                                                          const uint32_t *__restrict__ perm,
+                                                          uint64_t n, uint32_t d,
+                                                          double *__restrict__ X) {
+    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (r >= n) return;
+    const uint64_t i = perm[r];
+    for (uint32_t j = 0; j < d; ++j) X[j * n + r] = pts[i * d + j];
+}
+
+__global__ __launch_bounds__(kThreads) void k_make_f32(const double *__restrict__ X, uint64_t n,
+                                                        uint32_t d, GridParams shift,
+                                                        float *__restrict__ Y) {
+    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (r >= n) return;
+    for (uint32_t j = 0; j < d; ++j)
+        Y[j * n + r] = static_cast<float>(X[j * n + r] - shift.gmin[j]);
+}
+
+template <typename T>
+__global__ void k_fill(T *__restrict__ p, uint64_t n, T v) {
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+inline unsigned blocks_for(uint64_t n) {
+    return static_cast<unsigned>((n + kThreads - 1) / kThreads);
+}
+
+}  // namespace
+
+void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
+    if (!n) return;
+    const unsigned nb = static_cast<unsigned>(std::min<uint64_t>(4096, (n + kThreads - 1) / kThreads));
+    k_fill<uint32_t><<<nb, kThreads, 0, s>>>(p, n, v);
+    SJ_LAUNCH_CHECK();
+}
+
+void launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
+    if (!n) return;
+    const unsigned nb = static_cast<unsigned>(std::min<uint64_t>(4096, (n + kThreads - 1) / kThreads));
+    k_fill<uint64_t><<<nb, kThreads, 0, s>>>(p, n, v);
+    SJ_LAUNCH_CHECK();
+}
+
+// Y[j][r] = fl32(X[j][r] - shift_j); the shift travels in GridParams::gmin.
+void launch_make_f32(const double *X, uint64_t n, uint32_t d, const double *shift, float *Y,
+                     hipStream_t s) {
+    GridParams g{};
+    for (uint32_t j = 0; j < d && j < static_cast<uint32_t>(kMaxDim); ++j) g.gmin[j] = shift[j];
+    k_make_f32<<<blocks_for(n), kThreads, 0, s>>>(X, n, d, g, Y);
+    SJ_LAUNCH_CHECK();
+}
+
+void launch_bbox(const double *pts, uint64_t n, uint32_t d, double *bbox_out, uint32_t *bad,
+                 hipStream_t s) {
+    const uint32_t nb = static_cast<uint32_t>(std::min<uint64_t>(1024, (n + kThreads - 1) / kThreads));
+    DevBuf<double> part(static_cast<size_t>(nb) * 2 * kMaxDim);
+    k_zero_u32<<<1, 64, 0, s>>>(bad, 1);
+    SJ_LAUNCH_CHECK();
+    k_bbox_partial<<<nb, kThreads, 0, s>>>(pts, n, d, part.ptr, bad);
+    SJ_LAUNCH_CHECK();
+    k_bbox_final<<<1, 64, 0, s>>>(part.ptr, nb, bbox_out);
+    SJ_LAUNCH_CHECK();
+}
+
+void launch_cell_keys_u64(const double *pts, uint64_t n, const GridParams &g, uint64_t *keys,
+                          uint32_t *ids, hipStream_t s) {
+    k_cell_keys<uint64_t><<<blocks_for(n), kThreads, 0, s>>>(pts, n, g, keys, ids);
+    SJ_LAUNCH_CHECK();
+}
+
+void launch_cell_keys_u32(const double *pts, uint64_t n, const GridParams &g, uint32_t *keys,
+                          uint32_t *ids, hipStream_t s) {
+    k_cell_keys<uint32_t><<<blocks_for(n), kThreads, 0, s>>>(pts, n, g, keys, ids);
+    SJ_LAUNCH_CHECK();
+}
+
+template <typename K>
+uint64_t build_cells(const K *sorted_keys, uint64_t n, uint32_t *cell_of, uint64_t *B,
+                     uint32_t *starts, hipStream_t s) {
+    k_head_flags<K><<<blocks_for(n), kThreads, 0, s>>>(sorted_keys, n, cell_of);
+    SJ_LAUNCH_CHECK();
+    scan_inclusive_u32(cell_of, n, s);
+    uint32_t ncells = 0;
+    SJ_HIP(hipMemcpyAsync(&ncells, cell_of + (n - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    k_cell_tables<K><<<blocks_for(n), kThreads, 0, s>>>(sorted_keys, n, cell_of, B, starts);
+    SJ_LAUNCH_CHECK();
+    SJ_HIP(hipStreamSynchronize(s));
+    return ncells;
+}
+
+template uint64_t build_cells<uint64_t>(const uint64_t *, uint64_t, uint32_t *, uint64_t *,
+                                        uint32_t *, hipStream_t);
+template uint64_t build_cells<uint32_t>(const uint32_t *, uint64_t, uint32_t *, uint64_t *,
+                                        uint32_t *, hipStream_t);
+
+uint32_t launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_t ncells,
+                                  const GridParams &g, uint32_t *coords, uint32_t *masks,
+                                  const uint32_t *mask_off, uint32_t mask_words, hipStream_t s) {
+    DevBuf<uint32_t> mp(1);
+    if (masks) {
+        k_zero_u32<<<64, 256, 0, s>>>(masks, mask_words);
+        SJ_LAUNCH_CHECK();
+    }
+    k_zero_u32<<<1, 64, 0, s>>>(mp.ptr, 1);
+    SJ_LAUNCH_CHECK();
+    const unsigned nb = static_cast<unsigned>(std::min<uint64_t>(2048, (ncells + kThreads - 1) / kThreads));
+    k_cell_coords<<<nb, kThreads, 0, s>>>(B, starts, ncells, g, coords, masks, mask_off, mask_words,
+                                         mp.ptr);
+    SJ_LAUNCH_CHECK();
+    uint32_t host = 0;
+    SJ_HIP(hipMemcpyAsync(&host, mp.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    return host;
+}
+
+void launch_gather_soa(const double *pts, const uint32_t *perm, uint64_t n, uint32_t d, double *X,
+                       hipStream_t s) {
+    k_gather_soa<<<blocks_for(n), kThreads, 0, s>>>(pts, perm, n, d, X);
+    SJ_LAUNCH_CHECK();
+}
+
+}  // namespace sj

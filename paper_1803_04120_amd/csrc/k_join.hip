@@ -1,0 +1,431 @@
+// Adjacent-cell search and distance refine (Section IV-D, Algorithm 1) with
+// the unicomp cell subset (Section V-B, Algorithm 2).
+//
+// Search (one thread per non-empty query cell). Instead of probing the 3^d
+// cells one by one, the cells adjacent to C are grouped into "rows": cells
+// that agree in dimensions 1..d-1 and span [c_0 - 1, c_0 + 1] in dimension
+// 0. Cells of a row have consecutive linear ids, so one binary search in B
+// finds the first occupied cell of the row, and because points are stored
+// in cell order, all occupied cells of the row form ONE contiguous point
+// range. A full search therefore yields at most 3^(d-1) ranges per cell;
+// rows whose fixed coordinates are not in the occupancy masks M_j are
+// skipped without a search. The unicomp subset keeps, for every dimension k
+// with c_k odd, the cells that differ from C in dimension k, range freely in
+// dimensions below k and equal C above k; for k = 0 these are the two single
+// cells c_0 - 1 and c_0 + 1. The query's own cell is then evaluated as the
+// triangle q >= p.
+//
+// Refine (one thread per query point, cell order). Each lane keeps its
+// point in registers and scans its cell's ranges; candidate coordinates are
+// read from the structure-of-arrays copy, so lanes of the same cell read the
+// same addresses. Pair test in binary64, dimension order 0..d-1, no fused
+// multiply-add: d2 <= fl(eps^2). The FP32 variant tests the shifted single
+// precision copy first and re-decides only in the proven band [lo, hi].
+//
+// Emission. The count pass records each row's length: the query's own
+// hits in a register, and under unicomp the mirrored pair (q, p) as an
+// atomic increment of q's incoming count. The fill pass writes each row in
+// place: own hits at [row start, +own), mirrored hits after them at a slot
+// taken with an atomic on q's cursor.
+#include "sj_internal.h"
+#include "sj_device.h"
+
+namespace sj {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint32_t lower_bound_u64(const uint64_t *__restrict__ B, uint32_t n,
+                                                    uint64_t key) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (B[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool occupied(const SearchArgs &a, uint32_t j, uint32_t c) {
+    if (!a.masks) return true;
+    return (a.masks[a.mask_off[j] + (c >> 5)] >> (c & 31u)) & 1u;
+}
+
+// Emits the ranges of one row: dimension-0 span [lo0, hi0] with the other
+// coordinates given by `base_id` (their contribution to the linear id).
+template <bool kWrite>
+__device__ __forceinline__ void row_range(const SearchArgs &a, uint64_t base_id, uint32_t lo0,
+                                          uint32_t hi0, uint32_t &count, uint2 *out) {
+    const uint64_t klo = base_id + lo0;
+    const uint64_t khi = base_id + hi0;
+    uint32_t h = lower_bound_u64(a.B, a.ncells, klo);
+    if (h >= a.ncells || a.B[h] > khi) return;
+    const uint32_t first = h;
+    while (h + 1 < a.ncells && a.B[h + 1] <= khi) ++h;
+    if (kWrite) out[count] = make_uint2(a.starts[first], a.starts[h + 1]);
+    ++count;
+}
+
+template <bool kWrite>
+__device__ uint32_t search_cell(const SearchArgs &a, uint32_t cell, bool unicomp, uint2 *out) {
+    const uint32_t d = a.d;
+    uint32_t c[kMaxDim];
+    for (uint32_t j = 0; j < d; ++j) c[j] = a.coords[static_cast<uint64_t>(cell) * d + j];
+    uint32_t lo[kMaxDim], hi[kMaxDim];
+    for (uint32_t j = 0; j < d; ++j) {
+        lo[j] = c[j] > 0 ? c[j] - 1 : 0;
+        hi[j] = c[j] + 1 < a.dims[j] ? c[j] + 1 : static_cast<uint32_t>(a.dims[j] - 1);
+    }
+    uint32_t count = 0;
+    if (!unicomp) {
+        // every combination of dimensions 1..d-1 within [lo, hi]
+        uint32_t off[kMaxDim];
+        for (uint32_t j = 1; j < d; ++j) off[j] = lo[j];
+        while (true) {
+            bool ok = true;
+            uint64_t base = 0;
+            for (uint32_t j = 1; j < d; ++j) {
+                ok = ok && occupied(a, j, off[j]);
+                base += off[j] * a.stride[j];
+            }
+            if (ok) row_range<kWrite>(a, base, lo[0], hi[0], count, out);
+            uint32_t j = 1;
+            while (j < d) {
+                if (off[j] < hi[j]) {
+                    ++off[j];
+                    break;
+                }
+                off[j] = lo[j];
+                ++j;
+            }
+            if (j >= d) break;
+        }
+        return count;
+    }
+    // unicomp block k = 0: the two cells c_0 -/+ 1 of the own row
+    uint64_t own_rest = 0;
+    for (uint32_t j = 1; j < d; ++j) own_rest += c[j] * a.stride[j];
+    if (c[0] & 1u) {
+        if (c[0] > 0 && occupied(a, 0, c[0] - 1))
+            row_range<kWrite>(a, own_rest, c[0] - 1, c[0] - 1, count, out);
+        if (c[0] + 1 < a.dims[0] && occupied(a, 0, c[0] + 1))
+            row_range<kWrite>(a, own_rest, c[0] + 1, c[0] + 1, count, out);
+    }
+    // unicomp blocks k >= 1
+    for (uint32_t k = 1; k < d; ++k) {
+        if (!(c[k] & 1u)) continue;
+        // dims 1..k-1 free in [lo, hi]; dim k in {c_k - 1, c_k + 1}; dims > k fixed
+        uint64_t upper = 0;
+        for (uint32_t j = k + 1; j < d; ++j) upper += c[j] * a.stride[j];
+        for (int side = -1; side <= 1; side += 2) {
+            if (side < 0 && c[k] == 0) continue;
+            if (side > 0 && c[k] + 1 >= a.dims[k]) continue;
+            const uint32_t ck = c[k] + side;
+            if (!occupied(a, k, ck)) continue;
+            const uint64_t fixed = upper + ck * a.stride[k];
+            uint32_t off[kMaxDim];
+            for (uint32_t j = 1; j < k; ++j) off[j] = lo[j];
+            while (true) {
+                bool ok = true;
+                uint64_t base = fixed;
+                for (uint32_t j = 1; j < k; ++j) {
+                    ok = ok && occupied(a, j, off[j]);
+                    base += off[j] * a.stride[j];
+                }
+                if (ok) row_range<kWrite>(a, base, lo[0], hi[0], count, out);
+                uint32_t j = 1;
+                while (j < k) {
+                    if (off[j] < hi[j]) {
+                        ++off[j];
+                        break;
+                    }
+                    off[j] = lo[j];
+                    ++j;
+                }
+                if (j >= k) break;
+            }
+        }
+    }
+    return count;
+}
+
+__global__ __launch_bounds__(kThreads) void k_search_count(SearchArgs a, int unicomp,
+                                                            uint32_t *__restrict__ cnt) {
+    const uint32_t h = blockIdx.x * kThreads + threadIdx.x;
+    if (h >= a.ncells) return;
+    cnt[h] = search_cell<false>(a, h, unicomp != 0, nullptr);
+}
+
+__global__ __launch_bounds__(kThreads) void k_search_fill(SearchArgs a, int unicomp,
+                                                           const uint64_t *__restrict__ roff,
+                                                           uint2 *__restrict__ rng) {
+    const uint32_t h = blockIdx.x * kThreads + threadIdx.x;
+    if (h >= a.ncells) return;
+    search_cell<true>(a, h, unicomp != 0, rng + roff[h]);
+}
+
+// ------------------------------------------------------------------ join
+template <int D, bool kBand>
+struct Point {
+    double x[D];
+    float y[kBand ? D : 1];
+};
+
+template <int D, bool kBand>
+__device__ __forceinline__ bool pair_within(const JoinArgs &a, const Point<D, kBand> &p,
+                                            uint32_t q, uint32_t &rechecks) {
+    if (kBand) {
+        float s = 0.0f;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const float t = __fsub_rn(p.y[j], a.Y[static_cast<size_t>(j) * a.n + q]);
+            s = __fadd_rn(s, __fmul_rn(t, t));
+        }
+        if (s < a.lo) return true;
+        if (s > a.hi) return false;
+        ++rechecks;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const double t = __dsub_rn(p.x[j], a.X[static_cast<size_t>(j) * a.n + q]);
+        acc = __dadd_rn(acc, __dmul_rn(t, t));
+    }
+    return acc <= a.eps2;
+}
+
+// Lanes past the end of the query list stay in the kernel (inactive) so the
+// wave-wide counter reduction at the end sees every lane.
+template <int D, bool kUni, int kMode, bool kBand>
+__global__ __launch_bounds__(kThreads) void k_join_guarded(JoinArgs a) {
+    const uint32_t t = blockIdx.x * kThreads + threadIdx.x;
+    const bool active = t < a.nq;
+    uint32_t own = 0, evals = 0, rechecks = 0;
+    if (active) {
+        const uint32_t p = a.qlist ? a.qlist[t] : t;
+        const uint32_t h = a.cell_of[p];
+        Point<D, kBand> pt;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            pt.x[j] = a.X[static_cast<size_t>(j) * a.n + p];
+            if (kBand) pt.y[j] = a.Y[static_cast<size_t>(j) * a.n + p];
+        }
+        uint64_t my_row = 0;
+        uint32_t perm_p = 0;
+        if (kMode == kFill) {
+            my_row = a.offc[p] - a.out_base;
+            perm_p = a.perm[p];
+        }
+        // Fill positions come from the count pass; a write at or past the
+        // buffer end (only possible if the two passes disagreed) is dropped
+        // and flagged instead of being made.
+        auto emit = [&](uint32_t q, bool mirror) {
+            if (kMode == kCount) {
+                ++own;
+                if (mirror) atomicAdd(&a.in_cnt[q], 1u);
+            } else {
+                const uint64_t at = my_row + own;
+                if (at < a.out_cap)
+                    a.out_j[at] = a.perm[q];
+                else
+                    atomicOr(a.overflow, 1u);
+                ++own;
+                if (mirror) {
+                    const uint32_t slot = atomicAdd(&a.cur[q], 1u);
+                    const uint64_t at2 = a.offc[q] - a.out_base + a.own_cnt[q] + slot;
+                    if (at2 < a.out_cap)
+                        a.out_j[at2] = perm_p;
+                    else
+                        atomicOr(a.overflow, 1u);
+                }
+            }
+        };
+        if (kUni) {
+            const uint32_t end = a.starts[h + 1];
+            for (uint32_t q = p; q < end; ++q) {
+                ++evals;
+                if (pair_within<D, kBand>(a, pt, q, rechecks)) emit(q, q != p);
+            }
+        }
+        const uint64_t r0 = a.roff[h], r1 = a.roff[h + 1];
+        for (uint64_t e = r0; e < r1; ++e) {
+            const uint2 r = a.rng[e];
+            for (uint32_t q = r.x; q < r.y; ++q) {
+                ++evals;
+                if (pair_within<D, kBand>(a, pt, q, rechecks)) emit(q, kUni);
+            }
+        }
+        if (kMode == kCount) a.own_cnt[p] = own;
+    }
+    if (kMode == kCount) {
+        const unsigned long long ev = wave_sum<unsigned long long>(evals);
+        const unsigned long long rc = wave_sum<unsigned long long>(rechecks);
+        if (lane_id() == 0) {
+            atomicAdd(a.evals, ev);
+            if (kBand) atomicAdd(a.band_rechecks, rc);
+        }
+    }
+}
+
+template <int D>
+void launch_join_d(const JoinArgs &a, int unicomp, int mode, int band, hipStream_t s) {
+    const unsigned nb = (a.nq + kThreads - 1) / kThreads;
+    if (nb == 0) return;
+#define SJ_JOIN_CASE(U, M, BD)                                                   \
+    if (unicomp == U && mode == M && band == BD) {                               \
+        k_join_guarded<D, U, M, BD><<<nb, kThreads, 0, s>>>(a);                  \
+        SJ_LAUNCH_CHECK();                                                       \
+        return;                                                                  \
+    }
+    SJ_JOIN_CASE(0, kCount, 0)
+    SJ_JOIN_CASE(1, kCount, 0)
+    SJ_JOIN_CASE(0, kFill, 0)
+    SJ_JOIN_CASE(1, kFill, 0)
+    SJ_JOIN_CASE(0, kCount, 1)
+    SJ_JOIN_CASE(1, kCount, 1)
+    SJ_JOIN_CASE(0, kFill, 1)
+    SJ_JOIN_CASE(1, kFill, 1)
+#undef SJ_JOIN_CASE
+    throw Error(SJ_EINVAL, "join: bad mode");
+}
+
+// ------------------------------------------------------------ row plans
+__global__ __launch_bounds__(kThreads) void k_row_lengths(const uint32_t *__restrict__ own,
+                                                           const uint32_t *__restrict__ inc,
+                                                           const uint32_t *__restrict__ perm,
+                                                           uint64_t n, uint32_t *__restrict__ len) {
+    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (r >= n) return;
+    len[perm[r]] = own[r] + (inc ? inc[r] : 0u);
+}
+
+__global__ __launch_bounds__(kThreads) void k_gather_offsets(const uint64_t *__restrict__ off,
+                                                              const uint32_t *__restrict__ perm,
+                                                              uint64_t n, uint64_t *__restrict__ offc,
+                                                              const uint32_t *__restrict__ len,
+                                                              uint32_t *__restrict__ max_len) {
+    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    uint32_t m = 0;
+    if (r < n) {
+        offc[r] = off[perm[r]];
+        m = len[r];
+    }
+    m = wave_max(m);
+    if (lane_id() == 0 && m) atomicMax(max_len, m);
+}
+
+__global__ __launch_bounds__(kThreads) void k_batch_flags(const uint32_t *__restrict__ perm,
+                                                           uint64_t n, uint64_t i0, uint64_t i1,
+                                                           uint32_t *__restrict__ flag) {
+    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (r >= n) return;
+    const uint64_t i = perm[r];
+    flag[r] = (i >= i0 && i < i1) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_batch_compact(const uint32_t *__restrict__ perm,
+                                                             uint64_t n, uint64_t i0, uint64_t i1,
+                                                             const uint32_t *__restrict__ pos,
+                                                             uint32_t *__restrict__ qlist) {
+    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (r >= n) return;
+    const uint64_t i = perm[r];
+    if (i >= i0 && i < i1) qlist[pos[r]] = static_cast<uint32_t>(r);
+}
+
+__global__ void k_batch_bounds(const uint64_t *__restrict__ off, uint64_t n, uint64_t total,
+                               uint32_t nb, uint64_t *__restrict__ rows) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nb) return;
+    if (b == nb) {
+        rows[b] = n;
+        return;
+    }
+    const unsigned __int128 t128 = static_cast<unsigned __int128>(b) * total / nb;
+    const uint64_t target = static_cast<uint64_t>(t128);
+    uint64_t lo = 0, hi = n;  // first i in [0, n] with off[i] >= target
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (off[mid] < target)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    rows[b] = lo;
+}
+
+inline unsigned blocks_for(uint64_t n) {
+    return static_cast<unsigned>((n + kThreads - 1) / kThreads);
+}
+
+}  // namespace
+
+void launch_batch_bounds(const uint64_t *off, uint64_t n, uint64_t total, uint32_t nb,
+                         uint64_t *rows, hipStream_t s) {
+    k_batch_bounds<<<(nb + 1 + 255) / 256, 256, 0, s>>>(off, n, total, nb, rows);
+    SJ_LAUNCH_CHECK();
+}
+
+uint64_t build_ranges(const SearchArgs &a, int unicomp, uint64_t *roff, uint32_t **rng_out,
+                      size_t *rng_cap, hipStream_t s) {
+    if (a.ncells == 0) return 0;
+    DevBuf<uint32_t> cnt(a.ncells);
+    k_search_count<<<blocks_for(a.ncells), kThreads, 0, s>>>(a, unicomp, cnt.ptr);
+    SJ_LAUNCH_CHECK();
+    scan_exclusive_u32_to_u64(cnt.ptr, roff, a.ncells, s);
+    uint64_t total = 0;
+    SJ_HIP(hipMemcpyAsync(&total, roff + a.ncells, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    if (total > *rng_cap) {
+        if (*rng_out) dev_free(*rng_out);
+        const size_t cap = total + total / 8 + 64;
+        *rng_out = static_cast<uint32_t *>(dev_alloc(cap * 2 * sizeof(uint32_t)));
+        *rng_cap = cap;
+    }
+    k_search_fill<<<blocks_for(a.ncells), kThreads, 0, s>>>(a, unicomp, roff,
+                                                            reinterpret_cast<uint2 *>(*rng_out));
+    SJ_LAUNCH_CHECK();
+    SJ_HIP(hipStreamSynchronize(s));
+    return total;
+}
+
+void launch_join(const JoinArgs &a, uint32_t d, int unicomp, int mode, int band, hipStream_t s) {
+    switch (d) {
+        case 1: launch_join_d<1>(a, unicomp, mode, band, s); break;
+        case 2: launch_join_d<2>(a, unicomp, mode, band, s); break;
+        case 3: launch_join_d<3>(a, unicomp, mode, band, s); break;
+        case 4: launch_join_d<4>(a, unicomp, mode, band, s); break;
+        case 5: launch_join_d<5>(a, unicomp, mode, band, s); break;
+        case 6: launch_join_d<6>(a, unicomp, mode, band, s); break;
+        case 7: launch_join_d<7>(a, unicomp, mode, band, s); break;
+        case 8: launch_join_d<8>(a, unicomp, mode, band, s); break;
+        default: throw Error(SJ_EINVAL, "join: d out of range");
+    }
+}
+
+void launch_row_lengths(const uint32_t *own_cnt, const uint32_t *in_cnt, const uint32_t *perm,
+                        uint64_t n, uint32_t *len_orig, hipStream_t s) {
+    k_row_lengths<<<blocks_for(n), kThreads, 0, s>>>(own_cnt, in_cnt, perm, n, len_orig);
+    SJ_LAUNCH_CHECK();
+}
+
+void launch_gather_offsets(const uint64_t *off_orig, const uint32_t *perm, uint64_t n,
+                           uint64_t *offc, uint32_t *max_len, const uint32_t *len_orig,
+                           hipStream_t s) {
+    k_gather_offsets<<<blocks_for(n), kThreads, 0, s>>>(off_orig, perm, n, offc, len_orig, max_len);
+    SJ_LAUNCH_CHECK();
+}
+
+uint32_t build_query_list(const uint32_t *perm, uint64_t n, uint64_t i0, uint64_t i1,
+                          uint32_t *flags_scratch, uint32_t *qlist, hipStream_t s) {
+    k_batch_flags<<<blocks_for(n), kThreads, 0, s>>>(perm, n, i0, i1, flags_scratch);
+    SJ_LAUNCH_CHECK();
+    scan_exclusive_u32(flags_scratch, flags_scratch, n, s);
+    k_batch_compact<<<blocks_for(n), kThreads, 0, s>>>(perm, n, i0, i1, flags_scratch, qlist);
+    SJ_LAUNCH_CHECK();
+    return static_cast<uint32_t>(i1 - i0);
+}
+
+}  // namespace sj

@@ -1,0 +1,183 @@
+// Stable LSD radix sort of (cell id, point id) pairs: builds the point map A
+// of Section IV-C (points ordered by linearised cell id, ties by point id).
+//
+// One pass per 8-bit digit of the significant key bits:
+//   upsweep   - per-tile digit histogram (LDS atomics), digit-major table;
+//   scan      - exclusive scan of the table (digit-major, tile-minor) gives
+//               each (digit, tile) its first output slot;
+//   downsweep - per tile, a stable rank of every key within its digit using
+//               wave64 ballots (8 ballots give the lanes with an equal
+//               digit), per-wave running counts in LDS, and a block prefix;
+//               keys are staged in LDS in digit order so the global writes of
+//               one digit run are contiguous.
+#include "sj_internal.h"
+#include "sj_device.h"
+
+namespace sj {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kItems = 8;                 // per lane
+constexpr int kTile = kThreads * kItems;  // 2048 keys per workgroup
+constexpr int kRadix = 256;
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_upsweep(const K *__restrict__ keys, size_t n,
+                                                       int shift, uint32_t *__restrict__ hist,
+                                                       uint32_t ntiles) {
+    __shared__ uint32_t h[kWaves][kRadix];
+    const int wave = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < kWaves * kRadix; i += kThreads) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const size_t base = static_cast<size_t>(blockIdx.x) * kTile;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const size_t i = base + static_cast<size_t>(k) * kThreads + threadIdx.x;
+        if (i < n) {
+            const uint32_t dgt = static_cast<uint32_t>(keys[i] >> shift) & (kRadix - 1);
+            atomicAdd(&h[wave][dgt], 1u);
+        }
+    }
+    __syncthreads();
+    const int t = threadIdx.x;  // kThreads == kRadix
+    uint32_t s = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += h[w][t];
+    hist[static_cast<size_t>(t) * ntiles + blockIdx.x] = s;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_downsweep(const K *__restrict__ kin,
+                                                         const uint32_t *__restrict__ vin,
+                                                         K *__restrict__ kout,
+                                                         uint32_t *__restrict__ vout, size_t n,
+                                                         int shift,
+                                                         const uint32_t *__restrict__ hist_scan,
+                                                         uint32_t ntiles) {
+    __shared__ uint32_t wcnt[kWaves][kRadix];
+    __shared__ uint32_t doff[kRadix];
+    __shared__ uint32_t gbase[kRadix];
+    __shared__ uint32_t lds_scan[kWaves];
+    __shared__ K skey[kTile];
+    __shared__ uint32_t sval[kTile];
+
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    for (int i = threadIdx.x; i < kWaves * kRadix; i += kThreads) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+
+    const size_t base = static_cast<size_t>(blockIdx.x) * kTile;
+    const uint32_t count =
+        static_cast<uint32_t>((n - base) < static_cast<size_t>(kTile) ? (n - base) : kTile);
+
+    K key[kItems];
+    uint32_t val[kItems];
+    uint32_t rank[kItems];
+    uint32_t dig[kItems];
+    volatile uint32_t *my_cnt = wcnt[wave];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const uint32_t local = static_cast<uint32_t>(wave * (kItems * 64) + k * 64 + lane);
+        const bool valid = local < count;
+        key[k] = valid ? kin[base + local] : K(0);
+        val[k] = valid ? vin[base + local] : 0u;
+        const uint32_t dg = static_cast<uint32_t>(key[k] >> shift) & (kRadix - 1);
+        dig[k] = dg;
+        uint64_t m = ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dg >> b) & 1u;
+            const uint64_t bb = ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const uint32_t below = mbcnt(m);
+        const uint32_t same = static_cast<uint32_t>(__popcll(m));
+        uint32_t pre = 0;
+        if (valid) pre = my_cnt[dg];
+        rank[k] = pre + below;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && below == 0) my_cnt[dg] = pre + same;
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+
+    // wave prefixes per digit, block digit offsets, global bases
+    {
+        const int t = threadIdx.x;
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = wcnt[w][t];
+            wcnt[w][t] = run;
+            run += c;
+        }
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan<uint32_t, kThreads>(run, &tot, lds_scan);
+        doff[t] = ex;
+        gbase[t] = hist_scan[static_cast<size_t>(t) * ntiles + blockIdx.x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const uint32_t local = static_cast<uint32_t>(wave * (kItems * 64) + k * 64 + lane);
+        if (local < count) {
+            const uint32_t pos = doff[dig[k]] + wcnt[wave][dig[k]] + rank[k];
+            skey[pos] = key[k];
+            sval[pos] = val[k];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const uint32_t i = static_cast<uint32_t>(k * kThreads + threadIdx.x);
+        if (i < count) {
+            const K kk = skey[i];
+            const uint32_t dg = static_cast<uint32_t>(kk >> shift) & (kRadix - 1);
+            const size_t o = static_cast<size_t>(gbase[dg]) + (i - doff[dg]);
+            kout[o] = kk;
+            vout[o] = sval[i];
+        }
+    }
+}
+
+template <typename K>
+void radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, size_t n,
+                     int bits, hipStream_t s) {
+    if (n <= 1 || bits <= 0) return;
+    if (n >= 0xffffffffULL) throw Error(SJ_EINVAL, "radix sort: too many keys");
+    const uint32_t ntiles = static_cast<uint32_t>((n + kTile - 1) / kTile);
+    DevBuf<uint32_t> hist(static_cast<size_t>(kRadix) * ntiles);
+    K *src_k = keys, *dst_k = keys_alt;
+    uint32_t *src_v = vals, *dst_v = vals_alt;
+    int passes = 0;
+    for (int shift = 0; shift < bits; shift += 8) {
+        k_upsweep<K><<<ntiles, kThreads, 0, s>>>(src_k, n, shift, hist.ptr, ntiles);
+        SJ_LAUNCH_CHECK();
+        scan_exclusive_u32(hist.ptr, hist.ptr, hist.count, s);
+        k_downsweep<K><<<ntiles, kThreads, 0, s>>>(src_k, src_v, dst_k, dst_v, n, shift, hist.ptr,
+                                                   ntiles);
+        SJ_LAUNCH_CHECK();
+        std::swap(src_k, dst_k);
+        std::swap(src_v, dst_v);
+        ++passes;
+    }
+    if (passes & 1) {
+        SJ_HIP(hipMemcpyAsync(keys, src_k, n * sizeof(K), hipMemcpyDeviceToDevice, s));
+        SJ_HIP(hipMemcpyAsync(vals, src_v, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    }
+}
+
+}  // namespace
+
+void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
+                    size_t n, int bits, hipStream_t s) {
+    radix_sort_impl<uint64_t>(keys, vals, keys_alt, vals_alt, n, bits, s);
+}
+
+void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                    size_t n, int bits, hipStream_t s) {
+    radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, bits, s);
+}
+
+}  // namespace sj

@@ -1,0 +1,820 @@
+// C ABI of libsj: the index object, the count/fill join, batching and the
+// convenience entry point. Every entry point runs inside guarded(), which
+// turns internal errors into return codes, synchronises the call's stream
+// and only then hands the call's temporaries back to the memory pool.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sj.h"
+#include "sj_internal.h"
+
+using sj::DevBuf;
+using sj::Error;
+
+namespace {
+
+thread_local std::string t_error;
+
+void set_error(const std::string &m) { t_error = m; }
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename F>
+int guarded(hipStream_t s, F &&f) {
+    sj::pool_enter();
+    int rc = SJ_OK;
+    try {
+        f();
+    } catch (const Error &e) {
+        set_error(e.what());
+        rc = e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        rc = SJ_ENOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        rc = SJ_EDEVICE;
+    } catch (...) {
+        set_error("unknown error");
+        rc = SJ_EDEVICE;
+    }
+    const hipError_t se = hipStreamSynchronize(s);
+    if (se != hipSuccess && rc == SJ_OK) {
+        set_error(std::string("stream synchronisation failed: ") + hipGetErrorString(se));
+        rc = SJ_EDEVICE;
+    }
+    sj::pool_leave_after_sync();
+    if (rc == SJ_OK) t_error.clear();
+    return rc;
+}
+
+// Buffers handed to the caller by sj_selfjoin: remembered so sj_free knows
+// how to release them.
+std::mutex g_out_mu;
+std::map<void *, bool> g_out_bufs;  // ptr -> on device
+
+// FP32 pre-test thresholds (the reading documented with the band kernel):
+// gamma(k, u) = k u / (1 - k u); tau = X 2^-24 (1 + 2^-28) + 2^-126;
+// Delta(E) = 4 tau sqrt(dE) + 4 d tau^2 + gamma(d+2, 2^-24)(sqrt E + 2 tau sqrt d)^2
+//            + (2d + 2) 2^-126;
+// lo = down32(E_a - 2 Delta(E_a)), hi = up32(E_r + 2 Delta(E_r)),
+// E_a = eps^2 / (1 + g64), E_r = eps^2 / (1 - g64), g64 = gamma(d+2, 2^-53).
+bool band_thresholds(uint32_t d, double eps, double extent, float *lo, float *hi) {
+    const double u32 = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
+    const double tiny = std::ldexp(1.0, -126);
+    auto gamma = [](double k, double u) { return k * u / (1.0 - k * u); };
+    const double tau = extent * u32 * (1.0 + std::ldexp(1.0, -28)) + tiny;
+    if (!(eps >= 64.0 * tau * std::sqrt(static_cast<double>(d)))) return false;
+    const double dd = static_cast<double>(d);
+    auto delta = [&](double E) {
+        const double rE = std::sqrt(E > 0 ? E : 0.0);
+        const double a = rE + 2.0 * tau * std::sqrt(dd);
+        return 4.0 * tau * std::sqrt(dd * E) + 4.0 * dd * tau * tau + gamma(dd + 2.0, u32) * a * a +
+               (2.0 * dd + 2.0) * tiny;
+    };
+    const double eps2 = eps * eps;
+    const double g64 = gamma(dd + 2.0, u64);
+    const double Ea = eps2 / (1.0 + g64), Er = eps2 / (1.0 - g64);
+    const double l = Ea - 2.0 * delta(Ea), h = Er + 2.0 * delta(Er);
+    float lf = static_cast<float>(l);
+    if (static_cast<double>(lf) > l) lf = std::nextafter(lf, -std::numeric_limits<float>::infinity());
+    float hf = static_cast<float>(h);
+    if (static_cast<double>(hf) < h) hf = std::nextafter(hf, std::numeric_limits<float>::infinity());
+    *lo = lf;
+    *hi = hf;
+    return true;
+}
+
+}  // namespace
+
+struct sj_index {
+    uint64_t n = 0;
+    uint32_t d = 0;
+    double eps = 0.0;
+    sj::GridParams grid{};
+    int key_bits = 0;
+    uint64_t ncells = 0;
+    uint32_t max_cell = 0;
+    double bmin[sj::kMaxDim] = {}, bmax[sj::kMaxDim] = {};
+    // resident arrays
+    DevBuf<double> X;        // d x n, cell order
+    DevBuf<float> Y;         // d x n, cell order, shifted FP32 copy (built on demand)
+    bool y_ready = false;
+    double shift[sj::kMaxDim] = {};
+    double extent = 0.0;
+    DevBuf<uint32_t> perm;   // A
+    DevBuf<uint32_t> cell_of;
+    DevBuf<uint64_t> B;
+    DevBuf<uint32_t> starts;
+    DevBuf<uint32_t> coords;
+    DevBuf<uint32_t> masks;
+    uint32_t mask_off[sj::kMaxDim] = {};
+    uint32_t mask_words = 0;
+    // adjacent-cell search, cached per setting: [0] all adjacent cells,
+    // [1] the unicomp subset
+    struct Ranges {
+        bool ready = false;
+        DevBuf<uint64_t> roff;
+        uint32_t *rng = nullptr;
+        size_t cap = 0;
+        uint64_t count = 0;
+    } ranges[2];
+    int last_ranges = -1;
+    // join state
+    bool counted = false;
+    sj_join_opts opts{};
+    int band_used = 0;
+    float lo = 0.f, hi = 0.f;
+    DevBuf<uint32_t> own_cnt, in_cnt, len_orig, cur;
+    DevBuf<uint64_t> off_orig, offc;
+    DevBuf<unsigned long long> counters;  // evals, band rechecks
+    DevBuf<uint32_t> max_len;
+    DevBuf<uint32_t> overflow;
+    uint64_t pairs = 0;
+    uint32_t max_row = 0;
+    sj_stats stats{};
+
+    ~sj_index() {
+        for (auto &r : ranges)
+            if (r.rng) sj::dev_free(r.rng);
+    }
+};
+
+namespace {
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+void compute_grid(sj_index &ix) {
+    const uint32_t d = ix.d;
+    double w = std::nextafter(ix.eps * (1.0 + std::ldexp(1.0, -16)),
+                              std::numeric_limits<double>::infinity());
+    const unsigned __int128 limit = static_cast<unsigned __int128>(1) << 63;
+    for (int attempt = 0; attempt < 2100; ++attempt) {
+        bool ok = std::isfinite(w);
+        unsigned __int128 prod = 1;
+        for (uint32_t j = 0; j < d && ok; ++j) {
+            const double gmin = ix.bmin[j] - w;
+            const double cells = std::floor((ix.bmax[j] - gmin) / w) + 2.0;
+            if (!std::isfinite(gmin) || !(cells < 2147483648.0)) {
+                ok = false;
+                break;
+            }
+            ix.grid.gmin[j] = gmin;
+            ix.grid.dims[j] = static_cast<uint64_t>(cells);
+            prod *= static_cast<unsigned __int128>(ix.grid.dims[j]);
+            if (prod >= limit) ok = false;
+        }
+        if (ok) {
+            ix.grid.w = w;
+            ix.grid.d = d;
+            uint64_t stride = 1;
+            for (uint32_t j = 0; j < d; ++j) {
+                ix.grid.stride[j] = stride;
+                stride *= ix.grid.dims[j];
+            }
+            const uint64_t maxid = stride - 1;
+            int bits = 0;
+            while (bits < 64 && (maxid >> bits) != 0) ++bits;
+            ix.key_bits = bits;
+            return;
+        }
+        w = w * 2.0;
+    }
+    throw Error(SJ_EGRID, "grid cannot be represented (coordinate range too large for eps)");
+}
+
+void validate_points_args(const double *pts, uint64_t n, uint32_t d, double eps) {
+    if (d < 1 || d > static_cast<uint32_t>(sj::kMaxDim)) throw Error(SJ_EINVAL, "d must be in [1, 8]");
+    if (!(eps > 0.0) || !std::isfinite(eps)) throw Error(SJ_EINVAL, "eps must be finite and > 0");
+    if (n >= 0xffffffffULL) throw Error(SJ_EINVAL, "n must be below 2^32 - 1");
+    if (n > 0 && !pts) throw Error(SJ_EINVAL, "pts is NULL");
+}
+
+void validate_opts(const sj_join_opts *o) {
+    if (!o) return;
+    if (o->precision != SJ_FP64 && o->precision != SJ_FP32_BAND)
+        throw Error(SJ_EINVAL, "precision must be SJ_FP64 or SJ_FP32_BAND");
+    if (o->reserved != 0) throw Error(SJ_EINVAL, "opts.reserved must be 0");
+}
+
+sj_join_opts resolve_opts(const sj_join_opts *o) {
+    sj_join_opts r;
+    sj_default_opts(&r);
+    if (o) r = *o;
+    if (r.min_batches == 0) r.min_batches = 1;
+    return r;
+}
+
+void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
+    const double t0 = now_ms();
+    const uint64_t n = ix.n;
+    const uint32_t d = ix.d;
+    DevBuf<double> staged;
+    const double *dp = pts;
+    if (!on_device) {
+        staged.reset(n * d);
+        SJ_HIP(hipMemcpyAsync(staged.ptr, pts, n * d * sizeof(double), hipMemcpyHostToDevice, s));
+        dp = staged.ptr;
+    }
+    // bounding box (Section IV-B)
+    DevBuf<double> bb(2 * sj::kMaxDim);
+    DevBuf<uint32_t> bad(1);
+    sj::launch_bbox(dp, n, d, bb.ptr, bad.ptr, s);
+    double hb[2 * sj::kMaxDim];
+    uint32_t hbad = 0;
+    SJ_HIP(hipMemcpyAsync(hb, bb.ptr, sizeof(hb), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(&hbad, bad.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    if (hbad) throw Error(SJ_EINVAL, "coordinates contain NaN or Inf");
+    for (uint32_t j = 0; j < d; ++j) {
+        ix.bmin[j] = hb[j];
+        ix.bmax[j] = hb[sj::kMaxDim + j];
+    }
+    compute_grid(ix);
+    // cell ids and the sort by cell (A)
+    ix.perm.reset(n);
+    DevBuf<uint32_t> ids_alt(n);
+    ix.cell_of.reset(n);
+    ix.B.reset(n);
+    ix.starts.reset(n + 1);
+    if (ix.key_bits <= 32) {
+        DevBuf<uint32_t> keys(n), keys_alt(n);
+        sj::launch_cell_keys_u32(dp, n, ix.grid, keys.ptr, ix.perm.ptr, s);
+        sj::radix_sort_u32(keys.ptr, ix.perm.ptr, keys_alt.ptr, ids_alt.ptr, n, ix.key_bits, s);
+        ix.ncells = sj::build_cells<uint32_t>(keys.ptr, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
+    } else {
+        DevBuf<uint64_t> keys(n), keys_alt(n);
+        sj::launch_cell_keys_u64(dp, n, ix.grid, keys.ptr, ix.perm.ptr, s);
+        sj::radix_sort_u64(keys.ptr, ix.perm.ptr, keys_alt.ptr, ids_alt.ptr, n, ix.key_bits, s);
+        ix.ncells = sj::build_cells<uint64_t>(keys.ptr, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
+    }
+    // per-cell coordinates and occupancy masks M_j (Section IV-C)
+    uint64_t words = 0;
+    for (uint32_t j = 0; j < d; ++j) {
+        ix.mask_off[j] = static_cast<uint32_t>(words);
+        words += (ix.grid.dims[j] + 31) / 32;
+    }
+    DevBuf<uint32_t> moff(sj::kMaxDim);
+    if (words <= (1ull << 26)) {
+        ix.mask_words = static_cast<uint32_t>(words);
+        ix.masks.reset(words);
+        SJ_HIP(hipMemcpyAsync(moff.ptr, ix.mask_off, sizeof(ix.mask_off), hipMemcpyHostToDevice, s));
+    } else {
+        ix.mask_words = 0;  // masks only prune; a grid this wide goes without
+    }
+    ix.coords.reset(ix.ncells * d);
+    ix.max_cell = sj::launch_cell_coords_masks(ix.B.ptr, ix.starts.ptr, ix.ncells, ix.grid,
+                                               ix.coords.ptr, ix.masks.ptr, moff.ptr,
+                                               ix.mask_words, s);
+    // cell-ordered structure of arrays
+    ix.X.reset(n * d);
+    sj::launch_gather_soa(dp, ix.perm.ptr, n, d, ix.X.ptr, s);
+    for (uint32_t j = 0; j < d; ++j) {
+        ix.shift[j] = 0.5 * (ix.bmin[j] + ix.bmax[j]);
+        ix.extent = std::max(ix.extent, std::max(std::fabs(ix.bmax[j] - ix.shift[j]),
+                                                 std::fabs(ix.bmin[j] - ix.shift[j])));
+    }
+    SJ_HIP(hipStreamSynchronize(s));
+    ix.stats.ms_build = now_ms() - t0;
+}
+
+void ensure_ranges(sj_index &ix, int unicomp, hipStream_t s) {
+    ix.last_ranges = unicomp;
+    auto &R = ix.ranges[unicomp];
+    if (R.ready) return;
+    sj::SearchArgs a{};
+    a.B = ix.B.ptr;
+    a.starts = ix.starts.ptr;
+    a.coords = ix.coords.ptr;
+    a.masks = ix.mask_words ? ix.masks.ptr : nullptr;
+    for (uint32_t j = 0; j < ix.d; ++j) {
+        a.mask_off[j] = ix.mask_off[j];
+        a.dims[j] = ix.grid.dims[j];
+        a.stride[j] = ix.grid.stride[j];
+    }
+    a.ncells = static_cast<uint32_t>(ix.ncells);
+    a.d = ix.d;
+    R.roff.ensure(ix.ncells + 1);
+    R.count = sj::build_ranges(a, unicomp, R.roff.ptr, &R.rng, &R.cap, s);
+    R.ready = true;
+}
+
+void ensure_f32(sj_index &ix, hipStream_t s) {
+    if (ix.y_ready) return;
+    ix.Y.reset(ix.n * ix.d);
+    sj::launch_make_f32(ix.X.ptr, ix.n, ix.d, ix.shift, ix.Y.ptr, s);
+    ix.y_ready = true;
+}
+
+sj::JoinArgs base_args(sj_index &ix, int mode) {
+    sj::JoinArgs a{};
+    const auto &R = ix.ranges[mode];
+    a.X = ix.X.ptr;
+    a.Y = ix.band_used ? ix.Y.ptr : nullptr;
+    a.n = static_cast<uint32_t>(ix.n);
+    a.cell_of = ix.cell_of.ptr;
+    a.starts = ix.starts.ptr;
+    a.roff = R.roff.ptr;
+    a.rng = reinterpret_cast<const uint2 *>(R.rng);
+    a.qlist = nullptr;
+    a.nq = static_cast<uint32_t>(ix.n);
+    a.eps2 = ix.eps * ix.eps;
+    a.lo = ix.lo;
+    a.hi = ix.hi;
+    a.own_cnt = ix.own_cnt.ptr;
+    a.in_cnt = ix.in_cnt.ptr;
+    a.offc = ix.offc.ptr;
+    a.perm = ix.perm.ptr;
+    a.evals = ix.counters.ptr;
+    a.band_rechecks = ix.counters.ptr + 1;
+    return a;
+}
+
+void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
+    const double t0 = now_ms();
+    ix.counted = false;
+    ix.opts = o;
+    ix.pairs = 0;
+    ix.max_row = 0;
+    ix.stats.evals = ix.stats.band_rechecks = 0;
+    ix.stats.pairs = 0;
+    ix.stats.max_row_pairs = 0;
+    ix.stats.unicomp_used = o.unicomp ? 1u : 0u;
+    ix.band_used = 0;
+    if (o.precision == SJ_FP32_BAND && ix.n > 0)
+        ix.band_used = band_thresholds(ix.d, ix.eps, ix.extent, &ix.lo, &ix.hi) ? 1 : 0;
+    ix.stats.precision_used = ix.band_used ? SJ_FP32_BAND : SJ_FP64;
+    if (ix.n == 0) {
+        ix.counted = true;
+        ix.stats.ms_count = now_ms() - t0;
+        return;
+    }
+    const int uni = o.unicomp ? 1 : 0;
+    ensure_ranges(ix, uni, s);
+    if (ix.band_used) ensure_f32(ix, s);
+    const uint64_t n = ix.n;
+    ix.own_cnt.ensure(n);
+    ix.in_cnt.ensure(n);
+    ix.len_orig.ensure(n);
+    ix.off_orig.ensure(n + 1);
+    ix.offc.ensure(n);
+    ix.counters.ensure(2);
+    ix.max_len.ensure(1);
+    if (uni) sj::launch_fill_u32(ix.in_cnt.ptr, n, 0u, s);
+    sj::launch_fill_u64(reinterpret_cast<uint64_t *>(ix.counters.ptr), 2, 0ull, s);
+    sj::launch_fill_u32(ix.max_len.ptr, 1, 0u, s);
+    sj::JoinArgs a = base_args(ix, uni);
+    sj::launch_join(a, ix.d, uni, sj::kCount, ix.band_used, s);
+    sj::launch_row_lengths(ix.own_cnt.ptr, uni ? ix.in_cnt.ptr : nullptr, ix.perm.ptr, n,
+                           ix.len_orig.ptr, s);
+    sj::scan_exclusive_u32_to_u64(ix.len_orig.ptr, ix.off_orig.ptr, n, s);
+    sj::launch_gather_offsets(ix.off_orig.ptr, ix.perm.ptr, n, ix.offc.ptr, ix.max_len.ptr,
+                              ix.len_orig.ptr, s);
+    unsigned long long cnt[2];
+    SJ_HIP(hipMemcpyAsync(&ix.pairs, ix.off_orig.ptr + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(&ix.max_row, ix.max_len.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(cnt, ix.counters.ptr, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    ix.stats.evals = cnt[0];
+    ix.stats.band_rechecks = cnt[1];
+    ix.stats.pairs = ix.pairs;
+    ix.stats.max_row_pairs = ix.max_row;
+    ix.stats.ranges = ix.ranges[uni].count;
+    ix.counted = true;
+    ix.stats.ms_count = now_ms() - t0;
+}
+
+void check_overflow(sj_index &ix, hipStream_t s) {
+    uint32_t ov = 0;
+    SJ_HIP(hipMemcpyAsync(&ov, ix.overflow.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    if (ov) throw Error(SJ_EDEVICE, "internal: the fill pass disagreed with the count pass");
+}
+
+// Fill + row sort of result rows [i0, i1) into out_j / pairs (batch-relative).
+// unicomp_fill: evaluate the unicomp subset over all points (valid only for
+// the single batch holding every row); otherwise the batch's own query
+// points scan all adjacent cells and write only their own rows.
+struct Scratch {
+    DevBuf<uint32_t> qlist, flags, big_list, big_count;
+};
+
+void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t cap,
+               bool unicomp_fill, uint32_t *out_j, uint32_t *pairs, Scratch &sc, hipStream_t s) {
+    const uint64_t n = ix.n;
+    const int mode = unicomp_fill ? 1 : 0;
+    ensure_ranges(ix, mode, s);
+    sj::JoinArgs a = base_args(ix, mode);
+    a.out_j = out_j;
+    a.out_base = base;
+    a.out_cap = cap;
+    ix.overflow.ensure(1);
+    a.overflow = ix.overflow.ptr;
+    if (unicomp_fill) {
+        ix.cur.ensure(n);
+        sj::launch_fill_u32(ix.cur.ptr, n, 0u, s);
+        a.cur = ix.cur.ptr;
+        sj::launch_join(a, ix.d, 1, sj::kFill, ix.band_used, s);
+    } else {
+        if (i0 == 0 && i1 == n) {
+            a.qlist = nullptr;
+            a.nq = static_cast<uint32_t>(n);
+        } else {
+            sc.qlist.ensure(n);
+            sc.flags.ensure(n);
+            a.nq = sj::build_query_list(ix.perm.ptr, n, i0, i1, sc.flags.ptr, sc.qlist.ptr, s);
+            a.qlist = sc.qlist.ptr;
+        }
+        sj::launch_join(a, ix.d, 0, sj::kFill, ix.band_used, s);
+    }
+    sc.big_list.ensure(std::max<uint64_t>(1, i1 - i0));
+    sc.big_count.ensure(1);
+    sj::launch_rowsort(ix.off_orig.ptr, i0, i1, base, out_j, pairs, sc.big_list.ptr,
+                       sc.big_count.ptr, s);
+}
+
+void join_fill_all(sj_index &ix, uint32_t *pairs_dev, hipStream_t s) {
+    const double t0 = now_ms();
+    if (ix.n == 0 || ix.pairs == 0) return;
+    DevBuf<uint32_t> out_j(ix.pairs);
+    Scratch sc;
+    ix.overflow.ensure(1);
+    sj::launch_fill_u32(ix.overflow.ptr, 1, 0u, s);
+    fill_rows(ix, 0, ix.n, 0, ix.pairs, ix.opts.unicomp != 0, out_j.ptr, pairs_dev, sc, s);
+    check_overflow(ix, s);
+    ix.stats.batches = 1;
+    ix.stats.ms_fill = now_ms() - t0;
+}
+
+// Batched delivery (Section V-A): consecutive row ranges, double-buffered so
+// batch b+1 computes while the callback consumes batch b.
+int join_batched(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
+    const double t0 = now_ms();
+    const uint64_t n = ix.n, P = ix.pairs;
+    if (n == 0 || P == 0) {
+        ix.stats.batches = 0;
+        return 0;
+    }
+    const uint64_t cap = ix.opts.batch_capacity_pairs ? ix.opts.batch_capacity_pairs : P;
+    if (ix.max_row > cap)
+        throw Error(SJ_ECAPACITY, "batch capacity is smaller than the longest result row (" +
+                                      std::to_string(ix.max_row) + " pairs)");
+    const uint64_t per = cap > ix.max_row ? cap - ix.max_row : 1;
+    uint64_t nb64 = std::max<uint64_t>(ix.opts.min_batches, (P + per - 1) / per);
+    if (cap >= P && ix.opts.min_batches <= 1) nb64 = 1;
+    nb64 = std::min<uint64_t>(nb64, n);
+    const uint32_t nb = static_cast<uint32_t>(nb64);
+    std::vector<uint64_t> rows(nb + 1);
+    {
+        DevBuf<uint64_t> drows(nb + 1);
+        sj::launch_batch_bounds(ix.off_orig.ptr, n, P, nb, drows.ptr, s);
+        SJ_HIP(hipMemcpyAsync(rows.data(), drows.ptr, (nb + 1) * sizeof(uint64_t),
+                              hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<uint64_t> offs(nb + 1);
+    for (uint32_t b = 0; b <= nb; ++b)
+        SJ_HIP(hipMemcpyAsync(&offs[b], ix.off_orig.ptr + rows[b], sizeof(uint64_t),
+                              hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    uint64_t maxbatch = 0;
+    for (uint32_t b = 0; b < nb; ++b) maxbatch = std::max(maxbatch, offs[b + 1] - offs[b]);
+    const bool uni_fill = (nb == 1) && ix.opts.unicomp;
+    const int nsets = nb > 1 ? 2 : 1;
+    DevBuf<uint32_t> out_j[2], pairs[2];
+    for (int k = 0; k < nsets; ++k) {
+        out_j[k].reset(std::max<uint64_t>(1, maxbatch));
+        pairs[k].reset(2 * std::max<uint64_t>(1, maxbatch));
+    }
+    hipEvent_t ev[2];
+    SJ_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    SJ_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } evg{ev};
+    Scratch sc;
+    int rc = 0;
+    uint32_t delivered = 0;
+    auto deliver = [&](uint32_t b) {
+        const int k = b & 1;
+        SJ_HIP(hipEventSynchronize(ev[k]));
+        if (rc == 0 && cb)
+            rc = cb(user, pairs[k].ptr, offs[b + 1] - offs[b], b, rows[b], rows[b + 1]);
+        ++delivered;
+    };
+    ix.overflow.ensure(1);
+    sj::launch_fill_u32(ix.overflow.ptr, 1, 0u, s);
+    for (uint32_t b = 0; b < nb && rc == 0; ++b) {
+        const int k = b & 1;
+        if (offs[b + 1] > offs[b])
+            fill_rows(ix, rows[b], rows[b + 1], offs[b], offs[b + 1] - offs[b], uni_fill,
+                      out_j[k].ptr, pairs[k].ptr, sc, s);
+        SJ_HIP(hipEventRecord(ev[k], s));
+        if (b >= 1) deliver(b - 1);
+    }
+    if (rc == 0) deliver(nb - 1);
+    check_overflow(ix, s);
+    ix.stats.batches = nb;
+    ix.stats.ms_fill = now_ms() - t0;
+    return rc;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+void sj_default_opts(sj_join_opts *o) {
+    if (!o) return;
+    o->unicomp = 1;
+    o->precision = SJ_FP64;
+    o->batch_capacity_pairs = 0;
+    o->min_batches = 1;
+    o->reserved = 0;
+}
+
+const char *sj_last_error(void) { return t_error.c_str(); }
+
+const char *sj_version(void) { return "sj 0.1 (gfx950)"; }
+
+int sj_build_index(const double *pts, uint64_t n, uint32_t d, double eps, int pts_on_device,
+                   void *stream, sj_index **out) {
+    hipStream_t s = as_stream(stream);
+    return guarded(s, [&] {
+        if (!out) throw Error(SJ_EINVAL, "out is NULL");
+        *out = nullptr;
+        validate_points_args(pts, n, d, eps);
+        auto *ix = new sj_index;
+        ix->n = n;
+        ix->d = d;
+        ix->eps = eps;
+        ix->grid.d = d;
+        try {
+            if (n > 0) build(*ix, pts, pts_on_device, s);
+        } catch (...) {
+            (void)hipStreamSynchronize(s);
+            delete ix;
+            throw;
+        }
+        ix->stats.n = n;
+        ix->stats.d = d;
+        ix->stats.eps = eps;
+        *out = ix;
+    });
+}
+
+void sj_destroy_index(sj_index *idx) {
+    if (!idx) return;
+    (void)guarded(nullptr, [&] { delete idx; });
+}
+
+int sj_join_count(sj_index *idx, const sj_join_opts *opts, void *stream, uint64_t *total_pairs) {
+    hipStream_t s = as_stream(stream);
+    return guarded(s, [&] {
+        if (!idx) throw Error(SJ_EINVAL, "index is NULL");
+        validate_opts(opts);
+        join_count(*idx, resolve_opts(opts), s);
+        if (total_pairs) *total_pairs = idx->pairs;
+    });
+}
+
+int sj_join_fill(sj_index *idx, uint32_t *pairs_dev, uint64_t capacity_pairs, void *stream) {
+    hipStream_t s = as_stream(stream);
+    return guarded(s, [&] {
+        if (!idx) throw Error(SJ_EINVAL, "index is NULL");
+        if (!idx->counted) throw Error(SJ_ESTATE, "sj_join_fill needs a preceding sj_join_count");
+        if (capacity_pairs < idx->pairs)
+            throw Error(SJ_ECAPACITY, "output buffer holds " + std::to_string(capacity_pairs) +
+                                          " pairs, the result has " + std::to_string(idx->pairs));
+        if (idx->pairs && !pairs_dev) throw Error(SJ_EINVAL, "pairs_dev is NULL");
+        join_fill_all(*idx, pairs_dev, s);
+    });
+}
+
+int sj_selfjoin_index(sj_index *idx, const sj_join_opts *opts, sj_run_cb cb, void *user,
+                      void *stream, uint64_t *total_pairs) {
+    hipStream_t s = as_stream(stream);
+    int cb_rc = 0;
+    const int rc = guarded(s, [&] {
+        if (!idx) throw Error(SJ_EINVAL, "index is NULL");
+        validate_opts(opts);
+        join_count(*idx, resolve_opts(opts), s);
+        if (total_pairs) *total_pairs = idx->pairs;
+        cb_rc = join_batched(*idx, cb, user, s);
+    });
+    if (rc != SJ_OK) return rc;
+    if (cb_rc != 0) set_error("the batch callback stopped the join");
+    return cb_rc;
+}
+
+int sj_selfjoin(const double *pts, uint64_t n, uint32_t d, double eps, const sj_join_opts *opts,
+                int pts_on_device, int out_on_device, void *stream, uint32_t **pairs_out,
+                uint64_t *npairs) {
+    hipStream_t s = as_stream(stream);
+    if (!pairs_out || !npairs) {
+        set_error("pairs_out and npairs must not be NULL");
+        return SJ_EINVAL;
+    }
+    *pairs_out = nullptr;
+    *npairs = 0;
+    sj_index *ix = nullptr;
+    int rc = sj_build_index(pts, n, d, eps, pts_on_device, stream, &ix);
+    if (rc != SJ_OK) return rc;
+    uint32_t *buf = nullptr;
+    rc = guarded(s, [&] {
+        validate_opts(opts);
+        const sj_join_opts o = resolve_opts(opts);
+        join_count(*ix, o, s);
+        const uint64_t P = ix->pairs;
+        if (P == 0) return;
+        if (out_on_device) {
+            SJ_HIP(hipMalloc(reinterpret_cast<void **>(&buf), P * 2 * sizeof(uint32_t)));
+            {
+                std::lock_guard<std::mutex> lk(g_out_mu);
+                g_out_bufs[buf] = true;
+            }
+            if (o.batch_capacity_pairs == 0 && o.min_batches <= 1) {
+                join_fill_all(*ix, buf, s);
+            } else {
+                struct Ctx { uint32_t *dst; hipStream_t s; uint64_t at; } ctx{buf, s, 0};
+                auto cb = [](void *u, const uint32_t *p, uint64_t np, uint32_t, uint64_t, uint64_t) -> int {
+                    auto *c = static_cast<Ctx *>(u);
+                    if (hipMemcpyAsync(c->dst + 2 * c->at, p, np * 8, hipMemcpyDeviceToDevice, c->s) != hipSuccess)
+                        return SJ_EDEVICE;
+                    if (hipStreamSynchronize(c->s) != hipSuccess) return SJ_EDEVICE;
+                    c->at += np;
+                    return 0;
+                };
+                const int r = join_batched(*ix, cb, &ctx, s);
+                if (r) throw Error(r, "batched device copy failed");
+            }
+        } else {
+            SJ_HIP(hipHostMalloc(reinterpret_cast<void **>(&buf), P * 2 * sizeof(uint32_t),
+                                 hipHostMallocDefault));
+            {
+                std::lock_guard<std::mutex> lk(g_out_mu);
+                g_out_bufs[buf] = false;
+            }
+            hipStream_t cs = nullptr;
+            SJ_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            struct Ctx { uint32_t *dst; hipStream_t cs; uint64_t at; } ctx{buf, cs, 0};
+            auto cb = [](void *u, const uint32_t *p, uint64_t np, uint32_t, uint64_t, uint64_t) -> int {
+                auto *c = static_cast<Ctx *>(u);
+                if (hipMemcpyAsync(c->dst + 2 * c->at, p, np * 8, hipMemcpyDeviceToHost, c->cs) != hipSuccess)
+                    return SJ_EDEVICE;
+                if (hipStreamSynchronize(c->cs) != hipSuccess) return SJ_EDEVICE;
+                c->at += np;
+                return 0;
+            };
+            int r = 0;
+            try {
+                r = join_batched(*ix, cb, &ctx, s);
+            } catch (...) {
+                (void)hipStreamSynchronize(cs);
+                (void)hipStreamDestroy(cs);
+                throw;
+            }
+            (void)hipStreamSynchronize(cs);
+            (void)hipStreamDestroy(cs);
+            if (r) throw Error(r, "batched host copy failed");
+        }
+        *npairs = P;
+        *pairs_out = buf;
+    });
+    if (rc != SJ_OK && buf) sj_free(buf);
+    sj_destroy_index(ix);
+    if (rc != SJ_OK) {
+        *pairs_out = nullptr;
+        *npairs = 0;
+    }
+    return rc;
+}
+
+void sj_free(void *ptr) {
+    if (!ptr) return;
+    bool on_dev = true;
+    {
+        std::lock_guard<std::mutex> lk(g_out_mu);
+        auto it = g_out_bufs.find(ptr);
+        if (it == g_out_bufs.end()) return;
+        on_dev = it->second;
+        g_out_bufs.erase(it);
+    }
+    if (on_dev)
+        (void)hipFree(ptr);
+    else
+        (void)hipHostFree(ptr);
+}
+
+int sj_index_stats(const sj_index *idx, sj_stats *out) {
+    if (!idx || !out) {
+        set_error("NULL argument");
+        return SJ_EINVAL;
+    }
+    sj_stats st = idx->stats;
+    st.n = idx->n;
+    st.d = idx->d;
+    st.key_bits = static_cast<uint32_t>(idx->key_bits);
+    st.cells = idx->ncells;
+    for (int j = 0; j < sj::kMaxDim; ++j) st.grid_dims[j] = j < static_cast<int>(idx->d) ? idx->grid.dims[j] : 0;
+    st.eps = idx->eps;
+    st.cell_width = idx->grid.w;
+    st.max_cell_points = idx->max_cell;
+    *out = st;
+    return SJ_OK;
+}
+
+int sj_index_export_size(const sj_index *idx, int what, uint64_t *bytes) {
+    if (!idx || !bytes) {
+        set_error("NULL argument");
+        return SJ_EINVAL;
+    }
+    switch (what) {
+        case SJ_EXPORT_CELL_IDS: *bytes = idx->ncells * sizeof(uint64_t); break;
+        case SJ_EXPORT_CELL_START: *bytes = idx->n ? (idx->ncells + 1) * sizeof(uint32_t) : 0; break;
+        case SJ_EXPORT_PERM: *bytes = idx->n * sizeof(uint32_t); break;
+        case SJ_EXPORT_MASKS: *bytes = static_cast<uint64_t>(idx->mask_words) * sizeof(uint32_t); break;
+        case SJ_EXPORT_RANGE_OFF:
+            *bytes = (idx->last_ranges >= 0 && idx->ncells) ? (idx->ncells + 1) * sizeof(uint64_t) : 0;
+            break;
+        case SJ_EXPORT_RANGES:
+            *bytes = idx->last_ranges >= 0 ? idx->ranges[idx->last_ranges].count * 2 * sizeof(uint32_t) : 0;
+            break;
+        case SJ_EXPORT_GRID: *bytes = (2 * sj::kMaxDim + 1) * sizeof(double); break;
+        default: set_error("unknown export"); return SJ_EINVAL;
+    }
+    return SJ_OK;
+}
+
+int sj_index_export(const sj_index *idx, int what, void *host_dst, uint64_t bytes) {
+    uint64_t need = 0;
+    int rc = sj_index_export_size(idx, what, &need);
+    if (rc != SJ_OK) return rc;
+    if (bytes != need) {
+        set_error("export size mismatch: expected " + std::to_string(need));
+        return SJ_EINVAL;
+    }
+    if (need == 0) return SJ_OK;
+    if (!host_dst) {
+        set_error("host_dst is NULL");
+        return SJ_EINVAL;
+    }
+    return guarded(nullptr, [&] {
+        const void *src = nullptr;
+        switch (what) {
+            case SJ_EXPORT_CELL_IDS: src = idx->B.ptr; break;
+            case SJ_EXPORT_CELL_START: src = idx->starts.ptr; break;
+            case SJ_EXPORT_PERM: src = idx->perm.ptr; break;
+            case SJ_EXPORT_MASKS: src = idx->masks.ptr; break;
+            case SJ_EXPORT_RANGE_OFF: src = idx->ranges[idx->last_ranges].roff.ptr; break;
+            case SJ_EXPORT_RANGES: src = idx->ranges[idx->last_ranges].rng; break;
+            case SJ_EXPORT_GRID: {
+                double g[2 * sj::kMaxDim + 1] = {};
+                for (uint32_t j = 0; j < idx->d; ++j) {
+                    g[j] = idx->grid.gmin[j];
+                    g[sj::kMaxDim + j] = static_cast<double>(idx->grid.dims[j]);
+                }
+                g[2 * sj::kMaxDim] = idx->grid.w;
+                std::memcpy(host_dst, g, sizeof(g));
+                return;
+            }
+        }
+        SJ_HIP(hipMemcpy(host_dst, src, need, hipMemcpyDeviceToHost));
+    });
+}
+
+int sj_index_search(sj_index *idx, int unicomp, void *stream) {
+    hipStream_t s = as_stream(stream);
+    return guarded(s, [&] {
+        if (!idx) throw Error(SJ_EINVAL, "index is NULL");
+        if (idx->n) ensure_ranges(*idx, unicomp ? 1 : 0, s);
+    });
+}
+
+int sj_band_thresholds(uint32_t d, double eps, double extent, float *lo, float *hi) {
+    if (!lo || !hi || d < 1 || d > static_cast<uint32_t>(sj::kMaxDim) || !(eps > 0) ||
+        !std::isfinite(eps) || !(extent >= 0) || !std::isfinite(extent)) {
+        set_error("bad argument");
+        return SJ_EINVAL;
+    }
+    if (!band_thresholds(d, eps, extent, lo, hi)) {
+        set_error("FP32 pre-test not usable: eps too small for the coordinate extent");
+        return SJ_EINVAL;
+    }
+    return SJ_OK;
+}
+
+}  // extern "C"

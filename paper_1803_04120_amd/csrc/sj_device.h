@@ -1,0 +1,69 @@
+// Wave64 / workgroup helpers for gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace sj {
+
+__device__ __forceinline__ int lane_id() { return static_cast<int>(threadIdx.x & 63u); }
+
+// Number of set bits of `mask` in lanes below the calling lane.
+__device__ __forceinline__ uint32_t mbcnt(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T y = __shfl_up(v, off, 64);
+        if (lane >= off) v += y;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const T y = __shfl_xor(v, off, 64);
+        v = y > v ? y : v;
+    }
+    return v;
+}
+
+// Exclusive prefix of one value per thread over a workgroup of kThreads
+// (multiple of 64). *total receives the workgroup sum. `lds` holds
+// kThreads/64 values. Contains two barriers; every thread must call it.
+template <typename T, int kThreads>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *total, T *lds) {
+    const int lane = lane_id();
+    const int wave = static_cast<int>(threadIdx.x >> 6);
+    const T incl = wave_inclusive_scan(v);
+    if (lane == 63) lds[wave] = incl;
+    __syncthreads();
+    T before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        const T x = lds[w];
+        if (w < wave) before += x;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - v;
+}
+
+}  // namespace sj

@@ -1,0 +1,195 @@
+// Internal declarations shared by the HIP translation units of libsj.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "sj.h"
+
+namespace sj {
+
+constexpr int kMaxDim = 8;
+
+// Error carried from the internals to the C ABI boundary, where it becomes
+// a return code and the thread-local message.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char *what, const char *file, int line);
+#define SJ_HIP(call) ::sj::hip_check((call), #call, __FILE__, __LINE__)
+#define SJ_LAUNCH_CHECK() ::sj::hip_check(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
+
+// ---------------------------------------------------------------------
+// Device memory: a caching pool keyed by rounded size. Blocks are handed
+// back only after the owning call has synchronised its stream.
+// ---------------------------------------------------------------------
+void *dev_alloc(size_t bytes);
+void dev_free(void *p);
+void pool_trim();
+void pool_enter();
+void pool_leave_after_sync();
+
+template <typename T>
+struct DevBuf {
+    T *ptr = nullptr;
+    size_t count = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t n) { reset(n); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : ptr(o.ptr), count(o.count) { o.ptr = nullptr; o.count = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); ptr = o.ptr; count = o.count; o.ptr = nullptr; o.count = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void reset(size_t n) {
+        release();
+        count = n;
+        ptr = n ? static_cast<T *>(dev_alloc(n * sizeof(T))) : nullptr;
+    }
+    // grow-only reuse
+    void ensure(size_t n) { if (n > count) reset(n); }
+    void release() { if (ptr) dev_free(ptr); ptr = nullptr; count = 0; }
+    size_t bytes() const { return count * sizeof(T); }
+};
+
+// ---------------------------------------------------------------------
+// Grid description (Section IV-B), passed by value to kernels.
+// ---------------------------------------------------------------------
+struct GridParams {
+    double gmin[kMaxDim];
+    double w;
+    uint64_t dims[kMaxDim];
+    uint64_t stride[kMaxDim];
+    uint32_t d;
+};
+
+// ---------------------------------------------------------------------
+// Primitives (k_scan.hip, k_sort.hip)
+// ---------------------------------------------------------------------
+// out[i] = sum_{k<i} in[k] for i in [0, n]; out[n] is the total.
+void scan_exclusive_u32_to_u64(const uint32_t *in, uint64_t *out, size_t n, hipStream_t s);
+// in place inclusive scan of u32.
+void scan_inclusive_u32(uint32_t *data, size_t n, hipStream_t s);
+// exclusive scan of u32 into u32 (no total), in place allowed.
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) by the low `bits` bits of key.
+// On return the sorted data is in keys/vals (the alternate buffers are
+// scratch of the same size).
+void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
+                    size_t n, int bits, hipStream_t s);
+void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                    size_t n, int bits, hipStream_t s);
+
+// ---------------------------------------------------------------------
+// Index kernels (k_index.hip)
+// ---------------------------------------------------------------------
+// bbox_out[0..d) = min, [8..8+d) = max; *bad = nonzero if a NaN/Inf was seen.
+void launch_bbox(const double *pts, uint64_t n, uint32_t d, double *bbox_out, uint32_t *bad,
+                 hipStream_t s);
+void launch_cell_keys_u64(const double *pts, uint64_t n, const GridParams &g, uint64_t *keys,
+                          uint32_t *ids, hipStream_t s);
+void launch_cell_keys_u32(const double *pts, uint64_t n, const GridParams &g, uint32_t *keys,
+                          uint32_t *ids, hipStream_t s);
+// head flags + inclusive scan + cell tables. cell_of receives the cell of
+// each cell-ordered point, B the distinct ids, starts the first point of
+// each cell (starts[|G|] is written as n). Returns |G| (host sync).
+template <typename K>
+uint64_t build_cells(const K *sorted_keys, uint64_t n, uint32_t *cell_of, uint64_t *B,
+                     uint32_t *starts, hipStream_t s);
+// per-cell coordinates (cell-major, d per cell), occupancy masks, and the
+// largest cell (host sync for the latter).
+uint32_t launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_t ncells,
+                                  const GridParams &g, uint32_t *coords, uint32_t *masks,
+                                  const uint32_t *mask_off, uint32_t mask_words, hipStream_t s);
+void launch_gather_soa(const double *pts, const uint32_t *perm, uint64_t n, uint32_t d,
+                       double *X, hipStream_t s);
+void launch_make_f32(const double *X, uint64_t n, uint32_t d, const double *shift, float *Y,
+                     hipStream_t s);
+void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+void launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
+
+// ---------------------------------------------------------------------
+// Search and join (k_join.hip)
+// ---------------------------------------------------------------------
+struct SearchArgs {
+    const uint64_t *B;
+    const uint32_t *starts;
+    const uint32_t *coords;
+    const uint32_t *masks;
+    uint32_t mask_off[kMaxDim];
+    uint64_t dims[kMaxDim];
+    uint64_t stride[kMaxDim];
+    uint32_t ncells;
+    uint32_t d;
+};
+// Candidate point ranges of every cell: counts, scan, fill. Returns the
+// number of ranges R (host sync); roff gets |G|+1 entries, rng 2R values.
+uint64_t build_ranges(const SearchArgs &a, int unicomp, uint64_t *roff /*[ncells+1]*/,
+                      uint32_t **rng_out, size_t *rng_cap, hipStream_t s);
+
+struct JoinArgs {
+    const double *X;          // d x n, cell order
+    const float *Y;           // d x n, cell order, shifted (band path) or null
+    uint32_t n;
+    const uint32_t *cell_of;
+    const uint32_t *starts;
+    const uint64_t *roff;
+    const uint2 *rng;
+    const uint32_t *qlist;    // query points (cell order) or null for all
+    uint32_t nq;
+    double eps2;
+    float lo, hi;
+    // count outputs
+    uint32_t *own_cnt;
+    uint32_t *in_cnt;
+    // fill
+    const uint64_t *offc;     // row offset of each cell-ordered point's row
+    uint64_t out_base;
+    uint64_t out_cap;         // entries of out_j; writes at or past it set *overflow
+    uint32_t *overflow;
+    uint32_t *cur;
+    uint32_t *out_j;
+    const uint32_t *perm;     // A
+    // counters
+    unsigned long long *evals;
+    unsigned long long *band_rechecks;
+};
+enum JoinMode { kCount = 0, kFill = 1 };
+void launch_join(const JoinArgs &a, uint32_t d, int unicomp, int mode, int band, hipStream_t s);
+
+// row lengths in original order, exclusive offsets (u64, n+1), row offsets
+// in cell order, max row length (device).
+void launch_row_lengths(const uint32_t *own_cnt, const uint32_t *in_cnt, const uint32_t *perm,
+                        uint64_t n, uint32_t *len_orig, hipStream_t s);
+void launch_gather_offsets(const uint64_t *off_orig, const uint32_t *perm, uint64_t n,
+                           uint64_t *offc, uint32_t *max_len, const uint32_t *len_orig,
+                           hipStream_t s);
+// cell-ordered points whose original id lies in [i0, i1), in cell order.
+// Returns the count (host sync).
+uint32_t build_query_list(const uint32_t *perm, uint64_t n, uint64_t i0, uint64_t i1,
+                          uint32_t *flags_scratch, uint32_t *qlist, hipStream_t s);
+// rows[b] = first row i with off[i] >= floor(b * total / nb), b in [0, nb];
+// rows[nb] = n.
+void launch_batch_bounds(const uint64_t *off, uint64_t n, uint64_t total, uint32_t nb,
+                         uint64_t *rows, hipStream_t s);
+
+// ---------------------------------------------------------------------
+// Row sort and pair expansion (k_rowsort.hip)
+// ---------------------------------------------------------------------
+// Sorts each row's neighbour ids and writes interleaved (i, j) pairs.
+// Rows [i0, i1); row i occupies [off[i] - base, off[i+1] - base) of out_j
+// and of pairs. big_list/big_count are scratch (capacity i1 - i0 rows).
+void launch_rowsort(const uint64_t *off, uint64_t i0, uint64_t i1, uint64_t base,
+                    uint32_t *out_j, uint32_t *pairs, uint32_t *big_list, uint32_t *big_count,
+                    hipStream_t s);
+
+}  // namespace sj
