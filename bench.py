@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Throughput of the epsilon self-join on one MI355X.
+
+One step = the whole hot path for every eps of the workload: build the grid
+index (bounding box, cell ids, sort, cell tables, masks, cell-ordered copy),
+count pass (adjacent-cell search and refine), fill pass and row sorts, with
+the sorted (i, j) pairs written to a device buffer. Inputs are resident in
+HBM before the timed region starts; the output stays in HBM.
+
+Default workload: 2,000,000 points uniform in [0,100]^2 (FP64, seed 2), eps
+in {0.04, 0.08, 0.12, 0.16, 0.2} -- the shape of the paper's 2-D synthetic
+sets (Section VI-A). Prints ONE JSON line on stdout; everything else goes to
+stderr.
+
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # the 2-D sweep the headline metric is quoted on
+    "uniform2d_n2M_eps_sweep": dict(kind="uniform", n=2_000_000, d=2, seed=2,
+                                    eps=[0.04, 0.08, 0.12, 0.16, 0.2]),
+    # small 2-D case
+    "uniform2d_n10k_eps1": dict(kind="uniform", n=10_000, d=2, seed=1, eps=[1.0]),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="uniform2d_n2M_eps_sweep", choices=sorted(WORKLOADS))
+    ap.add_argument("--unicomp", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_band"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-capacity", type=int, default=1 << 24,
+                    help="pairs per batch for the batched-delivery figure")
+    return ap.parse_args()
+
+
+def kernel_bytes(name, n, d, cells, ranges, pairs):
+    """Algorithmic HBM bytes of one launch of a kernel (each array the
+    kernel must touch, read or written once). Neighbour re-reads, atomics and
+    scratch are overhead, not counted."""
+    if name.startswith("join_count"):
+        # X (d doubles) + cell of each point + its row length; cell range table
+        return n * (8 * d + 4 + 4) + 8 * (cells + 1) + 8 * ranges
+    if name.startswith("join_fill"):
+        # X + cell + row offset + permutation entry per point, range table,
+        # one 4-byte neighbour id per pair
+        return n * (8 * d + 4 + 8 + 4) + 8 * (cells + 1) + 8 * ranges + 4 * pairs
+    if name == "rowsort_small":
+        # row offsets, neighbour ids in, (i, j) pairs out
+        return 8 * (n + 1) + 4 * pairs + 8 * pairs
+    return None
+
+
+def pipeline_bytes(n, d, cells, pairs):
+    """Algorithmic bytes of the whole path for one eps: read the input,
+    write and read the cell-ordered copy (24 n d), the point map (4 n), the
+    cell tables written and read (32 |G|) and each pair written once (8 P)."""
+    return 24 * n * d + 4 * n + 32 * cells + 8 * pairs
+
+
+def cpu_baseline(pts, eps_list, target_s):
+    """The brute-force oracle on a bounded sample of query rows (all n
+    candidates each), on the host's cores, scaled to pairs/s."""
+    from oracle import reference
+    n = pts.shape[0]
+    g = np.random.default_rng(12345)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    pilot_rows = g.choice(n, size=min(n, 256), replace=False)
+    t0 = time.perf_counter()
+    reference.count_rows(pts, max(eps_list), pilot_rows)
+    per_row = (time.perf_counter() - t0) / len(pilot_rows)
+    rows_per_eps = int(max(64, min(n, target_s / (per_row * len(eps_list)))))
+    rows = g.choice(n, size=rows_per_eps, replace=False)
+    pairs = 0
+    t0 = time.perf_counter()
+    for e in eps_list:
+        pairs += int(reference.count_rows(pts, e, rows).sum())
+    dt = time.perf_counter() - t0
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"{rows_per_eps} random query rows x all {n} candidates for each of "
+                      f"{len(eps_list)} eps ({pairs} pairs in {dt:.1f} s); "
+                      f"rate = sample pairs / sample time"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the self-join path here is single-GPU)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    import paper_1803_04120_amd as sj
+    from paper_1803_04120_amd import _lib, datagen
+
+    wl = WORKLOADS[args.workload]
+    n, d = wl["n"], wl["d"]
+    eps_list = list(wl["eps"])
+    pts = datagen.make(wl["kind"], n, d, wl["seed"])
+    x = torch.from_numpy(pts).to("cuda")
+    stream = torch.cuda.current_stream()
+
+    # sizes per eps (also warms the library's memory pool)
+    info = []
+    for e in eps_list:
+        with sj.Index(x, e) as ix:
+            P = ix.count(unicomp=bool(args.unicomp), precision=args.precision)
+            st = ix.stats()
+            info.append(dict(eps=e, pairs=P, cells=st["cells"], ranges=st["ranges"],
+                             evals=st["evals"], band_rechecks=st["band_rechecks"],
+                             max_cell=st["max_cell_points"], key_bits=st["key_bits"]))
+    maxP = max(i["pairs"] for i in info)
+    out = torch.empty((maxP, 2), dtype=torch.int32, device="cuda")
+
+    def step():
+        total = 0
+        for e in eps_list:
+            with sj.Index(x, e) as ix:
+                P = ix.count(unicomp=bool(args.unicomp), precision=args.precision)
+                ix.fill(out)
+                total += P
+        return total
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    _lib.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pairs_total = 0
+    for _ in range(args.steps):
+        pairs_total += step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _lib.profile_enable(False)
+    prof = _lib.profile_read()
+    ms_per_step = 1e3 * dt / args.steps
+    value = pairs_total / dt
+    log(f"[bench] {args.steps} steps in {dt:.3f}s, {ms_per_step:.3f} ms/step, {value:.4g} pairs/s")
+    for k, (cnt, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+        log(f"[bench]   {k:28s} launches={cnt:6d} total={ms:9.3f} ms avg={1e3 * ms / cnt:9.2f} us")
+
+    # roofline of the dominant kernel (largest total time among modelled ones)
+    modelled = {}
+    for name, (cnt, ms) in prof.items():
+        per_step = [kernel_bytes(name, n, d, i["cells"], i["ranges"], i["pairs"]) for i in info]
+        if None in per_step:
+            continue
+        modelled[name] = (cnt, ms, sum(per_step) * args.steps)
+    dom = max(modelled, key=lambda k: modelled[k][1])
+    cnt, ms, byts = modelled[dom]
+    achieved = byts / (ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(1e3 * ms / cnt, 3),
+                "bytes_per_launch": int(byts / cnt)}
+    pipe = sum(pipeline_bytes(n, d, i["cells"], i["pairs"]) for i in info)
+    pipeline = {"alg_bytes_per_step": pipe, "achieved_GBs": round(pipe / (ms_per_step * 1e-3) / 1e9, 2),
+                "frac_of_hbm_peak": round(pipe / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    batched = None
+    if not args.no_batched:
+        cap = args.batch_capacity
+        t0 = time.perf_counter()
+        nb = []
+        tot = 0
+        for e in eps_list:
+            with sj.Index(x, e) as ix:
+                batches = []
+                tot += ix.batches(lambda p, np_, b, r0, r1: batches.append(np_),
+                                  unicomp=bool(args.unicomp), precision=args.precision,
+                                  batch_capacity_pairs=cap, min_batches=1)
+                nb.append(len(batches))
+        torch.cuda.synchronize()
+        bdt = time.perf_counter() - t0
+        batched = {"capacity_pairs": cap, "batches_per_eps": nb, "pairs_per_s": tot / bdt,
+                   "note": "one untimed-by-events pass, batches delivered in device memory"}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(pts, eps_list, args.cpu_seconds)
+        log(f"[bench] cpu oracle baseline {cpu['value']:.4g} pairs/s on {cpu['cores']} threads")
+
+    rec = {
+        "metric": "self-join neighbor pairs/s",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "distribution": wl["kind"], "n": n, "d": d,
+                   "eps": eps_list, "unicomp": bool(args.unicomp), "precision": args.precision,
+                   "output": "sorted (i,j) pairs in HBM"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "pipeline_hbm": pipeline,
+        "per_eps": info,
+        "batched": batched,
+        "kernels_ms": {k: round(v[1] / args.steps, 4) for k, v in prof.items()},
+    }
+    del stream
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -193,6 +193,20 @@ int sj_index_search(sj_index *idx, int unicomp, void *stream);
  */
 int sj_band_thresholds(uint32_t d, double eps, double extent, float *lo, float *hi);
 
+/*
+ * Per-kernel timing with HIP events recorded on the stream each kernel is
+ * launched on (off by default; enabling resets the totals). Records are
+ * {char name[48]; uint64_t launches; double total_ms;}; *count receives the
+ * number of kernels seen (records beyond cap are not written).
+ */
+typedef struct sj_kernel_time {
+    char     name[48];
+    uint64_t launches;
+    double   total_ms;
+} sj_kernel_time;
+int sj_profile_enable(int on);
+int sj_profile_read(sj_kernel_time *out, uint32_t cap, uint32_t *count);
+
 /* Thread-local description of the last failure ("" if none). */
 const char *sj_last_error(void);
 

@@ -65,6 +65,12 @@ class SjStats(ctypes.Structure):
                 ("ms_fill", ctypes.c_double)]
 
 
+class SjKernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48),
+                ("launches", ctypes.c_uint64),
+                ("total_ms", ctypes.c_double)]
+
+
 RUN_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                           ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64)
 
@@ -108,6 +114,9 @@ def load():
         "sj_index_search": (ctypes.c_int, [vp, ctypes.c_int, vp]),
         "sj_band_thresholds": (ctypes.c_int, [u32, dbl, dbl, ctypes.POINTER(ctypes.c_float),
                                               ctypes.POINTER(ctypes.c_float)]),
+        "sj_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+        "sj_profile_read": (ctypes.c_int, [ctypes.POINTER(SjKernelTime), u32,
+                                           ctypes.POINTER(ctypes.c_uint32)]),
         "sj_last_error": (ctypes.c_char_p, []),
         "sj_version": (ctypes.c_char_p, []),
     }
@@ -151,3 +160,18 @@ def stats_dict(st: SjStats) -> dict:
             v = [int(x) for x in v][: st.d]
         out[name] = v
     return out
+
+
+def profile_enable(on: bool = True):
+    load().sj_profile_enable(1 if on else 0)
+
+
+def profile_read() -> dict:
+    """{kernel name: (launches, total_ms)} recorded since profile_enable."""
+    L = load()
+    cnt = ctypes.c_uint32(0)
+    L.sj_profile_read(None, 0, ctypes.byref(cnt))
+    recs = (SjKernelTime * max(1, cnt.value))()
+    L.sj_profile_read(recs, cnt.value, ctypes.byref(cnt))
+    return {recs[i].name.decode(): (int(recs[i].launches), float(recs[i].total_ms))
+            for i in range(cnt.value)}

@@ -230,8 +230,11 @@ void launch_make_f32(const double *X, uint64_t n, uint32_t d, const double *shif
                      hipStream_t s) {
     GridParams g{};
     for (uint32_t j = 0; j < d && j < static_cast<uint32_t>(kMaxDim); ++j) g.gmin[j] = shift[j];
-    k_make_f32<<<blocks_for(n), kThreads, 0, s>>>(X, n, d, g, Y);
-    SJ_LAUNCH_CHECK();
+    {
+        KTimer kt_("make_f32", s);
+        k_make_f32<<<blocks_for(n), kThreads, 0, s>>>(X, n, d, g, Y);
+        SJ_LAUNCH_CHECK();
+    }
 }
 
 void launch_bbox(const double *pts, uint64_t n, uint32_t d, double *bbox_out, uint32_t *bad,
@@ -240,22 +243,31 @@ void launch_bbox(const double *pts, uint64_t n, uint32_t d, double *bbox_out, ui
     DevBuf<double> part(static_cast<size_t>(nb) * 2 * kMaxDim);
     k_zero_u32<<<1, 64, 0, s>>>(bad, 1);
     SJ_LAUNCH_CHECK();
-    k_bbox_partial<<<nb, kThreads, 0, s>>>(pts, n, d, part.ptr, bad);
-    SJ_LAUNCH_CHECK();
+    {
+        KTimer kt_("bbox", s);
+        k_bbox_partial<<<nb, kThreads, 0, s>>>(pts, n, d, part.ptr, bad);
+        SJ_LAUNCH_CHECK();
+    }
     k_bbox_final<<<1, 64, 0, s>>>(part.ptr, nb, bbox_out);
     SJ_LAUNCH_CHECK();
 }
 
 void launch_cell_keys_u64(const double *pts, uint64_t n, const GridParams &g, uint64_t *keys,
                           uint32_t *ids, hipStream_t s) {
-    k_cell_keys<uint64_t><<<blocks_for(n), kThreads, 0, s>>>(pts, n, g, keys, ids);
-    SJ_LAUNCH_CHECK();
+    {
+        KTimer kt_("cell_keys", s);
+        k_cell_keys<uint64_t><<<blocks_for(n), kThreads, 0, s>>>(pts, n, g, keys, ids);
+        SJ_LAUNCH_CHECK();
+    }
 }
 
 void launch_cell_keys_u32(const double *pts, uint64_t n, const GridParams &g, uint32_t *keys,
                           uint32_t *ids, hipStream_t s) {
-    k_cell_keys<uint32_t><<<blocks_for(n), kThreads, 0, s>>>(pts, n, g, keys, ids);
-    SJ_LAUNCH_CHECK();
+    {
+        KTimer kt_("cell_keys", s);
+        k_cell_keys<uint32_t><<<blocks_for(n), kThreads, 0, s>>>(pts, n, g, keys, ids);
+        SJ_LAUNCH_CHECK();
+    }
 }
 
 template <typename K>
@@ -266,8 +278,11 @@ uint64_t build_cells(const K *sorted_keys, uint64_t n, uint32_t *cell_of, uint64
     scan_inclusive_u32(cell_of, n, s);
     uint32_t ncells = 0;
     SJ_HIP(hipMemcpyAsync(&ncells, cell_of + (n - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    k_cell_tables<K><<<blocks_for(n), kThreads, 0, s>>>(sorted_keys, n, cell_of, B, starts);
-    SJ_LAUNCH_CHECK();
+    {
+        KTimer kt_("cell_tables", s);
+        k_cell_tables<K><<<blocks_for(n), kThreads, 0, s>>>(sorted_keys, n, cell_of, B, starts);
+        SJ_LAUNCH_CHECK();
+    }
     SJ_HIP(hipStreamSynchronize(s));
     return ncells;
 }
@@ -288,9 +303,12 @@ uint32_t launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uin
     k_zero_u32<<<1, 64, 0, s>>>(mp.ptr, 1);
     SJ_LAUNCH_CHECK();
     const unsigned nb = static_cast<unsigned>(std::min<uint64_t>(2048, (ncells + kThreads - 1) / kThreads));
-    k_cell_coords<<<nb, kThreads, 0, s>>>(B, starts, ncells, g, coords, masks, mask_off, mask_words,
-                                         mp.ptr);
-    SJ_LAUNCH_CHECK();
+    {
+        KTimer kt_("cell_coords_masks", s);
+        k_cell_coords<<<nb, kThreads, 0, s>>>(B, starts, ncells, g, coords, masks, mask_off, mask_words,
+                                             mp.ptr);
+        SJ_LAUNCH_CHECK();
+    }
     uint32_t host = 0;
     SJ_HIP(hipMemcpyAsync(&host, mp.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
@@ -299,8 +317,11 @@ uint32_t launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uin
 
 void launch_gather_soa(const double *pts, const uint32_t *perm, uint64_t n, uint32_t d, double *X,
                        hipStream_t s) {
-    k_gather_soa<<<blocks_for(n), kThreads, 0, s>>>(pts, perm, n, d, X);
-    SJ_LAUNCH_CHECK();
+    {
+        KTimer kt_("gather_soa", s);
+        k_gather_soa<<<blocks_for(n), kThreads, 0, s>>>(pts, perm, n, d, X);
+        SJ_LAUNCH_CHECK();
+    }
 }
 
 }  // namespace sj

@@ -269,26 +269,34 @@ __global__ __launch_bounds__(kThreads) void k_join_guarded(JoinArgs a) {
     }
 }
 
+const char *const kJoinNames[8] = {"join_count_full_fp64", "join_count_full_fp32band",
+                                   "join_count_unicomp_fp64", "join_count_unicomp_fp32band",
+                                   "join_fill_full_fp64", "join_fill_full_fp32band",
+                                   "join_fill_unicomp_fp64", "join_fill_unicomp_fp32band"};
+
+template <int D, bool U, int M, bool BD>
+void launch_one(const JoinArgs &a, unsigned nb, hipStream_t s) {
+    KTimer kt_(kJoinNames[M * 4 + (U ? 2 : 0) + (BD ? 1 : 0)], s);
+    k_join_guarded<D, U, M, BD><<<nb, kThreads, 0, s>>>(a);
+    SJ_LAUNCH_CHECK();
+}
+
 template <int D>
 void launch_join_d(const JoinArgs &a, int unicomp, int mode, int band, hipStream_t s) {
     const unsigned nb = (a.nq + kThreads - 1) / kThreads;
     if (nb == 0) return;
-#define SJ_JOIN_CASE(U, M, BD)                                                   \
-    if (unicomp == U && mode == M && band == BD) {                               \
-        k_join_guarded<D, U, M, BD><<<nb, kThreads, 0, s>>>(a);                  \
-        SJ_LAUNCH_CHECK();                                                       \
-        return;                                                                  \
+    const int sel = (mode == kFill ? 4 : 0) + (unicomp ? 2 : 0) + (band ? 1 : 0);
+    switch (sel) {
+        case 0: launch_one<D, false, kCount, false>(a, nb, s); break;
+        case 1: launch_one<D, false, kCount, true>(a, nb, s); break;
+        case 2: launch_one<D, true, kCount, false>(a, nb, s); break;
+        case 3: launch_one<D, true, kCount, true>(a, nb, s); break;
+        case 4: launch_one<D, false, kFill, false>(a, nb, s); break;
+        case 5: launch_one<D, false, kFill, true>(a, nb, s); break;
+        case 6: launch_one<D, true, kFill, false>(a, nb, s); break;
+        case 7: launch_one<D, true, kFill, true>(a, nb, s); break;
+        default: throw Error(SJ_EINVAL, "join: bad mode");
     }
-    SJ_JOIN_CASE(0, kCount, 0)
-    SJ_JOIN_CASE(1, kCount, 0)
-    SJ_JOIN_CASE(0, kFill, 0)
-    SJ_JOIN_CASE(1, kFill, 0)
-    SJ_JOIN_CASE(0, kCount, 1)
-    SJ_JOIN_CASE(1, kCount, 1)
-    SJ_JOIN_CASE(0, kFill, 1)
-    SJ_JOIN_CASE(1, kFill, 1)
-#undef SJ_JOIN_CASE
-    throw Error(SJ_EINVAL, "join: bad mode");
 }
 
 // ------------------------------------------------------------ row plans
@@ -372,8 +380,11 @@ uint64_t build_ranges(const SearchArgs &a, int unicomp, uint64_t *roff, uint32_t
                       size_t *rng_cap, hipStream_t s) {
     if (a.ncells == 0) return 0;
     DevBuf<uint32_t> cnt(a.ncells);
-    k_search_count<<<blocks_for(a.ncells), kThreads, 0, s>>>(a, unicomp, cnt.ptr);
-    SJ_LAUNCH_CHECK();
+    {
+        KTimer kt_("search_count", s);
+        k_search_count<<<blocks_for(a.ncells), kThreads, 0, s>>>(a, unicomp, cnt.ptr);
+        SJ_LAUNCH_CHECK();
+    }
     scan_exclusive_u32_to_u64(cnt.ptr, roff, a.ncells, s);
     uint64_t total = 0;
     SJ_HIP(hipMemcpyAsync(&total, roff + a.ncells, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
@@ -384,9 +395,12 @@ uint64_t build_ranges(const SearchArgs &a, int unicomp, uint64_t *roff, uint32_t
         *rng_out = static_cast<uint32_t *>(dev_alloc(cap * 2 * sizeof(uint32_t)));
         *rng_cap = cap;
     }
-    k_search_fill<<<blocks_for(a.ncells), kThreads, 0, s>>>(a, unicomp, roff,
-                                                            reinterpret_cast<uint2 *>(*rng_out));
-    SJ_LAUNCH_CHECK();
+    {
+        KTimer kt_("search_fill", s);
+        k_search_fill<<<blocks_for(a.ncells), kThreads, 0, s>>>(a, unicomp, roff,
+                                                                reinterpret_cast<uint2 *>(*rng_out));
+        SJ_LAUNCH_CHECK();
+    }
     SJ_HIP(hipStreamSynchronize(s));
     return total;
 }
@@ -407,15 +421,21 @@ void launch_join(const JoinArgs &a, uint32_t d, int unicomp, int mode, int band,
 
 void launch_row_lengths(const uint32_t *own_cnt, const uint32_t *in_cnt, const uint32_t *perm,
                         uint64_t n, uint32_t *len_orig, hipStream_t s) {
-    k_row_lengths<<<blocks_for(n), kThreads, 0, s>>>(own_cnt, in_cnt, perm, n, len_orig);
-    SJ_LAUNCH_CHECK();
+    {
+        KTimer kt_("row_lengths", s);
+        k_row_lengths<<<blocks_for(n), kThreads, 0, s>>>(own_cnt, in_cnt, perm, n, len_orig);
+        SJ_LAUNCH_CHECK();
+    }
 }
 
 void launch_gather_offsets(const uint64_t *off_orig, const uint32_t *perm, uint64_t n,
                            uint64_t *offc, uint32_t *max_len, const uint32_t *len_orig,
                            hipStream_t s) {
-    k_gather_offsets<<<blocks_for(n), kThreads, 0, s>>>(off_orig, perm, n, offc, len_orig, max_len);
-    SJ_LAUNCH_CHECK();
+    {
+        KTimer kt_("row_offsets_gather", s);
+        k_gather_offsets<<<blocks_for(n), kThreads, 0, s>>>(off_orig, perm, n, offc, len_orig, max_len);
+        SJ_LAUNCH_CHECK();
+    }
 }
 
 uint32_t build_query_list(const uint32_t *perm, uint64_t n, uint64_t i0, uint64_t i1,
@@ -423,8 +443,11 @@ uint32_t build_query_list(const uint32_t *perm, uint64_t n, uint64_t i0, uint64_
     k_batch_flags<<<blocks_for(n), kThreads, 0, s>>>(perm, n, i0, i1, flags_scratch);
     SJ_LAUNCH_CHECK();
     scan_exclusive_u32(flags_scratch, flags_scratch, n, s);
-    k_batch_compact<<<blocks_for(n), kThreads, 0, s>>>(perm, n, i0, i1, flags_scratch, qlist);
-    SJ_LAUNCH_CHECK();
+    {
+        KTimer kt_("batch_query_list", s);
+        k_batch_compact<<<blocks_for(n), kThreads, 0, s>>>(perm, n, i0, i1, flags_scratch, qlist);
+        SJ_LAUNCH_CHECK();
+    }
     return static_cast<uint32_t>(i1 - i0);
 }
 

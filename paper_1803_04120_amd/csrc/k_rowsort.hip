@@ -187,11 +187,17 @@ void launch_rowsort(const uint64_t *off, uint64_t i0, uint64_t i1, uint64_t base
     const uint64_t nb = (rows + kWaves - 1) / kWaves;
     if (nb > 0x7fffffffULL) throw Error(SJ_EINVAL, "row sort: too many rows");
     uint2 *p2 = reinterpret_cast<uint2 *>(pairs);
-    k_rowsort_small<<<static_cast<unsigned>(nb), kThreads, 0, s>>>(off, i0, i1, base, out_j, p2,
-                                                                   big_list, big_count);
-    SJ_LAUNCH_CHECK();
-    k_rowsort_big<<<512, kThreads, 0, s>>>(off, i0, base, out_j, p2, big_list, big_count);
-    SJ_LAUNCH_CHECK();
+    {
+        KTimer kt_("rowsort_small", s);
+        k_rowsort_small<<<static_cast<unsigned>(nb), kThreads, 0, s>>>(off, i0, i1, base, out_j, p2,
+                                                                       big_list, big_count);
+        SJ_LAUNCH_CHECK();
+    }
+    {
+        KTimer kt_("rowsort_big", s);
+        k_rowsort_big<<<512, kThreads, 0, s>>>(off, i0, base, out_j, p2, big_list, big_count);
+        SJ_LAUNCH_CHECK();
+    }
 }
 
 }  // namespace sj

@@ -108,9 +108,12 @@ void scan_impl(const Tin *in, Tout *out, size_t n, Tout *total_out, hipStream_t 
     SJ_LAUNCH_CHECK();
     k_scan_partials<Tout><<<1, kThreads, 0, s>>>(part.ptr, nb);
     SJ_LAUNCH_CHECK();
-    k_tile_scan<Tin, Tout, kInclusive><<<static_cast<unsigned>(nb), kThreads, 0, s>>>(
-        in, out, n, part.ptr, total_out);
-    SJ_LAUNCH_CHECK();
+    {
+        KTimer kt_("scan", s);
+        k_tile_scan<Tin, Tout, kInclusive><<<static_cast<unsigned>(nb), kThreads, 0, s>>>(
+            in, out, n, part.ptr, total_out);
+        SJ_LAUNCH_CHECK();
+    }
 }
 
 }  // namespace

@@ -152,12 +152,18 @@ void radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, s
     uint32_t *src_v = vals, *dst_v = vals_alt;
     int passes = 0;
     for (int shift = 0; shift < bits; shift += 8) {
-        k_upsweep<K><<<ntiles, kThreads, 0, s>>>(src_k, n, shift, hist.ptr, ntiles);
-        SJ_LAUNCH_CHECK();
+        {
+            KTimer kt_("radix_upsweep", s);
+            k_upsweep<K><<<ntiles, kThreads, 0, s>>>(src_k, n, shift, hist.ptr, ntiles);
+            SJ_LAUNCH_CHECK();
+        }
         scan_exclusive_u32(hist.ptr, hist.ptr, hist.count, s);
-        k_downsweep<K><<<ntiles, kThreads, 0, s>>>(src_k, src_v, dst_k, dst_v, n, shift, hist.ptr,
-                                                   ntiles);
-        SJ_LAUNCH_CHECK();
+        {
+            KTimer kt_("radix_downsweep", s);
+            k_downsweep<K><<<ntiles, kThreads, 0, s>>>(src_k, src_v, dst_k, dst_v, n, shift, hist.ptr,
+                                                       ntiles);
+            SJ_LAUNCH_CHECK();
+        }
         std::swap(src_k, dst_k);
         std::swap(src_v, dst_v);
         ++passes;

@@ -804,6 +804,16 @@ int sj_index_search(sj_index *idx, int unicomp, void *stream) {
     });
 }
 
+int sj_profile_enable(int on) {
+    if (on) sj::profile_reset();
+    sj::profile_set(on != 0);
+    return SJ_OK;
+}
+
+int sj_profile_read(sj_kernel_time *out, uint32_t cap, uint32_t *count) {
+    return sj::profile_read(out, cap, count);
+}
+
 int sj_band_thresholds(uint32_t d, double eps, double extent, float *lo, float *hi) {
     if (!lo || !hi || d < 1 || d > static_cast<uint32_t>(sj::kMaxDim) || !(eps > 0) ||
         !std::isfinite(eps) || !(extent >= 0) || !std::isfinite(extent)) {

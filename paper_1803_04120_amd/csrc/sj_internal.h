@@ -61,6 +61,24 @@ struct DevBuf {
 };
 
 // ---------------------------------------------------------------------
+// Per-kernel timing with HIP events, on the stream each kernel is launched
+// on. Off unless enabled through the ABI; the events of a call are resolved
+// after the call has synchronised its stream.
+// ---------------------------------------------------------------------
+bool profiling_enabled();
+struct KTimer {
+    KTimer(const char *name, hipStream_t s);
+    ~KTimer();
+    const char *name_;
+    hipStream_t s_;
+    hipEvent_t e0_ = nullptr, e1_ = nullptr;
+};
+void profile_resolve_pending();
+void profile_reset();
+void profile_set(bool on);
+int profile_read(void *out, uint32_t cap, uint32_t *count);
+
+// ---------------------------------------------------------------------
 // Grid description (Section IV-B), passed by value to kernels.
 // ---------------------------------------------------------------------
 struct GridParams {

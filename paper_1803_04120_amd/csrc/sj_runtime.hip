@@ -1,5 +1,7 @@
 // Host runtime: error plumbing and the caching device-memory pool.
 #include <cstdio>
+#include <cstring>
+#include <string>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -121,9 +123,107 @@ void pool_trim() {
     (void)hipSetDevice(cur);
 }
 
+// ---------------------------------------------------------------------
+// Kernel timing
+// ---------------------------------------------------------------------
+namespace {
+struct ProfEntry {
+    uint64_t launches = 0;
+    double total_ms = 0.0;
+};
+std::mutex g_prof_mu;
+std::map<std::string, ProfEntry> g_prof;
+bool g_prof_on = false;
+struct PendingEvent {
+    const char *name;
+    hipEvent_t e0, e1;
+};
+thread_local std::vector<PendingEvent> t_prof_pending;
+thread_local std::vector<hipEvent_t> t_event_pool;
+
+hipEvent_t take_event() {
+    if (!t_event_pool.empty()) {
+        hipEvent_t e = t_event_pool.back();
+        t_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+bool profiling_enabled() { return g_prof_on; }
+
+KTimer::KTimer(const char *name, hipStream_t s) : name_(name), s_(s) {
+    if (!g_prof_on) return;
+    e0_ = take_event();
+    e1_ = take_event();
+    if (!e0_ || !e1_) {
+        if (e0_) t_event_pool.push_back(e0_);
+        if (e1_) t_event_pool.push_back(e1_);
+        e0_ = e1_ = nullptr;
+        return;
+    }
+    (void)hipEventRecord(e0_, s_);
+}
+
+KTimer::~KTimer() {
+    if (!e0_) return;
+    (void)hipEventRecord(e1_, s_);
+    t_prof_pending.push_back({name_, e0_, e1_});
+}
+
+void profile_resolve_pending() {
+    std::vector<PendingEvent> v;
+    v.swap(t_prof_pending);
+    for (auto &p : v) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.e1) == hipSuccess && hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            auto &e = g_prof[p.name];
+            e.launches += 1;
+            e.total_ms += ms;
+        }
+        t_event_pool.push_back(p.e0);
+        t_event_pool.push_back(p.e1);
+    }
+}
+
+void profile_reset() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.clear();
+}
+
+void profile_set(bool on) { g_prof_on = on; }
+
+// out: array of {char name[48]; uint64 launches; double total_ms} records
+int profile_read(void *out, uint32_t cap, uint32_t *count) {
+    struct Rec {
+        char name[48];
+        uint64_t launches;
+        double total_ms;
+    };
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    uint32_t k = 0;
+    for (auto &kv : g_prof) {
+        if (out && k < cap) {
+            Rec &r = static_cast<Rec *>(out)[k];
+            std::memset(r.name, 0, sizeof(r.name));
+            std::strncpy(r.name, kv.first.c_str(), sizeof(r.name) - 1);
+            r.launches = kv.second.launches;
+            r.total_ms = kv.second.total_ms;
+        }
+        ++k;
+    }
+    if (count) *count = k;
+    return 0;
+}
+
 // Called by the API guard (sj_api.hip).
 void pool_enter() { ++t_depth; }
 void pool_leave_after_sync() {
+    profile_resolve_pending();
     if (--t_depth == 0) {
         std::vector<void *> v;
         v.swap(t_pending);
