@@ -86,6 +86,7 @@ typedef struct sj_stats {
     double   ms_build;          /* wall time of sj_build_index */
     double   ms_count;          /* wall time of the last sj_join_count */
     double   ms_fill;           /* wall time of the last fill / batch loop */
+    uint64_t chunks;            /* wave work units of the grid-row tiled join (0 if unused) */
 } sj_stats;
 
 /* ---- the index (Section IV-C: B, G, A, M plus the cell-ordered points) -- */

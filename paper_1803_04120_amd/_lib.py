@@ -62,7 +62,8 @@ class SjStats(ctypes.Structure):
                 ("unicomp_used", ctypes.c_uint32),
                 ("ms_build", ctypes.c_double),
                 ("ms_count", ctypes.c_double),
-                ("ms_fill", ctypes.c_double)]
+                ("ms_fill", ctypes.c_double),
+                ("chunks", ctypes.c_uint64)]
 
 
 class SjKernelTime(ctypes.Structure):

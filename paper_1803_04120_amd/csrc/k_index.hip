@@ -74,17 +74,40 @@ __global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *__restr
     }
 }
 
-__global__ void k_bbox_final(const double *__restrict__ part, uint32_t nblocks,
-                             double *__restrict__ out) {
-    const int j = threadIdx.x;
-    if (j >= kMaxDim) return;
-    double a = INFINITY, b = -INFINITY;
-    for (uint32_t k = 0; k < nblocks; ++k) {
-        a = fmin(a, part[k * 2 * kMaxDim + j]);
-        b = fmax(b, part[k * 2 * kMaxDim + kMaxDim + j]);
+// Second stage: one workgroup reduces the per-block partials (all threads
+// stride over the partials, then a wave/LDS reduction per dimension).
+__global__ __launch_bounds__(kThreads) void k_bbox_final(const double *__restrict__ part,
+                                                          uint32_t nblocks, uint32_t d,
+                                                          double *__restrict__ out) {
+    __shared__ double smn[kThreads / 64][kMaxDim], smx[kThreads / 64][kMaxDim];
+    const int wave = threadIdx.x >> 6;
+    for (uint32_t j = 0; j < d; ++j) {
+        double a = INFINITY, b = -INFINITY;
+        for (uint32_t k = threadIdx.x; k < nblocks; k += kThreads) {
+            a = fmin(a, part[k * 2 * kMaxDim + j]);
+            b = fmax(b, part[k * 2 * kMaxDim + kMaxDim + j]);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            a = fmin(a, __shfl_xor(a, off, 64));
+            b = fmax(b, __shfl_xor(b, off, 64));
+        }
+        if (lane_id() == 0) {
+            smn[wave][j] = a;
+            smx[wave][j] = b;
+        }
     }
-    out[j] = a;
-    out[kMaxDim + j] = b;
+    __syncthreads();
+    if (threadIdx.x < d) {
+        const int j = threadIdx.x;
+        double a = smn[0][j], b = smx[0][j];
+        for (int w = 1; w < kThreads / 64; ++w) {
+            a = fmin(a, smn[w][j]);
+            b = fmax(b, smx[w][j]);
+        }
+        out[j] = a;
+        out[kMaxDim + j] = b;
+    }
 }
 
 template <typename K>
@@ -166,8 +189,14 @@ __global__ __launch_bounds__(kThreads) void k_cell_coords(const uint64_t *__rest
         mp = sz > mp ? sz : mp;
     }
     mp = wave_max(mp);
-    if (lane_id() == 0) atomicMax(max_pts, mp);
+    __shared__ uint32_t smp[kThreads / 64];
+    if (lane_id() == 0) smp[threadIdx.x >> 6] = mp;
     __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t m = smp[0];
+        for (int w = 1; w < kThreads / 64; ++w) m = smp[w] > m ? smp[w] : m;
+        atomicMax(max_pts, m);
+    }
     if (use_lds)
         for (uint32_t i = threadIdx.x; i < mask_words; i += kThreads)
             if (lmask[i]) atomicOr(&masks[i], lmask[i]);
@@ -248,7 +277,7 @@ void launch_bbox(const double *pts, uint64_t n, uint32_t d, double *bbox_out, ui
         k_bbox_partial<<<nb, kThreads, 0, s>>>(pts, n, d, part.ptr, bad);
         SJ_LAUNCH_CHECK();
     }
-    k_bbox_final<<<1, 64, 0, s>>>(part.ptr, nb, bbox_out);
+    k_bbox_final<<<1, kThreads, 0, s>>>(part.ptr, nb, d, bbox_out);
     SJ_LAUNCH_CHECK();
 }
 

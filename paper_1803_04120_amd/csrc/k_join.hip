@@ -309,19 +309,29 @@ __global__ __launch_bounds__(kThreads) void k_row_lengths(const uint32_t *__rest
     len[perm[r]] = own[r] + (inc ? inc[r] : 0u);
 }
 
+// Row offset of every cell-ordered point (gather through A) and the longest
+// row (grid-stride; one atomic per workgroup).
 __global__ __launch_bounds__(kThreads) void k_gather_offsets(const uint64_t *__restrict__ off,
                                                               const uint32_t *__restrict__ perm,
                                                               uint64_t n, uint64_t *__restrict__ offc,
                                                               const uint32_t *__restrict__ len,
                                                               uint32_t *__restrict__ max_len) {
-    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
     uint32_t m = 0;
-    if (r < n) {
+    for (uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x; r < n;
+         r += static_cast<uint64_t>(gridDim.x) * kThreads) {
         offc[r] = off[perm[r]];
-        m = len[r];
+        const uint32_t l = len[r];
+        m = l > m ? l : m;
     }
     m = wave_max(m);
-    if (lane_id() == 0 && m) atomicMax(max_len, m);
+    __shared__ uint32_t sm[kThreads / 64];
+    if (lane_id() == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t b = sm[0];
+        for (int w = 1; w < kThreads / 64; ++w) b = sm[w] > b ? sm[w] : b;
+        if (b) atomicMax(max_len, b);
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_batch_flags(const uint32_t *__restrict__ perm,
@@ -433,7 +443,8 @@ void launch_gather_offsets(const uint64_t *off_orig, const uint32_t *perm, uint6
                            hipStream_t s) {
     {
         KTimer kt_("row_offsets_gather", s);
-        k_gather_offsets<<<blocks_for(n), kThreads, 0, s>>>(off_orig, perm, n, offc, len_orig, max_len);
+        k_gather_offsets<<<static_cast<unsigned>(std::min<uint64_t>(2048, blocks_for(n))), kThreads, 0, s>>>(
+            off_orig, perm, n, offc, len_orig, max_len);
         SJ_LAUNCH_CHECK();
     }
 }

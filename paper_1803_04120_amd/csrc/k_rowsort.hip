@@ -8,11 +8,16 @@
 // (i, j) without any global sort.
 //
 // Rows are sorted by size class:
-//   <= 64     one wave, one element per lane, bitonic network over lanes
-//   <= 1024   one wave, bitonic network in the wave's LDS slot
-//   <= 16384  one workgroup, bitonic network in 64 KiB of LDS
-//   larger    one workgroup, bitonic network in global memory, using the
-//             row's own output segment (twice the row's size) as scratch
+//   <= N (16, 32 or 64, chosen from the longest row)
+//             one lane per row: the row is loaded into N registers and
+//             sorted by a fully unrolled bitonic network (static register
+//             indices, v_min/v_max only); 64 consecutive rows per wave
+//   <= 1024   one wave per row, bitonic network in the wave's LDS slot
+//   <= 16384  one workgroup per row, bitonic network in 64 KiB of LDS
+//   larger    one workgroup per row, bitonic network in global memory, using
+//             the row's own output segment (twice the row's size) as scratch
+// Rows too long for the lane kernel are queued (device-side lists) for the
+// wave and workgroup kernels, whose grids loop over the queues.
 // j values within a row are distinct, so no stability is needed.
 #include "sj_internal.h"
 #include "sj_device.h"
@@ -41,43 +46,78 @@ __device__ __forceinline__ void bitonic_pair(uint32_t q, uint32_t j, uint32_t k,
     asc = (lo & k) == 0;
 }
 
-__device__ __forceinline__ void write_pairs(uint2 *__restrict__ out, uint64_t at, uint32_t row,
-                                            uint32_t j) {
-    out[at] = make_uint2(row, j);
+template <int N>
+__device__ __forceinline__ void register_bitonic(uint32_t (&v)[N]) {
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint32_t a = v[i], b = v[l];
+                    const uint32_t mn = a < b ? a : b, mx = a < b ? b : a;
+                    if ((i & k) == 0) {
+                        v[i] = mn;
+                        v[l] = mx;
+                    } else {
+                        v[i] = mx;
+                        v[l] = mn;
+                    }
+                }
+            }
+        }
+    }
 }
 
-__global__ __launch_bounds__(kThreads) void k_rowsort_small(const uint64_t *__restrict__ off,
-                                                             uint64_t i0, uint64_t i1,
-                                                             uint64_t base,
-                                                             const uint32_t *__restrict__ out_j,
-                                                             uint2 *__restrict__ pairs,
-                                                             uint32_t *__restrict__ big_list,
-                                                             uint32_t *__restrict__ big_count) {
-    __shared__ uint32_t slot[kWaves][kWaveCap];
-    const int wave = threadIdx.x >> 6;
-    const int lane = lane_id();
-    const uint64_t row = i0 + static_cast<uint64_t>(blockIdx.x) * kWaves + wave;
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_rowsort_lane(const uint64_t *__restrict__ off,
+                                                            uint64_t i0, uint64_t i1, uint64_t base,
+                                                            const uint32_t *__restrict__ out_j,
+                                                            uint2 *__restrict__ pairs,
+                                                            uint32_t *__restrict__ lists,
+                                                            uint32_t *__restrict__ counts) {
+    const uint64_t row = i0 + blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
     if (row >= i1) return;
     const uint64_t s = off[row] - base;
     const uint32_t len = static_cast<uint32_t>(off[row + 1] - off[row]);
-    if (len <= 64) {
-        uint32_t v = lane < static_cast<int>(len) ? out_j[s + lane] : kPad;
-#pragma unroll
-        for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                const uint32_t p = __shfl_xor(v, j, 64);
-                const bool up = (lane & k) == 0;
-                const bool lower = (lane & j) == 0;
-                const uint32_t mn = v < p ? v : p, mx = v < p ? p : v;
-                v = (lower == up) ? mn : mx;
-            }
+    if (len > static_cast<uint32_t>(N)) {
+        const uint64_t rows = i1 - i0;
+        if (len <= kWaveCap) {
+            const uint32_t at = atomicAdd(&counts[0], 1u);
+            lists[at] = static_cast<uint32_t>(row - i0);
+        } else {
+            const uint32_t at = atomicAdd(&counts[1], 1u);
+            lists[rows + at] = static_cast<uint32_t>(row - i0);
         }
-        if (lane < static_cast<int>(len)) write_pairs(pairs, s + lane, static_cast<uint32_t>(row), v);
         return;
     }
-    if (len <= kWaveCap) {
-        volatile uint32_t *sh = slot[wave];
+    uint32_t v[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = static_cast<uint32_t>(k) < len ? out_j[s + k] : kPad;
+    register_bitonic<N>(v);
+    const uint32_t r32 = static_cast<uint32_t>(row);
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (static_cast<uint32_t>(k) < len) pairs[s + k] = make_uint2(r32, v[k]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_rowsort_wave(const uint64_t *__restrict__ off,
+                                                            uint64_t i0, uint64_t base,
+                                                            const uint32_t *__restrict__ out_j,
+                                                            uint2 *__restrict__ pairs,
+                                                            const uint32_t *__restrict__ list,
+                                                            const uint32_t *__restrict__ count) {
+    __shared__ uint32_t slot[kWaves][kWaveCap];
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const uint32_t nrows = *count;
+    volatile uint32_t *sh = slot[wave];
+    for (uint32_t w = blockIdx.x * kWaves + wave; w < nrows; w += gridDim.x * kWaves) {
+        const uint64_t row = i0 + list[w];
+        const uint64_t s = off[row] - base;
+        const uint32_t len = static_cast<uint32_t>(off[row + 1] - off[row]);
         const uint32_t N = next_pow2(len);
         for (uint32_t e = lane; e < N; e += 64) sh[e] = e < len ? out_j[s + e] : kPad;
         __builtin_amdgcn_wave_barrier();
@@ -96,12 +136,9 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_small(const uint64_t *__re
                 __builtin_amdgcn_wave_barrier();
             }
         }
-        for (uint32_t e = lane; e < len; e += 64) write_pairs(pairs, s + e, static_cast<uint32_t>(row), sh[e]);
-        return;
-    }
-    if (lane == 0) {
-        const uint32_t at = atomicAdd(big_count, 1u);
-        big_list[at] = static_cast<uint32_t>(row - i0);
+        const uint32_t r32 = static_cast<uint32_t>(row);
+        for (uint32_t e = lane; e < len; e += 64) pairs[s + e] = make_uint2(r32, sh[e]);
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -118,6 +155,7 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_big(const uint64_t *__rest
         const uint64_t s = off[row] - base;
         const uint32_t len = static_cast<uint32_t>(off[row + 1] - off[row]);
         const uint32_t N = next_pow2(len);
+        const uint32_t r32 = static_cast<uint32_t>(row);
         if (N <= kBlockCap) {
             for (uint32_t e = threadIdx.x; e < N; e += kThreads) sh[e] = e < len ? out_j[s + e] : kPad;
             __syncthreads();
@@ -136,8 +174,7 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_big(const uint64_t *__rest
                     __syncthreads();
                 }
             }
-            for (uint32_t e = threadIdx.x; e < len; e += kThreads)
-                write_pairs(pairs, s + e, static_cast<uint32_t>(row), sh[e]);
+            for (uint32_t e = threadIdx.x; e < len; e += kThreads) pairs[s + e] = make_uint2(r32, sh[e]);
             __syncthreads();
             continue;
         }
@@ -166,37 +203,55 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_big(const uint64_t *__rest
         for (uint32_t e = threadIdx.x; e < len; e += kThreads) out_j[s + e] = T[e];
         __threadfence();
         __syncthreads();
-        for (uint32_t e = threadIdx.x; e < len; e += kThreads)
-            write_pairs(pairs, s + e, static_cast<uint32_t>(row), out_j[s + e]);
+        for (uint32_t e = threadIdx.x; e < len; e += kThreads) pairs[s + e] = make_uint2(r32, out_j[s + e]);
         __syncthreads();
     }
 }
 
-__global__ void k_zero1(uint32_t *p) {
-    if (threadIdx.x == 0) *p = 0;
+__global__ void k_zero2(uint32_t *p) {
+    if (threadIdx.x < 2) p[threadIdx.x] = 0;
+}
+
+template <int N>
+void launch_lane(const uint64_t *off, uint64_t i0, uint64_t i1, uint64_t base, const uint32_t *out_j,
+                 uint2 *pairs, uint32_t *lists, uint32_t *counts, hipStream_t s) {
+    const uint64_t nb = (i1 - i0 + kThreads - 1) / kThreads;
+    KTimer kt_("rowsort_lane", s);
+    k_rowsort_lane<N><<<static_cast<unsigned>(nb), kThreads, 0, s>>>(off, i0, i1, base, out_j, pairs,
+                                                                    lists, counts);
+    SJ_LAUNCH_CHECK();
 }
 
 }  // namespace
 
 void launch_rowsort(const uint64_t *off, uint64_t i0, uint64_t i1, uint64_t base, uint32_t *out_j,
-                    uint32_t *pairs, uint32_t *big_list, uint32_t *big_count, hipStream_t s) {
+                    uint32_t *pairs, uint32_t *lists, uint32_t *counts, uint32_t max_len,
+                    hipStream_t s) {
     if (i1 <= i0) return;
     const uint64_t rows = i1 - i0;
-    k_zero1<<<1, 64, 0, s>>>(big_count);
+    if (rows > 0x7fffffffULL) throw Error(SJ_EINVAL, "row sort: too many rows");
+    k_zero2<<<1, 64, 0, s>>>(counts);
     SJ_LAUNCH_CHECK();
-    const uint64_t nb = (rows + kWaves - 1) / kWaves;
-    if (nb > 0x7fffffffULL) throw Error(SJ_EINVAL, "row sort: too many rows");
     uint2 *p2 = reinterpret_cast<uint2 *>(pairs);
-    {
-        KTimer kt_("rowsort_small", s);
-        k_rowsort_small<<<static_cast<unsigned>(nb), kThreads, 0, s>>>(off, i0, i1, base, out_j, p2,
-                                                                       big_list, big_count);
-        SJ_LAUNCH_CHECK();
-    }
-    {
-        KTimer kt_("rowsort_big", s);
-        k_rowsort_big<<<512, kThreads, 0, s>>>(off, i0, base, out_j, p2, big_list, big_count);
-        SJ_LAUNCH_CHECK();
+    if (max_len <= 16)
+        launch_lane<16>(off, i0, i1, base, out_j, p2, lists, counts, s);
+    else if (max_len <= 32)
+        launch_lane<32>(off, i0, i1, base, out_j, p2, lists, counts, s);
+    else
+        launch_lane<64>(off, i0, i1, base, out_j, p2, lists, counts, s);
+    if (max_len > 64) {
+        {
+            KTimer kt_("rowsort_wave", s);
+            const uint64_t want = (rows + kWaves - 1) / kWaves;
+            k_rowsort_wave<<<static_cast<unsigned>(std::min<uint64_t>(want, 8192)), kThreads, 0, s>>>(
+                off, i0, base, out_j, p2, lists, counts);
+            SJ_LAUNCH_CHECK();
+        }
+        if (max_len > kWaveCap) {
+            KTimer kt_("rowsort_big", s);
+            k_rowsort_big<<<512, kThreads, 0, s>>>(off, i0, base, out_j, p2, lists + rows, counts + 1);
+            SJ_LAUNCH_CHECK();
+        }
     }
 }
 

@@ -1,0 +1,434 @@
+// Grid-row tiled adjacent-cell search and refine (Section IV-D, Algorithm 1;
+// unicomp of Section V-B, Algorithm 2), with neighbour-cell points staged in
+// LDS.
+//
+// Work unit: one wave = one "chunk" of at most 64 consecutive query points
+// (cell order) that all lie in one grid row, i.e. share their cell
+// coordinates in dimensions 1..d-1. For such a chunk the cells adjacent to
+// any of its points are the rows whose dimension-1..d-1 coordinates differ
+// from the chunk's by at most one, restricted in dimension 0 to
+// [c0(first) - 1, c0(last) + 1]; because points are stored in cell order,
+// each of those rows is ONE contiguous point segment, found with two binary
+// searches in B. The wave stages a segment's coordinates (and the dimension-0
+// cell coordinate of every candidate) in its LDS slot, tile by tile; each
+// lane then finds, by binary search over the staged dimension-0 coordinates,
+// the window of candidates in cells c0 - 1 .. c0 + 1 of its own point and
+// evaluates exactly those -- the same candidate set as the per-point search
+// of Algorithm 1, read from LDS instead of global memory.
+//
+// unicomp: rows whose block k >= 1 is gated by an odd dimension-k coordinate
+// are the same for all points of a chunk (they share dimensions 1..d-1); in
+// the chunk's own row a point evaluates its own cell as the triangle q >= p
+// and the cells c0 - 1, c0 + 1 only if c0 is odd (block 0).
+//
+// Pair test, counters and emission are those of the per-point kernel.
+#include <type_traits>
+
+#include "sj_internal.h"
+#include "sj_device.h"
+
+namespace sj {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+template <int D>
+struct TileSize {
+    static constexpr int value = D <= 3 ? 256 : (D <= 6 ? 128 : 64);
+};
+
+__device__ __forceinline__ uint32_t lb_u64(const uint64_t *__restrict__ B, uint32_t n, uint64_t key) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (B[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// first index in s[0..n) with s[i] >= v (s ascending)
+__device__ __forceinline__ uint32_t lb_lds(const uint32_t *s, uint32_t n, uint32_t v) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool t_occupied(const TileArgs &t, uint32_t j, uint32_t c) {
+    if (!t.masks) return true;
+    return (t.masks[t.mask_off[j] + (c >> 5)] >> (c & 31u)) & 1u;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int D, bool kUni, int kMode, bool kBand>
+__global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t) {
+    constexpr int TS = TileSize<D>::value;
+    using CT = typename std::conditional<kBand, float, double>::type;
+    __shared__ CT sx_all[kWaves][TS * D];
+    __shared__ uint32_t sc_all[kWaves][TS];
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    CT *sx = sx_all[wave];
+    uint32_t *scx = sc_all[wave];
+
+    uint32_t own = 0, evals = 0, rechecks = 0;
+    const uint32_t chunk = blockIdx.x * kWaves + wave;
+    if (chunk < t.nchunks) {  // uniform across the wave
+        const uint2 ch = t.chunks[chunk];
+        const uint32_t p = ch.x + static_cast<uint32_t>(lane);
+        const bool active = p < ch.y;
+        double xp[D];
+        CT yp[D];
+        uint32_t c0p = 0;
+        uint64_t my_row = 0;
+        uint32_t perm_p = 0;
+        if (active) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                xp[j] = a.X[static_cast<size_t>(j) * a.n + p];
+                if (kBand)
+                    yp[j] = static_cast<CT>(a.Y[static_cast<size_t>(j) * a.n + p]);
+                else
+                    yp[j] = static_cast<CT>(xp[j]);
+            }
+            c0p = t.cx[p];
+            if (kMode == kFill) {
+                my_row = a.offc[p] - a.out_base;
+                perm_p = a.perm[p];
+            }
+        }
+        // chunk geometry (uniform)
+        const uint32_t h_first = a.cell_of[ch.x];
+        const uint32_t h_last = a.cell_of[ch.y - 1];
+        uint32_t c[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) c[j] = t.coords[static_cast<size_t>(h_first) * D + j];
+        const uint32_t a0 = c[0];
+        const uint32_t b0 = t.coords[static_cast<size_t>(h_last) * D];
+        const uint32_t lo0 = a0 > 0 ? a0 - 1 : 0;
+        const uint32_t hi0 = b0 + 1 < t.dims[0] ? b0 + 1 : static_cast<uint32_t>(t.dims[0] - 1);
+
+        auto test = [&](uint32_t i, uint32_t q) -> bool {
+            if (kBand) {
+                float s = 0.0f;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const float d0 = __fsub_rn(static_cast<float>(yp[j]), static_cast<float>(sx[i * D + j]));
+                    s = __fadd_rn(s, __fmul_rn(d0, d0));
+                }
+                if (s < a.lo) return true;
+                if (s > a.hi) return false;
+                ++rechecks;
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const double d0 = __dsub_rn(xp[j], a.X[static_cast<size_t>(j) * a.n + q]);
+                    acc = __dadd_rn(acc, __dmul_rn(d0, d0));
+                }
+                return acc <= a.eps2;
+            } else {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const double d0 = __dsub_rn(xp[j], static_cast<double>(sx[i * D + j]));
+                    acc = __dadd_rn(acc, __dmul_rn(d0, d0));
+                }
+                return acc <= a.eps2;
+            }
+        };
+        auto emit = [&](uint32_t q, bool mirror) {
+            if (kMode == kCount) {
+                ++own;
+                if (mirror) atomicAdd(&a.in_cnt[q], 1u);
+            } else {
+                const uint64_t at = my_row + own;
+                if (at < a.out_cap)
+                    a.out_j[at] = a.perm[q];
+                else
+                    atomicOr(a.overflow, 1u);
+                ++own;
+                if (mirror) {
+                    const uint32_t slot = atomicAdd(&a.cur[q], 1u);
+                    const uint64_t at2 = a.offc[q] - a.out_base + a.own_cnt[q] + slot;
+                    if (at2 < a.out_cap)
+                        a.out_j[at2] = perm_p;
+                    else
+                        atomicOr(a.overflow, 1u);
+                }
+            }
+        };
+        // one candidate row: dims 1..d-1 fixed (their id contribution `base`)
+        auto process_row = [&](uint64_t base, bool own_row) {
+            const uint32_t g_lo = lb_u64(t.B, t.ncells, base + lo0);
+            const uint32_t g_hi = lb_u64(t.B, t.ncells, base + hi0 + 1);
+            if (g_lo >= g_hi) return;
+            const uint32_t P0 = a.starts[g_lo], P1 = a.starts[g_hi];
+            for (uint32_t T0 = P0; T0 < P1; T0 += TS) {
+                const uint32_t len = (P1 - T0) < static_cast<uint32_t>(TS) ? (P1 - T0) : TS;
+                wave_sync_lds();
+                for (uint32_t i = lane; i < len; i += 64) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        if (kBand)
+                            sx[i * D + j] = static_cast<CT>(a.Y[static_cast<size_t>(j) * a.n + T0 + i]);
+                        else
+                            sx[i * D + j] = static_cast<CT>(a.X[static_cast<size_t>(j) * a.n + T0 + i]);
+                    }
+                    scx[i] = t.cx[T0 + i];
+                }
+                wave_sync_lds();
+                if (!active) continue;
+                uint32_t lo_c = c0p > 0 ? c0p - 1 : 0, hi_c = c0p + 1;
+                if (kUni && own_row && !(c0p & 1u)) lo_c = hi_c = c0p;
+                if (scx[0] > hi_c || scx[len - 1] < lo_c) continue;
+                const uint32_t i_lo = lb_lds(scx, len, lo_c);
+                const uint32_t i_hi = lb_lds(scx, len, hi_c + 1);
+                for (uint32_t i = i_lo; i < i_hi; ++i) {
+                    const uint32_t q = T0 + i;
+                    if (kUni && own_row && q < p && scx[i] == c0p) continue;
+                    ++evals;
+                    if (test(i, q)) emit(q, kUni && q != p);
+                }
+            }
+        };
+
+        if (!kUni) {
+            // all 3^(d-1) rows of dims 1..d-1 within one step
+            uint32_t lo[D], hi[D], off[D];
+#pragma unroll
+            for (int j = 1; j < D; ++j) {
+                lo[j] = c[j] > 0 ? c[j] - 1 : 0;
+                hi[j] = c[j] + 1 < t.dims[j] ? c[j] + 1 : static_cast<uint32_t>(t.dims[j] - 1);
+                off[j] = lo[j];
+            }
+            while (true) {
+                bool ok = true, own_row = true;
+                uint64_t base = 0;
+#pragma unroll
+                for (int j = 1; j < D; ++j) {
+                    ok = ok && t_occupied(t, j, off[j]);
+                    own_row = own_row && off[j] == c[j];
+                    base += off[j] * t.stride[j];
+                }
+                if (ok) process_row(base, own_row);
+                int j = 1;
+                while (j < D) {
+                    if (off[j] < hi[j]) {
+                        ++off[j];
+                        break;
+                    }
+                    off[j] = lo[j];
+                    ++j;
+                }
+                if (j >= D) break;
+            }
+        } else {
+            uint64_t own_base = 0;
+#pragma unroll
+            for (int j = 1; j < D; ++j) own_base += c[j] * t.stride[j];
+            process_row(own_base, true);
+            for (int k = 1; k < D; ++k) {
+                if (!(c[k] & 1u)) continue;
+                uint64_t upper = 0;
+                for (int j = k + 1; j < D; ++j) upper += c[j] * t.stride[j];
+                for (int side = -1; side <= 1; side += 2) {
+                    if (side < 0 && c[k] == 0) continue;
+                    if (side > 0 && c[k] + 1 >= t.dims[k]) continue;
+                    const uint32_t ck = c[k] + side;
+                    if (!t_occupied(t, k, ck)) continue;
+                    const uint64_t fixed = upper + ck * t.stride[k];
+                    uint32_t lo[D], hi[D], off[D];
+                    for (int j = 1; j < k; ++j) {
+                        lo[j] = c[j] > 0 ? c[j] - 1 : 0;
+                        hi[j] = c[j] + 1 < t.dims[j] ? c[j] + 1 : static_cast<uint32_t>(t.dims[j] - 1);
+                        off[j] = lo[j];
+                    }
+                    while (true) {
+                        bool ok = true;
+                        uint64_t base = fixed;
+                        for (int j = 1; j < k; ++j) {
+                            ok = ok && t_occupied(t, j, off[j]);
+                            base += off[j] * t.stride[j];
+                        }
+                        if (ok) process_row(base, false);
+                        int j = 1;
+                        while (j < k) {
+                            if (off[j] < hi[j]) {
+                                ++off[j];
+                                break;
+                            }
+                            off[j] = lo[j];
+                            ++j;
+                        }
+                        if (j >= k) break;
+                    }
+                }
+            }
+        }
+        if (kMode == kCount && active) a.own_cnt[p] = own;
+    }
+    if (kMode == kCount) {
+        const unsigned long long ev = wave_sum<unsigned long long>(evals);
+        const unsigned long long rc = wave_sum<unsigned long long>(rechecks);
+        if (lane == 0) {
+            if (ev) atomicAdd(a.evals, ev);
+            if (kBand && rc) atomicAdd(a.band_rechecks, rc);
+        }
+    }
+}
+
+const char *const kTiledNames[8] = {"tiled_count_full_fp64", "tiled_count_full_fp32band",
+                                    "tiled_count_unicomp_fp64", "tiled_count_unicomp_fp32band",
+                                    "tiled_fill_full_fp64", "tiled_fill_full_fp32band",
+                                    "tiled_fill_unicomp_fp64", "tiled_fill_unicomp_fp32band"};
+
+template <int D, bool U, int M, bool BD>
+void launch_tiled_one(const JoinArgs &a, const TileArgs &t, hipStream_t s) {
+    const unsigned nb = (t.nchunks + kWaves - 1) / kWaves;
+    if (nb == 0) return;
+    KTimer kt_(kTiledNames[M * 4 + (U ? 2 : 0) + (BD ? 1 : 0)], s);
+    k_join_tiled<D, U, M, BD><<<nb, kThreads, 0, s>>>(a, t);
+    SJ_LAUNCH_CHECK();
+}
+
+template <int D>
+void launch_tiled_d(const JoinArgs &a, const TileArgs &t, int unicomp, int mode, int band,
+                    hipStream_t s) {
+    const int sel = (mode == kFill ? 4 : 0) + (unicomp ? 2 : 0) + (band ? 1 : 0);
+    switch (sel) {
+        case 0: launch_tiled_one<D, false, kCount, false>(a, t, s); break;
+        case 1: launch_tiled_one<D, false, kCount, true>(a, t, s); break;
+        case 2: launch_tiled_one<D, true, kCount, false>(a, t, s); break;
+        case 3: launch_tiled_one<D, true, kCount, true>(a, t, s); break;
+        case 4: launch_tiled_one<D, false, kFill, false>(a, t, s); break;
+        case 5: launch_tiled_one<D, false, kFill, true>(a, t, s); break;
+        case 6: launch_tiled_one<D, true, kFill, false>(a, t, s); break;
+        case 7: launch_tiled_one<D, true, kFill, true>(a, t, s); break;
+        default: throw Error(SJ_EINVAL, "tiled join: bad mode");
+    }
+}
+
+// ------------------------------------------------------------ chunk list
+__global__ __launch_bounds__(kThreads) void k_row_heads(const uint32_t *__restrict__ coords,
+                                                         uint32_t ncells, uint32_t d,
+                                                         uint32_t *__restrict__ flag) {
+    const uint32_t h = blockIdx.x * kThreads + threadIdx.x;
+    if (h >= ncells) return;
+    uint32_t f = h == 0 ? 1u : 0u;
+    if (h > 0)
+        for (uint32_t j = 1; j < d; ++j)
+            f |= coords[static_cast<size_t>(h) * d + j] != coords[static_cast<size_t>(h - 1) * d + j];
+    flag[h] = f;
+}
+
+// rows: first point of every grid row, rows[nrows] = n; chunks per row.
+__global__ __launch_bounds__(kThreads) void k_row_points(const uint32_t *__restrict__ flag,
+                                                          const uint32_t *__restrict__ row_of,
+                                                          const uint32_t *__restrict__ starts,
+                                                          uint32_t ncells, uint32_t n,
+                                                          uint32_t nrows,
+                                                          uint32_t *__restrict__ row_pt) {
+    const uint32_t h = blockIdx.x * kThreads + threadIdx.x;
+    if (h < ncells && flag[h]) row_pt[row_of[h]] = starts[h];
+    if (h == 0) row_pt[nrows] = n;
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_nchunks(const uint32_t *__restrict__ row_pt,
+                                                           uint32_t nrows, uint32_t *__restrict__ nch) {
+    const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
+    if (r >= nrows) return;
+    nch[r] = (row_pt[r + 1] - row_pt[r] + 63) / 64;
+}
+
+__global__ __launch_bounds__(kThreads) void k_emit_chunks(const uint32_t *__restrict__ row_pt,
+                                                           const uint32_t *__restrict__ ch_off,
+                                                           uint32_t nrows, uint2 *__restrict__ chunks) {
+    const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
+    if (r >= nrows) return;
+    const uint32_t s = row_pt[r], e = row_pt[r + 1];
+    uint32_t k = ch_off[r];
+    for (uint32_t q = s; q < e; q += 64, ++k) chunks[k] = make_uint2(q, q + 64 < e ? q + 64 : e);
+}
+
+__global__ __launch_bounds__(kThreads) void k_point_c0(const uint32_t *__restrict__ cell_of,
+                                                        const uint32_t *__restrict__ coords,
+                                                        uint32_t n, uint32_t d,
+                                                        uint32_t *__restrict__ cx) {
+    const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n) return;
+    cx[r] = coords[static_cast<size_t>(cell_of[r]) * d];
+}
+
+inline unsigned nblk(uint64_t n) { return static_cast<unsigned>((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, const uint32_t *cell_of,
+                      uint32_t ncells, uint32_t n, uint32_t d, uint32_t *cx, uint2 **chunks_out,
+                      size_t *chunks_cap, hipStream_t s) {
+    if (ncells == 0 || n == 0) return 0;
+    k_point_c0<<<nblk(n), kThreads, 0, s>>>(cell_of, coords, n, d, cx);
+    SJ_LAUNCH_CHECK();
+    DevBuf<uint32_t> flag(ncells), row_of(ncells);
+    k_row_heads<<<nblk(ncells), kThreads, 0, s>>>(coords, ncells, d, flag.ptr);
+    SJ_LAUNCH_CHECK();
+    DevBuf<uint64_t> row64(static_cast<size_t>(ncells) + 1);
+    scan_exclusive_u32_to_u64(flag.ptr, row64.ptr, ncells, s);
+    uint64_t nrows64 = 0;
+    SJ_HIP(hipMemcpyAsync(&nrows64, row64.ptr + ncells, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    scan_exclusive_u32(flag.ptr, row_of.ptr, ncells, s);
+    SJ_HIP(hipStreamSynchronize(s));
+    const uint32_t nrows = static_cast<uint32_t>(nrows64);
+    DevBuf<uint32_t> row_pt(static_cast<size_t>(nrows) + 1), nch(nrows);
+    k_row_points<<<nblk(ncells), kThreads, 0, s>>>(flag.ptr, row_of.ptr, starts, ncells, n, nrows,
+                                                   row_pt.ptr);
+    SJ_LAUNCH_CHECK();
+    k_row_nchunks<<<nblk(nrows), kThreads, 0, s>>>(row_pt.ptr, nrows, nch.ptr);
+    SJ_LAUNCH_CHECK();
+    DevBuf<uint64_t> choff64(static_cast<size_t>(nrows) + 1);
+    scan_exclusive_u32_to_u64(nch.ptr, choff64.ptr, nrows, s);
+    uint64_t total = 0;
+    SJ_HIP(hipMemcpyAsync(&total, choff64.ptr + nrows, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    DevBuf<uint32_t> choff(nrows);
+    scan_exclusive_u32(nch.ptr, choff.ptr, nrows, s);
+    SJ_HIP(hipStreamSynchronize(s));
+    if (total > *chunks_cap) {
+        if (*chunks_out) dev_free(*chunks_out);
+        *chunks_out = static_cast<uint2 *>(dev_alloc(total * sizeof(uint2)));
+        *chunks_cap = total;
+    }
+    k_emit_chunks<<<nblk(nrows), kThreads, 0, s>>>(row_pt.ptr, choff.ptr, nrows, *chunks_out);
+    SJ_LAUNCH_CHECK();
+    return static_cast<uint32_t>(total);
+}
+
+void launch_join_tiled(const JoinArgs &a, const TileArgs &t, uint32_t d, int unicomp, int mode,
+                       int band, hipStream_t s) {
+    switch (d) {
+        case 1: launch_tiled_d<1>(a, t, unicomp, mode, band, s); break;
+        case 2: launch_tiled_d<2>(a, t, unicomp, mode, band, s); break;
+        case 3: launch_tiled_d<3>(a, t, unicomp, mode, band, s); break;
+        case 4: launch_tiled_d<4>(a, t, unicomp, mode, band, s); break;
+        case 5: launch_tiled_d<5>(a, t, unicomp, mode, band, s); break;
+        case 6: launch_tiled_d<6>(a, t, unicomp, mode, band, s); break;
+        case 7: launch_tiled_d<7>(a, t, unicomp, mode, band, s); break;
+        case 8: launch_tiled_d<8>(a, t, unicomp, mode, band, s); break;
+        default: throw Error(SJ_EINVAL, "tiled join: d out of range");
+    }
+}
+
+}  // namespace sj

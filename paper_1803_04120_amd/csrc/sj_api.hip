@@ -4,6 +4,7 @@
 // and only then hands the call's temporaries back to the memory pool.
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <map>
@@ -129,6 +130,12 @@ struct sj_index {
         uint64_t count = 0;
     } ranges[2];
     int last_ranges = -1;
+    // grid-row chunks of the tiled join
+    DevBuf<uint32_t> cx;
+    uint2 *chunks = nullptr;
+    size_t chunks_cap = 0;
+    uint32_t nchunks = 0;
+    bool chunks_ready = false;
     // join state
     bool counted = false;
     sj_join_opts opts{};
@@ -146,6 +153,7 @@ struct sj_index {
     ~sj_index() {
         for (auto &r : ranges)
             if (r.rng) sj::dev_free(r.rng);
+        if (chunks) sj::dev_free(chunks);
     }
 };
 
@@ -308,6 +316,40 @@ void ensure_ranges(sj_index &ix, int unicomp, hipStream_t s) {
     R.ready = true;
 }
 
+// Which refine kernel runs whole-result passes: the grid-row tiled kernel
+// (default) or the per-point range kernel (SJ_JOIN_KERNEL=ranges).
+bool use_tiled() {
+    const char *e = std::getenv("SJ_JOIN_KERNEL");
+    return !(e && std::strcmp(e, "ranges") == 0);
+}
+
+void ensure_chunks(sj_index &ix, hipStream_t s) {
+    if (ix.chunks_ready) return;
+    ix.cx.ensure(ix.n);
+    ix.nchunks = sj::build_chunks(ix.coords.ptr, ix.starts.ptr, ix.cell_of.ptr,
+                                  static_cast<uint32_t>(ix.ncells), static_cast<uint32_t>(ix.n), ix.d,
+                                  ix.cx.ptr, &ix.chunks, &ix.chunks_cap, s);
+    ix.chunks_ready = true;
+    ix.stats.chunks = ix.nchunks;
+}
+
+sj::TileArgs tile_args(sj_index &ix) {
+    sj::TileArgs t{};
+    t.B = ix.B.ptr;
+    t.ncells = static_cast<uint32_t>(ix.ncells);
+    t.coords = ix.coords.ptr;
+    t.masks = ix.mask_words ? ix.masks.ptr : nullptr;
+    for (uint32_t j = 0; j < ix.d; ++j) {
+        t.mask_off[j] = ix.mask_off[j];
+        t.dims[j] = ix.grid.dims[j];
+        t.stride[j] = ix.grid.stride[j];
+    }
+    t.cx = ix.cx.ptr;
+    t.chunks = ix.chunks;
+    t.nchunks = ix.nchunks;
+    return t;
+}
+
 void ensure_f32(sj_index &ix, hipStream_t s) {
     if (ix.y_ready) return;
     ix.Y.reset(ix.n * ix.d);
@@ -359,7 +401,11 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
         return;
     }
     const int uni = o.unicomp ? 1 : 0;
-    ensure_ranges(ix, uni, s);
+    const bool tiled = use_tiled();
+    if (tiled)
+        ensure_chunks(ix, s);
+    else
+        ensure_ranges(ix, uni, s);
     if (ix.band_used) ensure_f32(ix, s);
     const uint64_t n = ix.n;
     ix.own_cnt.ensure(n);
@@ -373,7 +419,10 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     sj::launch_fill_u64(reinterpret_cast<uint64_t *>(ix.counters.ptr), 2, 0ull, s);
     sj::launch_fill_u32(ix.max_len.ptr, 1, 0u, s);
     sj::JoinArgs a = base_args(ix, uni);
-    sj::launch_join(a, ix.d, uni, sj::kCount, ix.band_used, s);
+    if (tiled)
+        sj::launch_join_tiled(a, tile_args(ix), ix.d, uni, sj::kCount, ix.band_used, s);
+    else
+        sj::launch_join(a, ix.d, uni, sj::kCount, ix.band_used, s);
     sj::launch_row_lengths(ix.own_cnt.ptr, uni ? ix.in_cnt.ptr : nullptr, ix.perm.ptr, n,
                            ix.len_orig.ptr, s);
     sj::scan_exclusive_u32_to_u64(ix.len_orig.ptr, ix.off_orig.ptr, n, s);
@@ -388,7 +437,7 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     ix.stats.band_rechecks = cnt[1];
     ix.stats.pairs = ix.pairs;
     ix.stats.max_row_pairs = ix.max_row;
-    ix.stats.ranges = ix.ranges[uni].count;
+    ix.stats.ranges = tiled ? 0 : ix.ranges[uni].count;
     ix.counted = true;
     ix.stats.ms_count = now_ms() - t0;
 }
@@ -412,8 +461,13 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
                bool unicomp_fill, uint32_t *out_j, uint32_t *pairs, Scratch &sc, hipStream_t s) {
     const uint64_t n = ix.n;
     const int mode = unicomp_fill ? 1 : 0;
-    ensure_ranges(ix, mode, s);
-    sj::JoinArgs a = base_args(ix, mode);
+    const bool whole = (i0 == 0 && i1 == n);
+    const bool tiled = whole && use_tiled();
+    if (tiled)
+        ensure_chunks(ix, s);
+    else
+        ensure_ranges(ix, mode, s);
+    sj::JoinArgs a = base_args(ix, tiled ? 0 : mode);
     a.out_j = out_j;
     a.out_base = base;
     a.out_cap = cap;
@@ -423,9 +477,13 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
         ix.cur.ensure(n);
         sj::launch_fill_u32(ix.cur.ptr, n, 0u, s);
         a.cur = ix.cur.ptr;
+    }
+    if (tiled) {
+        sj::launch_join_tiled(a, tile_args(ix), ix.d, mode, sj::kFill, ix.band_used, s);
+    } else if (unicomp_fill) {
         sj::launch_join(a, ix.d, 1, sj::kFill, ix.band_used, s);
     } else {
-        if (i0 == 0 && i1 == n) {
+        if (whole) {
             a.qlist = nullptr;
             a.nq = static_cast<uint32_t>(n);
         } else {
@@ -436,10 +494,10 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
         }
         sj::launch_join(a, ix.d, 0, sj::kFill, ix.band_used, s);
     }
-    sc.big_list.ensure(std::max<uint64_t>(1, i1 - i0));
-    sc.big_count.ensure(1);
+    sc.big_list.ensure(2 * std::max<uint64_t>(1, i1 - i0));
+    sc.big_count.ensure(2);
     sj::launch_rowsort(ix.off_orig.ptr, i0, i1, base, out_j, pairs, sc.big_list.ptr,
-                       sc.big_count.ptr, s);
+                       sc.big_count.ptr, ix.max_row, s);
 }
 
 void join_fill_all(sj_index &ix, uint32_t *pairs_dev, hipStream_t s) {

@@ -184,6 +184,27 @@ struct JoinArgs {
 enum JoinMode { kCount = 0, kFill = 1 };
 void launch_join(const JoinArgs &a, uint32_t d, int unicomp, int mode, int band, hipStream_t s);
 
+// Grid-row tiled join (k_tile.hip): chunks of <= 64 cell-ordered points of
+// one grid row, candidate rows staged in LDS.
+struct TileArgs {
+    const uint64_t *B;
+    uint32_t ncells;
+    const uint32_t *coords;
+    const uint32_t *masks;
+    uint32_t mask_off[kMaxDim];
+    uint64_t dims[kMaxDim];
+    uint64_t stride[kMaxDim];
+    const uint32_t *cx;       // dimension-0 cell coordinate of each cell-ordered point
+    const uint2 *chunks;      // [first, end) point range of each chunk
+    uint32_t nchunks;
+};
+// Builds cx and the chunk list; returns the number of chunks (host sync).
+uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, const uint32_t *cell_of,
+                      uint32_t ncells, uint32_t n, uint32_t d, uint32_t *cx, uint2 **chunks_out,
+                      size_t *chunks_cap, hipStream_t s);
+void launch_join_tiled(const JoinArgs &a, const TileArgs &t, uint32_t d, int unicomp, int mode,
+                       int band, hipStream_t s);
+
 // row lengths in original order, exclusive offsets (u64, n+1), row offsets
 // in cell order, max row length (device).
 void launch_row_lengths(const uint32_t *own_cnt, const uint32_t *in_cnt, const uint32_t *perm,
@@ -205,9 +226,10 @@ void launch_batch_bounds(const uint64_t *off, uint64_t n, uint64_t total, uint32
 // ---------------------------------------------------------------------
 // Sorts each row's neighbour ids and writes interleaved (i, j) pairs.
 // Rows [i0, i1); row i occupies [off[i] - base, off[i+1] - base) of out_j
-// and of pairs. big_list/big_count are scratch (capacity i1 - i0 rows).
+// and of pairs. lists (2 * (i1 - i0) entries) and counts (2) are scratch;
+// max_len is the longest row.
 void launch_rowsort(const uint64_t *off, uint64_t i0, uint64_t i1, uint64_t base,
-                    uint32_t *out_j, uint32_t *pairs, uint32_t *big_list, uint32_t *big_count,
-                    hipStream_t s);
+                    uint32_t *out_j, uint32_t *pairs, uint32_t *lists, uint32_t *counts,
+                    uint32_t max_len, hipStream_t s);
 
 }  // namespace sj

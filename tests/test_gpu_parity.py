@@ -77,6 +77,24 @@ def test_parity_small(sj, kind, d, n, eps, mode):
     assert_same(gpu_pairs(sj, pts, eps, **mode), want, f"{kind}-{d}d {mode}")
 
 
+@pytest.fixture(params=["tiled", "ranges"])
+def join_kernel(request, monkeypatch):
+    """Run a test with each refine kernel (grid-row tiled, per-point ranges)."""
+    monkeypatch.setenv("SJ_JOIN_KERNEL", request.param)
+    return request.param
+
+
+@pytest.mark.parametrize("kind,d,n,eps", [("uniform", 2, 30011, 0.35), ("clustered", 2, 30011, 0.2),
+                                          ("uniform", 3, 20011, 3.5), ("clustered", 3, 15013, 0.7),
+                                          ("uniform", 5, 9001, 18.0), ("uniform", 1, 4001, 0.02)])
+@pytest.mark.parametrize("mode", MODES, ids=lambda m: f"uni{int(m['unicomp'])}-{m['precision']}")
+def test_parity_both_kernels(sj, join_kernel, kind, d, n, eps, mode):
+    _say(f"{join_kernel} {kind} d={d} n={n} eps={eps} {mode}")
+    pts = datagen.make(kind, n, d, seed=2000 + d)
+    want = ref.pairs(pts, eps)
+    assert_same(gpu_pairs(sj, pts, eps, **mode), want, f"{join_kernel} {kind}-{d}d {mode}")
+
+
 # ---------------------------------------------------------------- edges
 def test_empty_and_single(sj):
     _say("empty and single point")
@@ -243,7 +261,7 @@ def test_worked_example_search(sj):
 
 @pytest.mark.parametrize("kind,d,eps", [("uniform", 2, 1.5), ("clustered", 2, 0.5),
                                         ("uniform", 3, 6.0), ("uniform", 5, 20.0)])
-def test_unicomp_evaluation_counts(sj, kind, d, eps):
+def test_unicomp_evaluation_counts(sj, join_kernel, kind, d, eps):
     """Distance evaluations: full search = the oracle's T, unicomp = (T+n)/2."""
     _say(f"evaluation counts {kind} d={d}")
     pts = datagen.make(kind, 6000, d, seed=3)
