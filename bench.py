@@ -64,14 +64,14 @@ def kernel_bytes(name, n, d, cells, ranges, pairs):
     """Algorithmic HBM bytes of one launch of a kernel (each array the
     kernel must touch, read or written once). Neighbour re-reads, atomics and
     scratch are overhead, not counted."""
-    if name.startswith("join_count"):
+    if name.startswith("join_count") or name.startswith("tiled_count"):
         # X (d doubles) + cell of each point + its row length; cell range table
         return n * (8 * d + 4 + 4) + 8 * (cells + 1) + 8 * ranges
-    if name.startswith("join_fill"):
+    if name.startswith("join_fill") or name.startswith("tiled_fill"):
         # X + cell + row offset + permutation entry per point, range table,
         # one 4-byte neighbour id per pair
         return n * (8 * d + 4 + 8 + 4) + 8 * (cells + 1) + 8 * ranges + 4 * pairs
-    if name == "rowsort_small":
+    if name in ("rowsort_small", "rowsort_lane"):
         # row offsets, neighbour ids in, (i, j) pairs out
         return 8 * (n + 1) + 4 * pairs + 8 * pairs
     return None
@@ -175,6 +175,8 @@ def main():
         if None in per_step:
             continue
         modelled[name] = (cnt, ms, sum(per_step) * args.steps)
+    if not modelled:
+        raise RuntimeError(f"no modelled kernel among {sorted(prof)}")
     dom = max(modelled, key=lambda k: modelled[k][1])
     cnt, ms, byts = modelled[dom]
     achieved = byts / (ms * 1e-3) / 1e9

@@ -113,14 +113,9 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         }
         // chunk geometry (uniform)
         const uint32_t h_first = a.cell_of[ch.x];
-        const uint32_t h_last = a.cell_of[ch.y - 1];
         uint32_t c[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) c[j] = t.coords[static_cast<size_t>(h_first) * D + j];
-        const uint32_t a0 = c[0];
-        const uint32_t b0 = t.coords[static_cast<size_t>(h_last) * D];
-        const uint32_t lo0 = a0 > 0 ? a0 - 1 : 0;
-        const uint32_t hi0 = b0 + 1 < t.dims[0] ? b0 + 1 : static_cast<uint32_t>(t.dims[0] - 1);
 
         auto test = [&](uint32_t i, uint32_t q) -> bool {
             if (kBand) {
@@ -171,12 +166,11 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 }
             }
         };
-        // one candidate row: dims 1..d-1 fixed (their id contribution `base`)
-        auto process_row = [&](uint64_t base, bool own_row) {
-            const uint32_t g_lo = lb_u64(t.B, t.ncells, base + lo0);
-            const uint32_t g_hi = lb_u64(t.B, t.ncells, base + hi0 + 1);
-            if (g_lo >= g_hi) return;
-            const uint32_t P0 = a.starts[g_lo], P1 = a.starts[g_hi];
+        // one candidate row (precomputed point segment of the chunk's window)
+        const uint2 *segs = t.segs + static_cast<size_t>(chunk) * t.rows_per_chunk;
+        auto process_row = [&](uint32_t ridx, bool own_row) {
+            const uint2 sg = segs[ridx];
+            const uint32_t P0 = sg.x, P1 = sg.y;
             for (uint32_t T0 = P0; T0 < P1; T0 += TS) {
                 const uint32_t len = (P1 - T0) < static_cast<uint32_t>(TS) ? (P1 - T0) : TS;
                 wave_sync_lds();
@@ -205,78 +199,34 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 }
             }
         };
-
-        if (!kUni) {
-            // all 3^(d-1) rows of dims 1..d-1 within one step
-            uint32_t lo[D], hi[D], off[D];
-#pragma unroll
+        // Row index of an offset vector o (o_j in {-1,0,1}, j = 1..d-1):
+        // sum_j (o_j + 1) 3^(j-1); the own row is all zeros.
+        uint32_t own_idx = 0;
+        {
+            uint32_t p3 = 1;
             for (int j = 1; j < D; ++j) {
-                lo[j] = c[j] > 0 ? c[j] - 1 : 0;
-                hi[j] = c[j] + 1 < t.dims[j] ? c[j] + 1 : static_cast<uint32_t>(t.dims[j] - 1);
-                off[j] = lo[j];
+                own_idx += p3;
+                p3 *= 3;
             }
-            while (true) {
-                bool ok = true, own_row = true;
-                uint64_t base = 0;
-#pragma unroll
-                for (int j = 1; j < D; ++j) {
-                    ok = ok && t_occupied(t, j, off[j]);
-                    own_row = own_row && off[j] == c[j];
-                    base += off[j] * t.stride[j];
-                }
-                if (ok) process_row(base, own_row);
-                int j = 1;
-                while (j < D) {
-                    if (off[j] < hi[j]) {
-                        ++off[j];
-                        break;
-                    }
-                    off[j] = lo[j];
-                    ++j;
-                }
-                if (j >= D) break;
-            }
+        }
+        if (!kUni) {
+            for (uint32_t r = 0; r < t.rows_per_chunk; ++r) process_row(r, r == own_idx);
         } else {
-            uint64_t own_base = 0;
-#pragma unroll
-            for (int j = 1; j < D; ++j) own_base += c[j] * t.stride[j];
-            process_row(own_base, true);
+            process_row(own_idx, true);
+            // block k >= 1 (c_k odd): o_k = -1 or +1, o_j free for j < k, 0 above
+            uint32_t p3k = 1;  // 3^(k-1)
             for (int k = 1; k < D; ++k) {
-                if (!(c[k] & 1u)) continue;
-                uint64_t upper = 0;
-                for (int j = k + 1; j < D; ++j) upper += c[j] * t.stride[j];
-                for (int side = -1; side <= 1; side += 2) {
-                    if (side < 0 && c[k] == 0) continue;
-                    if (side > 0 && c[k] + 1 >= t.dims[k]) continue;
-                    const uint32_t ck = c[k] + side;
-                    if (!t_occupied(t, k, ck)) continue;
-                    const uint64_t fixed = upper + ck * t.stride[k];
-                    uint32_t lo[D], hi[D], off[D];
-                    for (int j = 1; j < k; ++j) {
-                        lo[j] = c[j] > 0 ? c[j] - 1 : 0;
-                        hi[j] = c[j] + 1 < t.dims[j] ? c[j] + 1 : static_cast<uint32_t>(t.dims[j] - 1);
-                        off[j] = lo[j];
+                if (c[k] & 1u) {
+                    uint32_t upper = 0, p3 = p3k * 3;
+                    for (int j = k + 1; j < D; ++j) {
+                        upper += p3;  // o_j = 0 contributes 1 * 3^(j-1)
+                        p3 *= 3;
                     }
-                    while (true) {
-                        bool ok = true;
-                        uint64_t base = fixed;
-                        for (int j = 1; j < k; ++j) {
-                            ok = ok && t_occupied(t, j, off[j]);
-                            base += off[j] * t.stride[j];
-                        }
-                        if (ok) process_row(base, false);
-                        int j = 1;
-                        while (j < k) {
-                            if (off[j] < hi[j]) {
-                                ++off[j];
-                                break;
-                            }
-                            off[j] = lo[j];
-                            ++j;
-                        }
-                        if (j >= k) break;
-                    }
+                    for (uint32_t side = 0; side <= 2; side += 2)
+                        for (uint32_t low = 0; low < p3k; ++low)
+                            process_row(upper + side * p3k + low, false);
                 }
+                p3k *= 3;
             }
         }
         if (kMode == kCount && active) a.own_cnt[p] = own;
@@ -364,6 +314,48 @@ __global__ __launch_bounds__(kThreads) void k_emit_chunks(const uint32_t *__rest
     for (uint32_t q = s; q < e; q += 64, ++k) chunks[k] = make_uint2(q, q + 64 < e ? q + 64 : e);
 }
 
+// Point segment of every (chunk, row) pair: the chunk's dimension-0 window
+// [c0(first) - 1, c0(last) + 1] in the row with offset vector o (index
+// sum_j (o_j + 1) 3^(j-1)); empty if the row leaves the grid or a fixed
+// coordinate is not in its occupancy mask.
+__global__ __launch_bounds__(kThreads) void k_chunk_segments(TileArgs t, const uint32_t *__restrict__ cell_of,
+                                                              const uint32_t *__restrict__ starts,
+                                                              uint32_t d, uint2 *__restrict__ segs) {
+    const uint64_t idx = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    const uint64_t total = static_cast<uint64_t>(t.nchunks) * t.rows_per_chunk;
+    if (idx >= total) return;
+    const uint32_t chunk = static_cast<uint32_t>(idx / t.rows_per_chunk);
+    uint32_t r = static_cast<uint32_t>(idx % t.rows_per_chunk);
+    const uint2 ch = t.chunks[chunk];
+    const uint32_t hf = cell_of[ch.x], hl = cell_of[ch.y - 1];
+    const uint32_t a0 = t.coords[static_cast<size_t>(hf) * d], b0 = t.coords[static_cast<size_t>(hl) * d];
+    const uint32_t lo0 = a0 > 0 ? a0 - 1 : 0;
+    const uint32_t hi0 = b0 + 1 < t.dims[0] ? b0 + 1 : static_cast<uint32_t>(t.dims[0] - 1);
+    uint64_t base = 0;
+    bool ok = true;
+    for (uint32_t j = 1; j < d; ++j) {
+        const int o = static_cast<int>(r % 3) - 1;
+        r /= 3;
+        const int64_t cj = static_cast<int64_t>(t.coords[static_cast<size_t>(hf) * d + j]) + o;
+        if (cj < 0 || cj >= static_cast<int64_t>(t.dims[j])) {
+            ok = false;
+            break;
+        }
+        if (t.masks && !((t.masks[t.mask_off[j] + (cj >> 5)] >> (cj & 31)) & 1u)) {
+            ok = false;
+            break;
+        }
+        base += static_cast<uint64_t>(cj) * t.stride[j];
+    }
+    uint2 sg = make_uint2(0, 0);
+    if (ok) {
+        const uint32_t g_lo = lb_u64(t.B, t.ncells, base + lo0);
+        const uint32_t g_hi = lb_u64(t.B, t.ncells, base + hi0 + 1);
+        if (g_lo < g_hi) sg = make_uint2(starts[g_lo], starts[g_hi]);
+    }
+    segs[idx] = sg;
+}
+
 __global__ __launch_bounds__(kThreads) void k_point_c0(const uint32_t *__restrict__ cell_of,
                                                         const uint32_t *__restrict__ coords,
                                                         uint32_t n, uint32_t d,
@@ -380,6 +372,7 @@ inline unsigned nblk(uint64_t n) { return static_cast<unsigned>((n + kThreads - 
 uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, const uint32_t *cell_of,
                       uint32_t ncells, uint32_t n, uint32_t d, uint32_t *cx, uint2 **chunks_out,
                       size_t *chunks_cap, hipStream_t s) {
+    // chunk list only; row segments come from build_chunk_segments
     if (ncells == 0 || n == 0) return 0;
     k_point_c0<<<nblk(n), kThreads, 0, s>>>(cell_of, coords, n, d, cx);
     SJ_LAUNCH_CHECK();
@@ -414,6 +407,16 @@ uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, const uint
     k_emit_chunks<<<nblk(nrows), kThreads, 0, s>>>(row_pt.ptr, choff.ptr, nrows, *chunks_out);
     SJ_LAUNCH_CHECK();
     return static_cast<uint32_t>(total);
+}
+
+void build_chunk_segments(const TileArgs &t, const uint32_t *cell_of, const uint32_t *starts,
+                          uint32_t d, uint2 *segs, hipStream_t s) {
+    const uint64_t total = static_cast<uint64_t>(t.nchunks) * t.rows_per_chunk;
+    if (!total) return;
+    KTimer kt_("chunk_segments", s);
+    k_chunk_segments<<<static_cast<unsigned>((total + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+        t, cell_of, starts, d, segs);
+    SJ_LAUNCH_CHECK();
 }
 
 void launch_join_tiled(const JoinArgs &a, const TileArgs &t, uint32_t d, int unicomp, int mode,

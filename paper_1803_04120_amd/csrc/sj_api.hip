@@ -135,6 +135,8 @@ struct sj_index {
     uint2 *chunks = nullptr;
     size_t chunks_cap = 0;
     uint32_t nchunks = 0;
+    uint32_t rows_per_chunk = 0;
+    DevBuf<uint2> segs;
     bool chunks_ready = false;
     // join state
     bool counted = false;
@@ -323,16 +325,6 @@ bool use_tiled() {
     return !(e && std::strcmp(e, "ranges") == 0);
 }
 
-void ensure_chunks(sj_index &ix, hipStream_t s) {
-    if (ix.chunks_ready) return;
-    ix.cx.ensure(ix.n);
-    ix.nchunks = sj::build_chunks(ix.coords.ptr, ix.starts.ptr, ix.cell_of.ptr,
-                                  static_cast<uint32_t>(ix.ncells), static_cast<uint32_t>(ix.n), ix.d,
-                                  ix.cx.ptr, &ix.chunks, &ix.chunks_cap, s);
-    ix.chunks_ready = true;
-    ix.stats.chunks = ix.nchunks;
-}
-
 sj::TileArgs tile_args(sj_index &ix) {
     sj::TileArgs t{};
     t.B = ix.B.ptr;
@@ -347,7 +339,24 @@ sj::TileArgs tile_args(sj_index &ix) {
     t.cx = ix.cx.ptr;
     t.chunks = ix.chunks;
     t.nchunks = ix.nchunks;
+    t.rows_per_chunk = ix.rows_per_chunk;
+    t.segs = ix.segs.ptr;
     return t;
+}
+
+void ensure_chunks(sj_index &ix, hipStream_t s) {
+    if (ix.chunks_ready) return;
+    ix.cx.ensure(ix.n);
+    ix.nchunks = sj::build_chunks(ix.coords.ptr, ix.starts.ptr, ix.cell_of.ptr,
+                                  static_cast<uint32_t>(ix.ncells), static_cast<uint32_t>(ix.n), ix.d,
+                                  ix.cx.ptr, &ix.chunks, &ix.chunks_cap, s);
+    uint32_t r3 = 1;
+    for (uint32_t j = 1; j < ix.d; ++j) r3 *= 3;
+    ix.rows_per_chunk = r3;
+    ix.segs.reset(static_cast<size_t>(ix.nchunks) * r3);
+    sj::build_chunk_segments(tile_args(ix), ix.cell_of.ptr, ix.starts.ptr, ix.d, ix.segs.ptr, s);
+    ix.chunks_ready = true;
+    ix.stats.chunks = ix.nchunks;
 }
 
 void ensure_f32(sj_index &ix, hipStream_t s) {

@@ -197,11 +197,15 @@ struct TileArgs {
     const uint32_t *cx;       // dimension-0 cell coordinate of each cell-ordered point
     const uint2 *chunks;      // [first, end) point range of each chunk
     uint32_t nchunks;
+    uint32_t rows_per_chunk;  // 3^(d-1)
+    const uint2 *segs;        // [chunk * rows_per_chunk + row] candidate point segment
 };
 // Builds cx and the chunk list; returns the number of chunks (host sync).
 uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, const uint32_t *cell_of,
                       uint32_t ncells, uint32_t n, uint32_t d, uint32_t *cx, uint2 **chunks_out,
                       size_t *chunks_cap, hipStream_t s);
+void build_chunk_segments(const TileArgs &t, const uint32_t *cell_of, const uint32_t *starts,
+                          uint32_t d, uint2 *segs, hipStream_t s);
 void launch_join_tiled(const JoinArgs &a, const TileArgs &t, uint32_t d, int unicomp, int mode,
                        int band, hipStream_t s);
 
