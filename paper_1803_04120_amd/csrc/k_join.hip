@@ -260,12 +260,8 @@ __global__ __launch_bounds__(kThreads) void k_join_guarded(JoinArgs a) {
         if (kMode == kCount) a.own_cnt[p] = own;
     }
     if (kMode == kCount) {
-        const unsigned long long ev = wave_sum<unsigned long long>(evals);
-        const unsigned long long rc = wave_sum<unsigned long long>(rechecks);
-        if (lane_id() == 0) {
-            atomicAdd(a.evals, ev);
-            if (kBand) atomicAdd(a.band_rechecks, rc);
-        }
+        add_counter(a.evals, evals);
+        if (kBand) add_counter(a.band_rechecks, rechecks);
     }
 }
 
@@ -443,7 +439,7 @@ void launch_gather_offsets(const uint64_t *off_orig, const uint32_t *perm, uint6
                            hipStream_t s) {
     {
         KTimer kt_("row_offsets_gather", s);
-        k_gather_offsets<<<static_cast<unsigned>(std::min<uint64_t>(2048, blocks_for(n))), kThreads, 0, s>>>(
+        k_gather_offsets<<<static_cast<unsigned>(std::min<uint64_t>(512, blocks_for(n))), kThreads, 0, s>>>(
             off_orig, perm, n, offc, len_orig, max_len);
         SJ_LAUNCH_CHECK();
     }

@@ -232,12 +232,8 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         if (kMode == kCount && active) a.own_cnt[p] = own;
     }
     if (kMode == kCount) {
-        const unsigned long long ev = wave_sum<unsigned long long>(evals);
-        const unsigned long long rc = wave_sum<unsigned long long>(rechecks);
-        if (lane == 0) {
-            if (ev) atomicAdd(a.evals, ev);
-            if (kBand && rc) atomicAdd(a.band_rechecks, rc);
-        }
+        add_counter(a.evals, evals);
+        if (kBand) add_counter(a.band_rechecks, rechecks);
     }
 }
 

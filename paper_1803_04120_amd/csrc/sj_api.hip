@@ -14,6 +14,7 @@
 
 #include "sj.h"
 #include "sj_internal.h"
+#include "sj_device.h"
 
 using sj::DevBuf;
 using sj::Error;
@@ -386,7 +387,7 @@ sj::JoinArgs base_args(sj_index &ix, int mode) {
     a.offc = ix.offc.ptr;
     a.perm = ix.perm.ptr;
     a.evals = ix.counters.ptr;
-    a.band_rechecks = ix.counters.ptr + 1;
+    a.band_rechecks = ix.counters.ptr + sj::kCounterSlots * sj::kCounterStride;
     return a;
 }
 
@@ -422,10 +423,11 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     ix.len_orig.ensure(n);
     ix.off_orig.ensure(n + 1);
     ix.offc.ensure(n);
-    ix.counters.ensure(2);
+    const size_t nctr = 2 * sj::kCounterSlots * sj::kCounterStride;
+    ix.counters.ensure(nctr);
     ix.max_len.ensure(1);
     if (uni) sj::launch_fill_u32(ix.in_cnt.ptr, n, 0u, s);
-    sj::launch_fill_u64(reinterpret_cast<uint64_t *>(ix.counters.ptr), 2, 0ull, s);
+    sj::launch_fill_u64(reinterpret_cast<uint64_t *>(ix.counters.ptr), nctr, 0ull, s);
     sj::launch_fill_u32(ix.max_len.ptr, 1, 0u, s);
     sj::JoinArgs a = base_args(ix, uni);
     if (tiled)
@@ -437,13 +439,17 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     sj::scan_exclusive_u32_to_u64(ix.len_orig.ptr, ix.off_orig.ptr, n, s);
     sj::launch_gather_offsets(ix.off_orig.ptr, ix.perm.ptr, n, ix.offc.ptr, ix.max_len.ptr,
                               ix.len_orig.ptr, s);
-    unsigned long long cnt[2];
+    std::vector<unsigned long long> cnt(nctr);
     SJ_HIP(hipMemcpyAsync(&ix.pairs, ix.off_orig.ptr + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipMemcpyAsync(&ix.max_row, ix.max_len.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    SJ_HIP(hipMemcpyAsync(cnt, ix.counters.ptr, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(cnt.data(), ix.counters.ptr, nctr * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
-    ix.stats.evals = cnt[0];
-    ix.stats.band_rechecks = cnt[1];
+    ix.stats.evals = ix.stats.band_rechecks = 0;
+    for (int k = 0; k < sj::kCounterSlots; ++k) {
+        ix.stats.evals += cnt[static_cast<size_t>(k) * sj::kCounterStride];
+        ix.stats.band_rechecks += cnt[(sj::kCounterSlots + static_cast<size_t>(k)) * sj::kCounterStride];
+    }
     ix.stats.pairs = ix.pairs;
     ix.stats.max_row_pairs = ix.max_row;
     ix.stats.ranges = tiled ? 0 : ix.ranges[uni].count;

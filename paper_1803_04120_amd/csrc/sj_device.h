@@ -66,4 +66,18 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *total, T *lds) {
     return before + incl - v;
 }
 
+// Counters that many workgroups add to are spread over kCounterSlots
+// addresses, one 128-byte line apart, so the additions do not serialise on a
+// single L2 line; the host sums the slots.
+constexpr int kCounterSlots = 256;
+constexpr int kCounterStride = 16;  // u64 per slot (128 bytes)
+
+// Adds a per-lane value to counter slot (block % slots): wave sum, then one
+// atomic per wave. Every lane of the wave must call it.
+__device__ __forceinline__ void add_counter(unsigned long long *slots, uint32_t v) {
+    const unsigned long long s = wave_sum<unsigned long long>(v);
+    if (lane_id() == 0 && s)
+        atomicAdd(slots + static_cast<size_t>(blockIdx.x % kCounterSlots) * kCounterStride, s);
+}
+
 }  // namespace sj
