@@ -194,6 +194,70 @@ int sj_index_search(sj_index *idx, int unicomp, void *stream);
  */
 int sj_band_thresholds(uint32_t d, double eps, double extent, float *lo, float *hi);
 
+/* ---- continuous-batching request server ------------------------------- */
+/*
+ * A server runs self-join requests as they arrive. `slots` worker threads,
+ * each with its own HIP stream, take queued requests in arrival order when
+ * the request's estimated device memory (index bytes + expected_pairs * 12)
+ * fits in what `mem_budget_bytes` has left; the first request is admitted
+ * whenever nothing else holds memory. After the count pass the exact result
+ * size replaces the estimate (waiting for memory if it grew). Requests on
+ * different slots overlap on the device. Results stay in device memory,
+ * counted against the budget, until sj_server_release.
+ *
+ * Points passed to sj_server_submit must stay valid (and unchanged) until
+ * the request completes; they may be device or host memory.
+ */
+typedef struct sj_server sj_server;
+
+#define SJ_SERVER_DRY_RUN 1  /* flags: no device work (scheduler tests without a GPU):
+                                 a request takes n/1e6 ms twice and its count pass
+                                 reports expected_pairs pairs (twice that for even ids) */
+
+typedef struct sj_server_opts {
+    uint32_t slots;             /* concurrent requests (worker threads/streams), 1..64 */
+    uint32_t flags;             /* 0 or SJ_SERVER_DRY_RUN */
+    uint64_t mem_budget_bytes;  /* soft device-memory budget for admission */
+} sj_server_opts;
+
+typedef struct sj_completion {
+    uint64_t        req_id;
+    int32_t         status;       /* SJ_OK or an SJ_E* code */
+    uint32_t        slot;         /* slot that ran the request */
+    const uint32_t *pairs_dev;    /* npairs sorted (i, j) pairs, valid until release */
+    uint64_t        npairs;
+    double          queue_ms;     /* submit -> admitted */
+    double          service_ms;   /* admitted -> result ready */
+    double          latency_ms;   /* submit -> result ready */
+    uint64_t        evals;        /* distance evaluations of the count pass */
+    uint64_t        band_rechecks;
+} sj_completion;
+
+typedef struct sj_server_info_t {
+    uint64_t queued;
+    uint64_t running;
+    uint64_t mem_used_bytes;
+    uint64_t peak_mem_bytes;
+    uint64_t over_estimate;      /* requests whose result outgrew the estimate */
+    uint64_t completed;
+} sj_server_info_t;
+
+int  sj_server_create(const sj_server_opts *opts, sj_server **out);
+/* Queues a request; *req_id identifies it. opts may be NULL (defaults);
+ * expected_pairs 0 means "about n". Never blocks on device work. */
+int  sj_server_submit(sj_server *srv, const double *pts, uint64_t n, uint32_t d, double eps,
+                      int pts_on_device, const sj_join_opts *opts, uint64_t expected_pairs,
+                      uint64_t *req_id);
+/* Up to cap completed requests (each reported once); waits up to timeout_ms
+ * (0: do not wait, < 0: wait until one completes). */
+int  sj_server_poll(sj_server *srv, sj_completion *out, uint32_t cap, uint32_t *count,
+                    int32_t timeout_ms);
+/* Frees a completed request's result and its memory reservation. */
+int  sj_server_release(sj_server *srv, uint64_t req_id);
+int  sj_server_info(sj_server *srv, sj_server_info_t *info);
+/* Drops queued requests, waits for running ones, frees everything. */
+void sj_server_destroy(sj_server *srv);
+
 /*
  * Per-kernel timing with HIP events recorded on the stream each kernel is
  * launched on (off by default; enabling resets the totals). Records are
