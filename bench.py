@@ -151,6 +151,21 @@ def main():
 
     for _ in range(args.warmup):
         step()
+    # wall time of each ABI call for one step (calls return after their device work)
+    host_ms = {"build": 0.0, "count": 0.0, "fill": 0.0, "destroy": 0.0}
+    for e in eps_list:
+        t_a = time.perf_counter()
+        ix = sj.Index(x, e)
+        t_b = time.perf_counter()
+        ix.count(unicomp=bool(args.unicomp), precision=args.precision)
+        t_c = time.perf_counter()
+        ix.fill(out)
+        t_d = time.perf_counter()
+        ix.close()
+        t_e = time.perf_counter()
+        for k, v in zip(host_ms, (t_b - t_a, t_c - t_b, t_d - t_c, t_e - t_d)):
+            host_ms[k] += 1e3 * v
+    log("[bench] per-step call wall times (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in host_ms.items()))
     torch.cuda.synchronize()
     _lib.profile_enable(True)
     torch.cuda.synchronize()
@@ -233,6 +248,7 @@ def main():
         "per_eps": info,
         "batched": batched,
         "kernels_ms": {k: round(v[1] / args.steps, 4) for k, v in prof.items()},
+        "call_wall_ms": {k: round(v, 3) for k, v in host_ms.items()},
     }
     del stream
     print(json.dumps(rec), flush=True)

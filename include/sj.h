@@ -87,6 +87,8 @@ typedef struct sj_stats {
     double   ms_count;          /* wall time of the last sj_join_count */
     double   ms_fill;           /* wall time of the last fill / batch loop */
     uint64_t chunks;            /* wave work units of the grid-row tiled join (0 if unused) */
+    uint32_t fill_unicomp;      /* 1 if the last fill evaluated the unicomp subset */
+    uint32_t reserved0;
 } sj_stats;
 
 /* ---- the index (Section IV-C: B, G, A, M plus the cell-ordered points) -- */

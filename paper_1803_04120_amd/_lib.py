@@ -63,7 +63,9 @@ class SjStats(ctypes.Structure):
                 ("ms_build", ctypes.c_double),
                 ("ms_count", ctypes.c_double),
                 ("ms_fill", ctypes.c_double),
-                ("chunks", ctypes.c_uint64)]
+                ("chunks", ctypes.c_uint64),
+                ("fill_unicomp", ctypes.c_uint32),
+                ("reserved0", ctypes.c_uint32)]
 
 
 class SjKernelTime(ctypes.Structure):

@@ -321,27 +321,23 @@ template uint64_t build_cells<uint64_t>(const uint64_t *, uint64_t, uint32_t *, 
 template uint64_t build_cells<uint32_t>(const uint32_t *, uint64_t, uint32_t *, uint64_t *,
                                         uint32_t *, hipStream_t);
 
-uint32_t launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_t ncells,
-                                  const GridParams &g, uint32_t *coords, uint32_t *masks,
-                                  const uint32_t *mask_off, uint32_t mask_words, hipStream_t s) {
-    DevBuf<uint32_t> mp(1);
+void launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_t ncells,
+                              const GridParams &g, uint32_t *coords, uint32_t *masks,
+                              const uint32_t *mask_off, uint32_t mask_words, uint32_t *max_pts,
+                              hipStream_t s) {
     if (masks) {
         k_zero_u32<<<64, 256, 0, s>>>(masks, mask_words);
         SJ_LAUNCH_CHECK();
     }
-    k_zero_u32<<<1, 64, 0, s>>>(mp.ptr, 1);
+    k_zero_u32<<<1, 64, 0, s>>>(max_pts, 1);
     SJ_LAUNCH_CHECK();
-    const unsigned nb = static_cast<unsigned>(std::min<uint64_t>(2048, (ncells + kThreads - 1) / kThreads));
+    const unsigned nb = static_cast<unsigned>(std::min<uint64_t>(256, (ncells + kThreads - 1) / kThreads));
     {
         KTimer kt_("cell_coords_masks", s);
         k_cell_coords<<<nb, kThreads, 0, s>>>(B, starts, ncells, g, coords, masks, mask_off, mask_words,
-                                             mp.ptr);
+                                             max_pts);
         SJ_LAUNCH_CHECK();
     }
-    uint32_t host = 0;
-    SJ_HIP(hipMemcpyAsync(&host, mp.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    SJ_HIP(hipStreamSynchronize(s));
-    return host;
 }
 
 void launch_gather_soa(const double *pts, const uint32_t *perm, uint64_t n, uint32_t d, double *X,

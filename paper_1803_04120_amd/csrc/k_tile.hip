@@ -78,12 +78,16 @@ template <int D, bool kUni, int kMode, bool kBand>
 __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t) {
     constexpr int TS = TileSize<D>::value;
     using CT = typename std::conditional<kBand, float, double>::type;
+    constexpr bool kAgg = (kMode == kCount) && kUni;  // mirrored counts summed in LDS
+    constexpr bool kPerm = (kMode == kFill);          // candidate ids staged in LDS
     __shared__ CT sx_all[kWaves][TS * D];
     __shared__ uint32_t sc_all[kWaves][TS];
+    __shared__ uint32_t sa_all[kWaves][(kAgg || kPerm) ? TS : 1];
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
     CT *sx = sx_all[wave];
     uint32_t *scx = sc_all[wave];
+    uint32_t *saux = sa_all[wave];
 
     uint32_t own = 0, evals = 0, rechecks = 0;
     const uint32_t chunk = blockIdx.x * kWaves + wave;
@@ -145,14 +149,14 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 return acc <= a.eps2;
             }
         };
-        auto emit = [&](uint32_t q, bool mirror) {
+        auto emit = [&](uint32_t i, uint32_t q, bool mirror) {
             if (kMode == kCount) {
                 ++own;
-                if (mirror) atomicAdd(&a.in_cnt[q], 1u);
+                if (mirror) atomicAdd(&saux[i], 1u);
             } else {
                 const uint64_t at = my_row + own;
                 if (at < a.out_cap)
-                    a.out_j[at] = a.perm[q];
+                    a.out_j[at] = saux[i];
                 else
                     atomicOr(a.overflow, 1u);
                 ++own;
@@ -164,6 +168,19 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                     else
                         atomicOr(a.overflow, 1u);
                 }
+            }
+        };
+        auto evaluate_tile = [&](uint32_t T0, uint32_t len, bool own_row) {
+            uint32_t lo_c = c0p > 0 ? c0p - 1 : 0, hi_c = c0p + 1;
+            if (kUni && own_row && !(c0p & 1u)) lo_c = hi_c = c0p;
+            if (scx[0] > hi_c || scx[len - 1] < lo_c) return;
+            const uint32_t i_lo = lb_lds(scx, len, lo_c);
+            const uint32_t i_hi = lb_lds(scx, len, hi_c + 1);
+            for (uint32_t i = i_lo; i < i_hi; ++i) {
+                const uint32_t q = T0 + i;
+                if (kUni && own_row && q < p && scx[i] == c0p) continue;
+                ++evals;
+                if (test(i, q)) emit(i, q, kUni && q != p);
             }
         };
         // one candidate row (precomputed point segment of the chunk's window)
@@ -183,19 +200,18 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                             sx[i * D + j] = static_cast<CT>(a.X[static_cast<size_t>(j) * a.n + T0 + i]);
                     }
                     scx[i] = t.cx[T0 + i];
+                    if (kAgg) saux[i] = 0;
+                    if (kPerm) saux[i] = a.perm[T0 + i];
                 }
                 wave_sync_lds();
-                if (!active) continue;
-                uint32_t lo_c = c0p > 0 ? c0p - 1 : 0, hi_c = c0p + 1;
-                if (kUni && own_row && !(c0p & 1u)) lo_c = hi_c = c0p;
-                if (scx[0] > hi_c || scx[len - 1] < lo_c) continue;
-                const uint32_t i_lo = lb_lds(scx, len, lo_c);
-                const uint32_t i_hi = lb_lds(scx, len, hi_c + 1);
-                for (uint32_t i = i_lo; i < i_hi; ++i) {
-                    const uint32_t q = T0 + i;
-                    if (kUni && own_row && q < p && scx[i] == c0p) continue;
-                    ++evals;
-                    if (test(i, q)) emit(q, kUni && q != p);
+                if (active) evaluate_tile(T0, len, own_row);
+                if (kAgg) {
+                    // one global add per candidate that collected mirrored hits
+                    wave_sync_lds();
+                    for (uint32_t i = lane; i < len; i += 64) {
+                        const uint32_t c = saux[i];
+                        if (c) atomicAdd(&a.in_cnt[T0 + i], c);
+                    }
                 }
             }
         };
@@ -281,32 +297,36 @@ __global__ __launch_bounds__(kThreads) void k_row_heads(const uint32_t *__restri
     flag[h] = f;
 }
 
-// rows: first point of every grid row, rows[nrows] = n; chunks per row.
+// First point of every grid row (row index = exclusive scan of the row-head
+// flags, total at row_of[ncells]); row_pt[nrows] = n.
 __global__ __launch_bounds__(kThreads) void k_row_points(const uint32_t *__restrict__ flag,
-                                                          const uint32_t *__restrict__ row_of,
+                                                          const uint64_t *__restrict__ row_of,
                                                           const uint32_t *__restrict__ starts,
                                                           uint32_t ncells, uint32_t n,
-                                                          uint32_t nrows,
                                                           uint32_t *__restrict__ row_pt) {
     const uint32_t h = blockIdx.x * kThreads + threadIdx.x;
     if (h < ncells && flag[h]) row_pt[row_of[h]] = starts[h];
-    if (h == 0) row_pt[nrows] = n;
+    if (h == 0) row_pt[row_of[ncells]] = n;
 }
 
+// Chunks per row (rows past the device-side row count get none).
 __global__ __launch_bounds__(kThreads) void k_row_nchunks(const uint32_t *__restrict__ row_pt,
-                                                           uint32_t nrows, uint32_t *__restrict__ nch) {
+                                                           const uint64_t *__restrict__ row_of,
+                                                           uint32_t ncells, uint32_t *__restrict__ nch) {
     const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
-    if (r >= nrows) return;
-    nch[r] = (row_pt[r + 1] - row_pt[r] + 63) / 64;
+    if (r >= ncells) return;
+    const uint64_t nrows = row_of[ncells];
+    nch[r] = r < nrows ? (row_pt[r + 1] - row_pt[r] + 63) / 64 : 0u;
 }
 
 __global__ __launch_bounds__(kThreads) void k_emit_chunks(const uint32_t *__restrict__ row_pt,
-                                                           const uint32_t *__restrict__ ch_off,
-                                                           uint32_t nrows, uint2 *__restrict__ chunks) {
+                                                           const uint64_t *__restrict__ row_of,
+                                                           const uint64_t *__restrict__ ch_off,
+                                                           uint32_t ncells, uint2 *__restrict__ chunks) {
     const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
-    if (r >= nrows) return;
+    if (r >= ncells || r >= row_of[ncells]) return;
     const uint32_t s = row_pt[r], e = row_pt[r + 1];
-    uint32_t k = ch_off[r];
+    uint64_t k = ch_off[r];
     for (uint32_t q = s; q < e; q += 64, ++k) chunks[k] = make_uint2(q, q + 64 < e ? q + 64 : e);
 }
 
@@ -372,35 +392,27 @@ uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, const uint
     if (ncells == 0 || n == 0) return 0;
     k_point_c0<<<nblk(n), kThreads, 0, s>>>(cell_of, coords, n, d, cx);
     SJ_LAUNCH_CHECK();
-    DevBuf<uint32_t> flag(ncells), row_of(ncells);
+    // rows are bounded by the cells, so every array below is sized by ncells
+    DevBuf<uint32_t> flag(ncells), row_pt(static_cast<size_t>(ncells) + 1), nch(ncells);
+    DevBuf<uint64_t> row_of(static_cast<size_t>(ncells) + 1), choff(static_cast<size_t>(ncells) + 1);
     k_row_heads<<<nblk(ncells), kThreads, 0, s>>>(coords, ncells, d, flag.ptr);
     SJ_LAUNCH_CHECK();
-    DevBuf<uint64_t> row64(static_cast<size_t>(ncells) + 1);
-    scan_exclusive_u32_to_u64(flag.ptr, row64.ptr, ncells, s);
-    uint64_t nrows64 = 0;
-    SJ_HIP(hipMemcpyAsync(&nrows64, row64.ptr + ncells, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    scan_exclusive_u32(flag.ptr, row_of.ptr, ncells, s);
-    SJ_HIP(hipStreamSynchronize(s));
-    const uint32_t nrows = static_cast<uint32_t>(nrows64);
-    DevBuf<uint32_t> row_pt(static_cast<size_t>(nrows) + 1), nch(nrows);
-    k_row_points<<<nblk(ncells), kThreads, 0, s>>>(flag.ptr, row_of.ptr, starts, ncells, n, nrows,
-                                                   row_pt.ptr);
+    scan_exclusive_u32_to_u64(flag.ptr, row_of.ptr, ncells, s);
+    k_row_points<<<nblk(ncells), kThreads, 0, s>>>(flag.ptr, row_of.ptr, starts, ncells, n, row_pt.ptr);
     SJ_LAUNCH_CHECK();
-    k_row_nchunks<<<nblk(nrows), kThreads, 0, s>>>(row_pt.ptr, nrows, nch.ptr);
+    k_row_nchunks<<<nblk(ncells), kThreads, 0, s>>>(row_pt.ptr, row_of.ptr, ncells, nch.ptr);
     SJ_LAUNCH_CHECK();
-    DevBuf<uint64_t> choff64(static_cast<size_t>(nrows) + 1);
-    scan_exclusive_u32_to_u64(nch.ptr, choff64.ptr, nrows, s);
+    scan_exclusive_u32_to_u64(nch.ptr, choff.ptr, ncells, s);
     uint64_t total = 0;
-    SJ_HIP(hipMemcpyAsync(&total, choff64.ptr + nrows, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    DevBuf<uint32_t> choff(nrows);
-    scan_exclusive_u32(nch.ptr, choff.ptr, nrows, s);
+    SJ_HIP(hipMemcpyAsync(&total, choff.ptr + ncells, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
+    if (total >= 0xffffffffULL) throw Error(SJ_ECAPACITY, "too many join chunks");
     if (total > *chunks_cap) {
         if (*chunks_out) dev_free(*chunks_out);
         *chunks_out = static_cast<uint2 *>(dev_alloc(total * sizeof(uint2)));
         *chunks_cap = total;
     }
-    k_emit_chunks<<<nblk(nrows), kThreads, 0, s>>>(row_pt.ptr, choff.ptr, nrows, *chunks_out);
+    k_emit_chunks<<<nblk(ncells), kThreads, 0, s>>>(row_pt.ptr, row_of.ptr, choff.ptr, ncells, *chunks_out);
     SJ_LAUNCH_CHECK();
     return static_cast<uint32_t>(total);
 }

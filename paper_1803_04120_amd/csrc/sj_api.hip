@@ -119,6 +119,7 @@ struct sj_index {
     DevBuf<uint32_t> starts;
     DevBuf<uint32_t> coords;
     DevBuf<uint32_t> masks;
+    DevBuf<uint32_t> max_cell_dev;
     uint32_t mask_off[sj::kMaxDim] = {};
     uint32_t mask_words = 0;
     // adjacent-cell search, cached per setting: [0] all adjacent cells,
@@ -283,9 +284,9 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
         ix.mask_words = 0;  // masks only prune; a grid this wide goes without
     }
     ix.coords.reset(ix.ncells * d);
-    ix.max_cell = sj::launch_cell_coords_masks(ix.B.ptr, ix.starts.ptr, ix.ncells, ix.grid,
-                                               ix.coords.ptr, ix.masks.ptr, moff.ptr,
-                                               ix.mask_words, s);
+    ix.max_cell_dev.ensure(1);
+    sj::launch_cell_coords_masks(ix.B.ptr, ix.starts.ptr, ix.ncells, ix.grid, ix.coords.ptr,
+                                 ix.masks.ptr, moff.ptr, ix.mask_words, ix.max_cell_dev.ptr, s);
     // cell-ordered structure of arrays
     ix.X.reset(n * d);
     sj::launch_gather_soa(dp, ix.perm.ptr, n, d, ix.X.ptr, s);
@@ -515,6 +516,20 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
                        sc.big_count.ptr, ix.max_row, s);
 }
 
+// The fill pass may evaluate the unicomp subset (every mirrored pair then
+// takes a global slot with an atomic) or all adjacent cells (each point
+// writes only its own row, no atomics, twice the distance evaluations).
+// Both fill the same rows. When pairs are a large fraction of the unicomp
+// evaluations the atomics cost more than the extra evaluations.
+// SJ_FILL_MODE=full|unicomp overrides the choice.
+bool choose_unicomp_fill(const sj_index &ix) {
+    if (!ix.opts.unicomp) return false;
+    const char *e = std::getenv("SJ_FILL_MODE");
+    if (e && std::strcmp(e, "full") == 0) return false;
+    if (e && std::strcmp(e, "unicomp") == 0) return true;
+    return static_cast<double>(ix.pairs) < 0.05 * static_cast<double>(ix.stats.evals);
+}
+
 void join_fill_all(sj_index &ix, uint32_t *pairs_dev, hipStream_t s) {
     const double t0 = now_ms();
     if (ix.n == 0 || ix.pairs == 0) return;
@@ -522,7 +537,9 @@ void join_fill_all(sj_index &ix, uint32_t *pairs_dev, hipStream_t s) {
     Scratch sc;
     ix.overflow.ensure(1);
     sj::launch_fill_u32(ix.overflow.ptr, 1, 0u, s);
-    fill_rows(ix, 0, ix.n, 0, ix.pairs, ix.opts.unicomp != 0, out_j.ptr, pairs_dev, sc, s);
+    const bool uni_fill = choose_unicomp_fill(ix);
+    ix.stats.fill_unicomp = uni_fill ? 1u : 0u;
+    fill_rows(ix, 0, ix.n, 0, ix.pairs, uni_fill, out_j.ptr, pairs_dev, sc, s);
     check_overflow(ix, s);
     ix.stats.batches = 1;
     ix.stats.ms_fill = now_ms() - t0;
@@ -561,7 +578,8 @@ int join_batched(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
     SJ_HIP(hipStreamSynchronize(s));
     uint64_t maxbatch = 0;
     for (uint32_t b = 0; b < nb; ++b) maxbatch = std::max(maxbatch, offs[b + 1] - offs[b]);
-    const bool uni_fill = (nb == 1) && ix.opts.unicomp;
+    const bool uni_fill = (nb == 1) && choose_unicomp_fill(ix);
+    ix.stats.fill_unicomp = uni_fill ? 1u : 0u;
     const int nsets = nb > 1 ? 2 : 1;
     DevBuf<uint32_t> out_j[2], pairs[2];
     for (int k = 0; k < nsets; ++k) {
@@ -805,7 +823,10 @@ int sj_index_stats(const sj_index *idx, sj_stats *out) {
     for (int j = 0; j < sj::kMaxDim; ++j) st.grid_dims[j] = j < static_cast<int>(idx->d) ? idx->grid.dims[j] : 0;
     st.eps = idx->eps;
     st.cell_width = idx->grid.w;
-    st.max_cell_points = idx->max_cell;
+    uint32_t mc = idx->max_cell;
+    if (idx->max_cell_dev.ptr && hipMemcpy(&mc, idx->max_cell_dev.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost) == hipSuccess)
+        const_cast<sj_index *>(idx)->max_cell = mc;
+    st.max_cell_points = mc;
     *out = st;
     return SJ_OK;
 }

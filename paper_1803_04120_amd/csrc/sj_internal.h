@@ -124,10 +124,11 @@ template <typename K>
 uint64_t build_cells(const K *sorted_keys, uint64_t n, uint32_t *cell_of, uint64_t *B,
                      uint32_t *starts, hipStream_t s);
 // per-cell coordinates (cell-major, d per cell), occupancy masks, and the
-// largest cell (host sync for the latter).
-uint32_t launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_t ncells,
-                                  const GridParams &g, uint32_t *coords, uint32_t *masks,
-                                  const uint32_t *mask_off, uint32_t mask_words, hipStream_t s);
+// largest cell (written to *max_pts on the device).
+void launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_t ncells,
+                              const GridParams &g, uint32_t *coords, uint32_t *masks,
+                              const uint32_t *mask_off, uint32_t mask_words, uint32_t *max_pts,
+                              hipStream_t s);
 void launch_gather_soa(const double *pts, const uint32_t *perm, uint64_t n, uint32_t d,
                        double *X, hipStream_t s);
 void launch_make_f32(const double *X, uint64_t n, uint32_t d, const double *shift, float *Y,
