@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-capacity", type=int, default=1 << 24,
                     help="pairs per batch for the batched-delivery figure")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy three times (reference kernel "
+                         "of known traffic for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -220,6 +223,15 @@ def main():
         bdt = time.perf_counter() - t0
         batched = {"capacity_pairs": cap, "batches_per_eps": nb, "pairs_per_s": tot / bdt,
                    "note": "one untimed-by-events pass, batches delivered in device memory"}
+
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 3 x 1 GiB read + 1 GiB written")
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:
