@@ -74,7 +74,7 @@ def kernel_bytes(name, n, d, cells, ranges, pairs):
         # X + cell + row offset + permutation entry per point, range table,
         # one 4-byte neighbour id per pair
         return n * (8 * d + 4 + 8 + 4) + 8 * (cells + 1) + 8 * ranges + 4 * pairs
-    if name in ("rowsort_small", "rowsort_lane"):
+    if name in ("rowsort_small", "rowsort_lane", "rowsort_group16"):
         # row offsets, neighbour ids in, (i, j) pairs out
         return 8 * (n + 1) + 4 * pairs + 8 * pairs
     return None

@@ -296,27 +296,20 @@ void launch_join_d(const JoinArgs &a, int unicomp, int mode, int band, hipStream
 }
 
 // ------------------------------------------------------------ row plans
+// Row lengths in original order (for the output offsets) and in cell order
+// (for the fill layout), and the longest row (one atomic per workgroup).
 __global__ __launch_bounds__(kThreads) void k_row_lengths(const uint32_t *__restrict__ own,
                                                            const uint32_t *__restrict__ inc,
                                                            const uint32_t *__restrict__ perm,
-                                                           uint64_t n, uint32_t *__restrict__ len) {
-    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
-    if (r >= n) return;
-    len[perm[r]] = own[r] + (inc ? inc[r] : 0u);
-}
-
-// Row offset of every cell-ordered point (gather through A) and the longest
-// row (grid-stride; one atomic per workgroup).
-__global__ __launch_bounds__(kThreads) void k_gather_offsets(const uint64_t *__restrict__ off,
-                                                              const uint32_t *__restrict__ perm,
-                                                              uint64_t n, uint64_t *__restrict__ offc,
-                                                              const uint32_t *__restrict__ len,
-                                                              uint32_t *__restrict__ max_len) {
+                                                           uint64_t n, uint32_t *__restrict__ len,
+                                                           uint32_t *__restrict__ len_cell,
+                                                           uint32_t *__restrict__ max_len) {
     uint32_t m = 0;
     for (uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x; r < n;
          r += static_cast<uint64_t>(gridDim.x) * kThreads) {
-        offc[r] = off[perm[r]];
-        const uint32_t l = len[r];
+        const uint32_t l = own[r] + (inc ? inc[r] : 0u);
+        len[perm[r]] = l;
+        len_cell[r] = l;
         m = l > m ? l : m;
     }
     m = wave_max(m);
@@ -328,6 +321,14 @@ __global__ __launch_bounds__(kThreads) void k_gather_offsets(const uint64_t *__r
         for (int w = 1; w < kThreads / 64; ++w) b = sm[w] > b ? sm[w] : b;
         if (b) atomicMax(max_len, b);
     }
+}
+
+// Original-order row offset of every cell-ordered point (gather through A).
+__global__ __launch_bounds__(kThreads) void k_gather_offsets(const uint64_t *__restrict__ off,
+                                                              const uint32_t *__restrict__ perm,
+                                                              uint64_t n, uint64_t *__restrict__ offc) {
+    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (r < n) offc[r] = off[perm[r]];
 }
 
 __global__ __launch_bounds__(kThreads) void k_batch_flags(const uint32_t *__restrict__ perm,
@@ -426,23 +427,19 @@ void launch_join(const JoinArgs &a, uint32_t d, int unicomp, int mode, int band,
 }
 
 void launch_row_lengths(const uint32_t *own_cnt, const uint32_t *in_cnt, const uint32_t *perm,
-                        uint64_t n, uint32_t *len_orig, hipStream_t s) {
-    {
-        KTimer kt_("row_lengths", s);
-        k_row_lengths<<<blocks_for(n), kThreads, 0, s>>>(own_cnt, in_cnt, perm, n, len_orig);
-        SJ_LAUNCH_CHECK();
-    }
+                        uint64_t n, uint32_t *len_orig, uint32_t *len_cell, uint32_t *max_len,
+                        hipStream_t s) {
+    KTimer kt_("row_lengths", s);
+    k_row_lengths<<<static_cast<unsigned>(std::min<uint64_t>(512, blocks_for(n))), kThreads, 0, s>>>(
+        own_cnt, in_cnt, perm, n, len_orig, len_cell, max_len);
+    SJ_LAUNCH_CHECK();
 }
 
 void launch_gather_offsets(const uint64_t *off_orig, const uint32_t *perm, uint64_t n,
-                           uint64_t *offc, uint32_t *max_len, const uint32_t *len_orig,
-                           hipStream_t s) {
-    {
-        KTimer kt_("row_offsets_gather", s);
-        k_gather_offsets<<<static_cast<unsigned>(std::min<uint64_t>(512, blocks_for(n))), kThreads, 0, s>>>(
-            off_orig, perm, n, offc, len_orig, max_len);
-        SJ_LAUNCH_CHECK();
-    }
+                           uint64_t *offc, hipStream_t s) {
+    KTimer kt_("row_offsets_gather", s);
+    k_gather_offsets<<<blocks_for(n), kThreads, 0, s>>>(off_orig, perm, n, offc);
+    SJ_LAUNCH_CHECK();
 }
 
 uint32_t build_query_list(const uint32_t *perm, uint64_t n, uint64_t i0, uint64_t i1,

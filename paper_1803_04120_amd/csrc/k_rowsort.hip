@@ -8,16 +8,24 @@
 // (i, j) without any global sort.
 //
 // Rows are sorted by size class:
-//   <= N (16, 32 or 64, chosen from the longest row)
-//             one lane per row: the row is loaded into N registers and
-//             sorted by a fully unrolled bitonic network (static register
-//             indices, v_min/v_max only); 64 consecutive rows per wave
+//   <= 16     (when no row is longer) one lane per row: the row is loaded
+//             into 16 registers and sorted by a fully unrolled bitonic
+//             network (static register indices, v_min/v_max only)
+//   <= 64     16 lanes per row, 4 registers each, bitonic network over
+//             registers and 16-lane shuffles
 //   <= 1024   one wave per row, bitonic network in the wave's LDS slot
 //   <= 16384  one workgroup per row, bitonic network in 64 KiB of LDS
 //   larger    one workgroup per row, bitonic network in global memory, using
 //             the row's own output segment (twice the row's size) as scratch
 // Rows too long for the lane kernel are queued (device-side lists) for the
 // wave and workgroup kernels, whose grids loop over the queues.
+//
+// Row r's neighbour ids are read from out_j[in_off[r] - in_base, +len) and
+// its pairs are written at pairs[out_off[id] - out_base, +len) with
+// id = perm ? perm[r] : r0 + r. A whole result is filled in cell order (the
+// rows of one wave's points are adjacent, so the fill writes and these reads
+// are contiguous) and scattered to the rows' places in order of i here;
+// batches are filled directly in order of i (in_off = out_off).
 // j values within a row are distinct, so no stability is needed.
 #include "sj_internal.h"
 #include "sj_device.h"
@@ -30,6 +38,31 @@ constexpr int kWaves = kThreads / 64;
 constexpr uint32_t kWaveCap = 1024;
 constexpr uint32_t kBlockCap = 16384;
 constexpr uint32_t kPad = 0xffffffffu;
+
+struct RowMap {
+    const uint64_t *in_off;
+    uint64_t in_base;
+    const uint64_t *out_off;
+    uint64_t out_base;
+    const uint32_t *perm;
+    uint64_t r0;
+    uint64_t rows;
+};
+
+struct RowRef {
+    uint64_t in, out;
+    uint32_t len, id;
+};
+
+__device__ __forceinline__ RowRef row_ref(const RowMap &m, uint64_t r) {
+    RowRef x;
+    x.in = m.in_off[r] - m.in_base;
+    x.len = static_cast<uint32_t>(m.in_off[r + 1] - m.in_off[r]);
+    const uint64_t id = m.perm ? m.perm[r] : m.r0 + r;
+    x.id = static_cast<uint32_t>(id);
+    x.out = m.out_off[id] - m.out_base;
+    return x;
+}
 
 __device__ __forceinline__ uint32_t next_pow2(uint32_t v) {
     uint32_t p = 1;
@@ -72,39 +105,102 @@ __device__ __forceinline__ void register_bitonic(uint32_t (&v)[N]) {
 }
 
 template <int N>
-__global__ __launch_bounds__(kThreads) void k_rowsort_lane(const uint64_t *__restrict__ off,
-                                                            uint64_t i0, uint64_t i1, uint64_t base,
-                                                            const uint32_t *__restrict__ out_j,
+__global__ __launch_bounds__(kThreads) void k_rowsort_lane(RowMap m, const uint32_t *__restrict__ out_j,
                                                             uint2 *__restrict__ pairs,
                                                             uint32_t *__restrict__ lists,
                                                             uint32_t *__restrict__ counts) {
-    const uint64_t row = i0 + blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
-    if (row >= i1) return;
-    const uint64_t s = off[row] - base;
-    const uint32_t len = static_cast<uint32_t>(off[row + 1] - off[row]);
-    if (len > static_cast<uint32_t>(N)) {
-        const uint64_t rows = i1 - i0;
-        if (len <= kWaveCap) {
+    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (r >= m.rows) return;
+    const RowRef x = row_ref(m, r);
+    if (x.len > static_cast<uint32_t>(N)) {
+        if (x.len <= kWaveCap) {
             const uint32_t at = atomicAdd(&counts[0], 1u);
-            lists[at] = static_cast<uint32_t>(row - i0);
+            lists[at] = static_cast<uint32_t>(r);
         } else {
             const uint32_t at = atomicAdd(&counts[1], 1u);
-            lists[rows + at] = static_cast<uint32_t>(row - i0);
+            lists[m.rows + at] = static_cast<uint32_t>(r);
         }
         return;
     }
     uint32_t v[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = static_cast<uint32_t>(k) < len ? out_j[s + k] : kPad;
+    for (int k = 0; k < N; ++k) v[k] = static_cast<uint32_t>(k) < x.len ? out_j[x.in + k] : kPad;
     register_bitonic<N>(v);
-    const uint32_t r32 = static_cast<uint32_t>(row);
 #pragma unroll
     for (int k = 0; k < N; ++k)
-        if (static_cast<uint32_t>(k) < len) pairs[s + k] = make_uint2(r32, v[k]);
+        if (static_cast<uint32_t>(k) < x.len) pairs[x.out + k] = make_uint2(x.id, v[k]);
 }
 
-__global__ __launch_bounds__(kThreads) void k_rowsort_wave(const uint64_t *__restrict__ off,
-                                                            uint64_t i0, uint64_t base,
+// Rows of up to 64 entries, 16 lanes per row (4 rows per wave): lane l holds
+// elements e = 16 k + l, k = 0..3; bitonic stages with a partner distance of
+// 16 or more exchange registers within the lane, shorter ones exchange with
+// lane l ^ j of the same 16-lane group. Each row is read and written by 16
+// consecutive lanes at consecutive addresses.
+__global__ __launch_bounds__(kThreads) void k_rowsort_group16(RowMap m, const uint32_t *__restrict__ out_j,
+                                                               uint2 *__restrict__ pairs,
+                                                               uint32_t *__restrict__ lists,
+                                                               uint32_t *__restrict__ counts) {
+    const uint64_t r = (blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x) >> 4;
+    const uint32_t l = threadIdx.x & 15u;
+    const bool valid = r < m.rows;
+    RowRef x{0, 0, 0, 0};
+    if (valid) x = row_ref(m, r);
+    const bool big = valid && x.len > 64;
+    if (big && l == 0) {
+        if (x.len <= kWaveCap) {
+            const uint32_t at = atomicAdd(&counts[0], 1u);
+            lists[at] = static_cast<uint32_t>(r);
+        } else {
+            const uint32_t at = atomicAdd(&counts[1], 1u);
+            lists[m.rows + at] = static_cast<uint32_t>(r);
+        }
+    }
+    const bool mine = valid && !big;
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t e = static_cast<uint32_t>(k) * 16 + l;
+        v[k] = (mine && e < x.len) ? out_j[x.in + e] : kPad;
+    }
+#pragma unroll
+    for (int kk = 2; kk <= 64; kk <<= 1) {
+#pragma unroll
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j >= 16) {
+                const int jr = j >> 4;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int kp = k ^ jr;
+                    if (kp > k) {
+                        const uint32_t e = static_cast<uint32_t>(k) * 16 + l;
+                        const bool asc = (e & static_cast<uint32_t>(kk)) == 0;
+                        const uint32_t a = v[k], b = v[kp];
+                        const uint32_t mn = a < b ? a : b, mx = a < b ? b : a;
+                        v[k] = asc ? mn : mx;
+                        v[kp] = asc ? mx : mn;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t p = __shfl_xor(v[k], j, 16);
+                    const uint32_t e = static_cast<uint32_t>(k) * 16 + l;
+                    const bool asc = (e & static_cast<uint32_t>(kk)) == 0;
+                    const bool lower = (l & static_cast<uint32_t>(j)) == 0;
+                    const uint32_t mn = v[k] < p ? v[k] : p, mx = v[k] < p ? p : v[k];
+                    v[k] = (lower == asc) ? mn : mx;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t e = static_cast<uint32_t>(k) * 16 + l;
+        if (mine && e < x.len) pairs[x.out + e] = make_uint2(x.id, v[k]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_rowsort_wave(RowMap m,
                                                             const uint32_t *__restrict__ out_j,
                                                             uint2 *__restrict__ pairs,
                                                             const uint32_t *__restrict__ list,
@@ -115,11 +211,10 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_wave(const uint64_t *__res
     const uint32_t nrows = *count;
     volatile uint32_t *sh = slot[wave];
     for (uint32_t w = blockIdx.x * kWaves + wave; w < nrows; w += gridDim.x * kWaves) {
-        const uint64_t row = i0 + list[w];
-        const uint64_t s = off[row] - base;
-        const uint32_t len = static_cast<uint32_t>(off[row + 1] - off[row]);
+        const RowRef x = row_ref(m, list[w]);
+        const uint32_t len = x.len;
         const uint32_t N = next_pow2(len);
-        for (uint32_t e = lane; e < N; e += 64) sh[e] = e < len ? out_j[s + e] : kPad;
+        for (uint32_t e = lane; e < N; e += 64) sh[e] = e < len ? out_j[x.in + e] : kPad;
         __builtin_amdgcn_wave_barrier();
         for (uint32_t k = 2; k <= N; k <<= 1) {
             for (uint32_t j = k >> 1; j > 0; j >>= 1) {
@@ -136,14 +231,12 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_wave(const uint64_t *__res
                 __builtin_amdgcn_wave_barrier();
             }
         }
-        const uint32_t r32 = static_cast<uint32_t>(row);
-        for (uint32_t e = lane; e < len; e += 64) pairs[s + e] = make_uint2(r32, sh[e]);
+        for (uint32_t e = lane; e < len; e += 64) pairs[x.out + e] = make_uint2(x.id, sh[e]);
         __builtin_amdgcn_wave_barrier();
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_rowsort_big(const uint64_t *__restrict__ off,
-                                                           uint64_t i0, uint64_t base,
+__global__ __launch_bounds__(kThreads) void k_rowsort_big(RowMap m,
                                                            uint32_t *__restrict__ out_j,
                                                            uint2 *__restrict__ pairs,
                                                            const uint32_t *__restrict__ big_list,
@@ -151,11 +244,11 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_big(const uint64_t *__rest
     __shared__ uint32_t sh[kBlockCap];
     const uint32_t nbig = *big_count;
     for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
-        const uint64_t row = i0 + big_list[b];
-        const uint64_t s = off[row] - base;
-        const uint32_t len = static_cast<uint32_t>(off[row + 1] - off[row]);
+        const RowRef x = row_ref(m, big_list[b]);
+        const uint64_t s = x.in, so = x.out;
+        const uint32_t len = x.len;
         const uint32_t N = next_pow2(len);
-        const uint32_t r32 = static_cast<uint32_t>(row);
+        const uint32_t r32 = x.id;
         if (N <= kBlockCap) {
             for (uint32_t e = threadIdx.x; e < N; e += kThreads) sh[e] = e < len ? out_j[s + e] : kPad;
             __syncthreads();
@@ -174,13 +267,13 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_big(const uint64_t *__rest
                     __syncthreads();
                 }
             }
-            for (uint32_t e = threadIdx.x; e < len; e += kThreads) pairs[s + e] = make_uint2(r32, sh[e]);
+            for (uint32_t e = threadIdx.x; e < len; e += kThreads) pairs[so + e] = make_uint2(r32, sh[e]);
             __syncthreads();
             continue;
         }
         // Global-memory network; the row's pair segment (2 * len words >= N)
         // is the scratch array.
-        uint32_t *T = reinterpret_cast<uint32_t *>(pairs + s);
+        uint32_t *T = reinterpret_cast<uint32_t *>(pairs + so);
         for (uint32_t e = threadIdx.x; e < N; e += kThreads) T[e] = e < len ? out_j[s + e] : kPad;
         __threadfence();
         __syncthreads();
@@ -203,7 +296,7 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_big(const uint64_t *__rest
         for (uint32_t e = threadIdx.x; e < len; e += kThreads) out_j[s + e] = T[e];
         __threadfence();
         __syncthreads();
-        for (uint32_t e = threadIdx.x; e < len; e += kThreads) pairs[s + e] = make_uint2(r32, out_j[s + e]);
+        for (uint32_t e = threadIdx.x; e < len; e += kThreads) pairs[so + e] = make_uint2(r32, out_j[s + e]);
         __syncthreads();
     }
 }
@@ -213,13 +306,43 @@ __global__ void k_zero2(uint32_t *p) {
 }
 
 template <int N>
-void launch_lane(const uint64_t *off, uint64_t i0, uint64_t i1, uint64_t base, const uint32_t *out_j,
-                 uint2 *pairs, uint32_t *lists, uint32_t *counts, hipStream_t s) {
-    const uint64_t nb = (i1 - i0 + kThreads - 1) / kThreads;
+void launch_lane(const RowMap &m, const uint32_t *out_j, uint2 *pairs, uint32_t *lists,
+                 uint32_t *counts, hipStream_t s) {
+    const uint64_t nb = (m.rows + kThreads - 1) / kThreads;
     KTimer kt_("rowsort_lane", s);
-    k_rowsort_lane<N><<<static_cast<unsigned>(nb), kThreads, 0, s>>>(off, i0, i1, base, out_j, pairs,
-                                                                    lists, counts);
+    k_rowsort_lane<N><<<static_cast<unsigned>(nb), kThreads, 0, s>>>(m, out_j, pairs, lists, counts);
     SJ_LAUNCH_CHECK();
+}
+
+void rowsort(const RowMap &m, uint32_t *out_j, uint32_t *pairs, uint32_t *lists, uint32_t *counts,
+             uint32_t max_len, hipStream_t s) {
+    if (m.rows == 0) return;
+    if (m.rows > 0x7fffffffULL) throw Error(SJ_EINVAL, "row sort: too many rows");
+    k_zero2<<<1, 64, 0, s>>>(counts);
+    SJ_LAUNCH_CHECK();
+    uint2 *p2 = reinterpret_cast<uint2 *>(pairs);
+    if (max_len <= 16) {
+        launch_lane<16>(m, out_j, p2, lists, counts, s);
+    } else {
+        const uint64_t nb = (m.rows * 16 + kThreads - 1) / kThreads;
+        KTimer kt_("rowsort_group16", s);
+        k_rowsort_group16<<<static_cast<unsigned>(nb), kThreads, 0, s>>>(m, out_j, p2, lists, counts);
+        SJ_LAUNCH_CHECK();
+    }
+    if (max_len > 64) {
+        {
+            KTimer kt_("rowsort_wave", s);
+            const uint64_t want = (m.rows + kWaves - 1) / kWaves;
+            k_rowsort_wave<<<static_cast<unsigned>(std::min<uint64_t>(want, 8192)), kThreads, 0, s>>>(
+                m, out_j, p2, lists, counts);
+            SJ_LAUNCH_CHECK();
+        }
+        if (max_len > kWaveCap) {
+            KTimer kt_("rowsort_big", s);
+            k_rowsort_big<<<512, kThreads, 0, s>>>(m, out_j, p2, lists + m.rows, counts + 1);
+            SJ_LAUNCH_CHECK();
+        }
+    }
 }
 
 }  // namespace
@@ -228,31 +351,15 @@ void launch_rowsort(const uint64_t *off, uint64_t i0, uint64_t i1, uint64_t base
                     uint32_t *pairs, uint32_t *lists, uint32_t *counts, uint32_t max_len,
                     hipStream_t s) {
     if (i1 <= i0) return;
-    const uint64_t rows = i1 - i0;
-    if (rows > 0x7fffffffULL) throw Error(SJ_EINVAL, "row sort: too many rows");
-    k_zero2<<<1, 64, 0, s>>>(counts);
-    SJ_LAUNCH_CHECK();
-    uint2 *p2 = reinterpret_cast<uint2 *>(pairs);
-    if (max_len <= 16)
-        launch_lane<16>(off, i0, i1, base, out_j, p2, lists, counts, s);
-    else if (max_len <= 32)
-        launch_lane<32>(off, i0, i1, base, out_j, p2, lists, counts, s);
-    else
-        launch_lane<64>(off, i0, i1, base, out_j, p2, lists, counts, s);
-    if (max_len > 64) {
-        {
-            KTimer kt_("rowsort_wave", s);
-            const uint64_t want = (rows + kWaves - 1) / kWaves;
-            k_rowsort_wave<<<static_cast<unsigned>(std::min<uint64_t>(want, 8192)), kThreads, 0, s>>>(
-                off, i0, base, out_j, p2, lists, counts);
-            SJ_LAUNCH_CHECK();
-        }
-        if (max_len > kWaveCap) {
-            KTimer kt_("rowsort_big", s);
-            k_rowsort_big<<<512, kThreads, 0, s>>>(off, i0, base, out_j, p2, lists + rows, counts + 1);
-            SJ_LAUNCH_CHECK();
-        }
-    }
+    RowMap m{off + i0, base, off, base, nullptr, i0, i1 - i0};
+    rowsort(m, out_j, pairs, lists, counts, max_len, s);
+}
+
+void launch_rowsort_cells(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,
+                          uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t *lists,
+                          uint32_t *counts, uint32_t max_len, hipStream_t s) {
+    RowMap m{off_cell, 0, off_orig, 0, perm, 0, n};
+    rowsort(m, out_j, pairs, lists, counts, max_len, s);
 }
 
 }  // namespace sj

@@ -145,8 +145,11 @@ struct sj_index {
     sj_join_opts opts{};
     int band_used = 0;
     float lo = 0.f, hi = 0.f;
-    DevBuf<uint32_t> own_cnt, in_cnt, len_orig, cur;
-    DevBuf<uint64_t> off_orig, offc;
+    DevBuf<uint32_t> own_cnt, in_cnt, len_orig, len_cell, cur;
+    DevBuf<uint64_t> off_orig;   // row offsets in order of i (n + 1)
+    DevBuf<uint64_t> off_cell;   // row offsets in cell order (n + 1): whole-result fill layout
+    DevBuf<uint64_t> offc;       // off_orig gathered to cell order (batched fills)
+    bool offc_ready = false;
     DevBuf<unsigned long long> counters;  // evals, band rechecks
     DevBuf<uint32_t> max_len;
     DevBuf<uint32_t> overflow;
@@ -385,7 +388,7 @@ sj::JoinArgs base_args(sj_index &ix, int mode) {
     a.hi = ix.hi;
     a.own_cnt = ix.own_cnt.ptr;
     a.in_cnt = ix.in_cnt.ptr;
-    a.offc = ix.offc.ptr;
+    a.offc = nullptr;
     a.perm = ix.perm.ptr;
     a.evals = ix.counters.ptr;
     a.band_rechecks = ix.counters.ptr + sj::kCounterSlots * sj::kCounterStride;
@@ -423,7 +426,9 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     ix.in_cnt.ensure(n);
     ix.len_orig.ensure(n);
     ix.off_orig.ensure(n + 1);
-    ix.offc.ensure(n);
+    ix.off_cell.ensure(n + 1);
+    ix.len_cell.ensure(n);
+    ix.offc_ready = false;
     const size_t nctr = 2 * sj::kCounterSlots * sj::kCounterStride;
     ix.counters.ensure(nctr);
     ix.max_len.ensure(1);
@@ -436,10 +441,9 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     else
         sj::launch_join(a, ix.d, uni, sj::kCount, ix.band_used, s);
     sj::launch_row_lengths(ix.own_cnt.ptr, uni ? ix.in_cnt.ptr : nullptr, ix.perm.ptr, n,
-                           ix.len_orig.ptr, s);
+                           ix.len_orig.ptr, ix.len_cell.ptr, ix.max_len.ptr, s);
     sj::scan_exclusive_u32_to_u64(ix.len_orig.ptr, ix.off_orig.ptr, n, s);
-    sj::launch_gather_offsets(ix.off_orig.ptr, ix.perm.ptr, n, ix.offc.ptr, ix.max_len.ptr,
-                              ix.len_orig.ptr, s);
+    sj::scan_exclusive_u32_to_u64(ix.len_cell.ptr, ix.off_cell.ptr, n, s);
     std::vector<unsigned long long> cnt(nctr);
     SJ_HIP(hipMemcpyAsync(&ix.pairs, ix.off_orig.ptr + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipMemcpyAsync(&ix.max_row, ix.max_len.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -489,6 +493,18 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
     a.out_cap = cap;
     ix.overflow.ensure(1);
     a.overflow = ix.overflow.ptr;
+    if (whole) {
+        // whole result: rows laid out in cell order, scattered to order of i
+        // by the row sort
+        a.offc = ix.off_cell.ptr;
+    } else {
+        if (!ix.offc_ready) {
+            ix.offc.ensure(n);
+            sj::launch_gather_offsets(ix.off_orig.ptr, ix.perm.ptr, n, ix.offc.ptr, s);
+            ix.offc_ready = true;
+        }
+        a.offc = ix.offc.ptr;
+    }
     if (unicomp_fill) {
         ix.cur.ensure(n);
         sj::launch_fill_u32(ix.cur.ptr, n, 0u, s);
@@ -512,8 +528,12 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
     }
     sc.big_list.ensure(2 * std::max<uint64_t>(1, i1 - i0));
     sc.big_count.ensure(2);
-    sj::launch_rowsort(ix.off_orig.ptr, i0, i1, base, out_j, pairs, sc.big_list.ptr,
-                       sc.big_count.ptr, ix.max_row, s);
+    if (whole)
+        sj::launch_rowsort_cells(ix.off_cell.ptr, ix.off_orig.ptr, ix.perm.ptr, n, out_j, pairs,
+                                 sc.big_list.ptr, sc.big_count.ptr, ix.max_row, s);
+    else
+        sj::launch_rowsort(ix.off_orig.ptr, i0, i1, base, out_j, pairs, sc.big_list.ptr,
+                           sc.big_count.ptr, ix.max_row, s);
 }
 
 // The fill pass may evaluate the unicomp subset (every mirrored pair then

@@ -213,10 +213,10 @@ void launch_join_tiled(const JoinArgs &a, const TileArgs &t, uint32_t d, int uni
 // row lengths in original order, exclusive offsets (u64, n+1), row offsets
 // in cell order, max row length (device).
 void launch_row_lengths(const uint32_t *own_cnt, const uint32_t *in_cnt, const uint32_t *perm,
-                        uint64_t n, uint32_t *len_orig, hipStream_t s);
+                        uint64_t n, uint32_t *len_orig, uint32_t *len_cell, uint32_t *max_len,
+                        hipStream_t s);
 void launch_gather_offsets(const uint64_t *off_orig, const uint32_t *perm, uint64_t n,
-                           uint64_t *offc, uint32_t *max_len, const uint32_t *len_orig,
-                           hipStream_t s);
+                           uint64_t *offc, hipStream_t s);
 // cell-ordered points whose original id lies in [i0, i1), in cell order.
 // Returns the count (host sync).
 uint32_t build_query_list(const uint32_t *perm, uint64_t n, uint64_t i0, uint64_t i1,
@@ -236,5 +236,11 @@ void launch_batch_bounds(const uint64_t *off, uint64_t n, uint64_t total, uint32
 void launch_rowsort(const uint64_t *off, uint64_t i0, uint64_t i1, uint64_t base,
                     uint32_t *out_j, uint32_t *pairs, uint32_t *lists, uint32_t *counts,
                     uint32_t max_len, hipStream_t s);
+// Whole result filled in cell order: row r (cell-ordered point r) occupies
+// out_j[off_cell[r], off_cell[r+1]) and goes to pairs[off_orig[perm[r]], ...)
+// with i = perm[r]. lists holds 2 n entries.
+void launch_rowsort_cells(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,
+                          uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t *lists,
+                          uint32_t *counts, uint32_t max_len, hipStream_t s);
 
 }  // namespace sj
