@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-capacity", type=int, default=1 << 24,
                     help="pairs per batch for the batched-delivery figure")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serve-requests", type=int, default=128)
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy three times (reference kernel "
                          "of known traffic for hardware byte counters)")
@@ -109,6 +112,65 @@ def cpu_baseline(pts, eps_list, target_s):
             "sample": f"{rows_per_eps} random query rows x all {n} candidates for each of "
                       f"{len(eps_list)} eps ({pairs} pairs in {dt:.1f} s); "
                       f"rate = sample pairs / sample time"}
+
+
+def calibrate_eps_gpu(sj, x, k, eps0):
+    """eps whose mean neighbour count (self excluded) is about k, by bisection
+    on the GPU count pass (a few builds of the request's own points)."""
+    n = x.shape[0]
+    lo, hi = eps0 * 0.05, eps0 * 2.0
+
+    def mean_k(e):
+        with sj.Index(x, e) as ix:
+            return ix.count(unicomp=True) / n - 1.0
+    for _ in range(14):
+        mid = (lo * hi) ** 0.5
+        if mean_k(mid) < k:
+            lo = mid
+        else:
+            hi = mid
+    return (lo * hi) ** 0.5
+
+
+def serving_leg(args, sj, torch):
+    """Poisson stream of self-join requests through the continuous-batching
+    server: n log-uniform in [1e3, 2e6], d uniform in 2..6, uniform or
+    clustered points, eps for a target mean neighbour count log-uniform in
+    [4, 128], FP32 pre-test path. A closed-loop pass (all requests at once)
+    gives the saturation rate; the open-loop pass runs at 0.7 of it."""
+    from paper_1803_04120_amd import datagen
+    from paper_1803_04120_amd.serve import Server, run_stream, uniform_eps_for_k
+    descs = datagen.serving_requests(args.serve_requests, seed=5)
+    reqs = []
+    for q in descs:
+        pts = datagen.make(q["kind"], q["n"], q["d"], q["seed"])
+        x = torch.from_numpy(pts).cuda()
+        eps = uniform_eps_for_k(q["n"], q["d"], q["k"])
+        if q["kind"] == "clustered":
+            eps = calibrate_eps_gpu(sj, x, q["k"], eps)
+        reqs.append({"points": x, "eps": eps, "precision": "fp32_band", "unicomp": True,
+                     "expected_pairs": int(q["n"] * (q["k"] + 1)), "n": q["n"], "d": q["d"]})
+    torch.cuda.synchronize()
+    budget = 64 << 30
+    with Server(slots=args.serve_slots, mem_budget_bytes=budget) as srv:
+        # closed loop: everything arrives at t = 0
+        done, span = run_stream(srv, reqs, np.zeros(len(reqs)))
+        sat = len(reqs) / span
+        rate = 0.7 * sat
+        arr = datagen.poisson_arrivals(len(reqs), rate, seed=6)
+        done, span2 = run_stream(srv, reqs, arr)
+        info = srv.info()
+    lat = np.array([c["latency_ms"] for c in done])
+    pairs = sum(c["npairs"] for c in done)
+    return {"requests": len(reqs), "slots": args.serve_slots, "mem_budget_bytes": budget,
+            "precision": "fp32_band", "saturation_req_per_s": round(sat, 2),
+            "rate_req_per_s": round(rate, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_queue_ms": round(float(np.mean([c["queue_ms"] for c in done])), 3),
+            "pairs_per_s": pairs / span2, "closed_loop_pairs_per_s": pairs / span,
+            "errors": int(sum(c["status"] != 0 for c in done)),
+            "over_estimate": info["over_estimate"],
+            "n_range": [int(min(r["n"] for r in reqs)), int(max(r["n"] for r in reqs))]}
 
 
 def main():
@@ -233,6 +295,12 @@ def main():
         log("[bench] calibration copy: 3 x 1 GiB read + 1 GiB written")
         del src, dst
 
+    serving = None
+    if not args.no_serve:
+        serving = serving_leg(args, sj, torch)
+        log(f"[bench] serving: p50 {serving['p50_ms']} ms p99 {serving['p99_ms']} ms at "
+            f"{serving['rate_req_per_s']} req/s, {serving['pairs_per_s']:.4g} pairs/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pts, eps_list, args.cpu_seconds)
@@ -259,6 +327,7 @@ def main():
         "pipeline_hbm": pipeline,
         "per_eps": info,
         "batched": batched,
+        "serving": serving,
         "kernels_ms": {k: round(v[1] / args.steps, 4) for k, v in prof.items()},
         "call_wall_ms": {k: round(v, 3) for k, v in host_ms.items()},
     }

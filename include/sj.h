@@ -171,6 +171,7 @@ int sj_index_stats(const sj_index *idx, sj_stats *out);
  *   SJ_EXPORT_RANGE_OFF   uint32[|G|+1] candidate ranges of cell h are rng[off[h] .. off[h+1]-1]
  *   SJ_EXPORT_RANGES      uint32[2*R]   (start, end) point ranges in cell order
  *   SJ_EXPORT_GRID        double[2*8+1] g_min[8], |g_j| as doubles [8], w
+ *   SJ_EXPORT_ROW_OFFSETS uint64[n+1]   result row i holds pairs [off[i], off[i+1]) (after sj_join_count)
  * The two range arrays describe the last join (or the last sj_index_search).
  */
 #define SJ_EXPORT_CELL_IDS   1
@@ -180,6 +181,7 @@ int sj_index_stats(const sj_index *idx, sj_stats *out);
 #define SJ_EXPORT_RANGE_OFF  5
 #define SJ_EXPORT_RANGES     6
 #define SJ_EXPORT_GRID       7
+#define SJ_EXPORT_ROW_OFFSETS 8
 int sj_index_export_size(const sj_index *idx, int what, uint64_t *bytes);
 int sj_index_export(const sj_index *idx, int what, void *host_dst, uint64_t bytes);
 

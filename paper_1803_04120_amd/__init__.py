@@ -161,7 +161,7 @@ class Index:
             _lib.SJ_EXPORT_CELL_IDS: np.uint64, _lib.SJ_EXPORT_CELL_START: np.uint32,
             _lib.SJ_EXPORT_PERM: np.uint32, _lib.SJ_EXPORT_MASKS: np.uint32,
             _lib.SJ_EXPORT_RANGE_OFF: np.uint64, _lib.SJ_EXPORT_RANGES: np.uint32,
-            _lib.SJ_EXPORT_GRID: np.float64}[what]
+            _lib.SJ_EXPORT_GRID: np.float64, _lib.SJ_EXPORT_ROW_OFFSETS: np.uint64}[what]
         out = np.zeros(int(size.value) // np.dtype(dtype).itemsize, dtype=dtype)
         _lib.check(L.sj_index_export(self._h, what,
                                      ctypes.c_void_p(out.ctypes.data) if out.size else None,

@@ -30,6 +30,7 @@ SJ_EXPORT_MASKS = 4
 SJ_EXPORT_RANGE_OFF = 5
 SJ_EXPORT_RANGES = 6
 SJ_EXPORT_GRID = 7
+SJ_EXPORT_ROW_OFFSETS = 8
 
 _ERRNAMES = {SJ_EINVAL: "SJ_EINVAL", SJ_ENOMEM: "SJ_ENOMEM", SJ_EGRID: "SJ_EGRID",
              SJ_EDEVICE: "SJ_EDEVICE", SJ_ESTATE: "SJ_ESTATE", SJ_ECAPACITY: "SJ_ECAPACITY"}

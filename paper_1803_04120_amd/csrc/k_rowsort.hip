@@ -8,11 +8,11 @@
 // (i, j) without any global sort.
 //
 // Rows are sorted by size class:
-//   <= 16     (when no row is longer) one lane per row: the row is loaded
-//             into 16 registers and sorted by a fully unrolled bitonic
-//             network (static register indices, v_min/v_max only)
+//   <= 32     one lane per row: the row is loaded into 16 or 32 registers
+//             (16 when no row is longer) and sorted by a fully unrolled
+//             bitonic network (static register indices, v_min/v_max only)
 //   <= 64     16 lanes per row, 4 registers each, bitonic network over
-//             registers and 16-lane shuffles
+//             registers and 16-lane shuffles (queued rows only)
 //   <= 1024   one wave per row, bitonic network in the wave's LDS slot
 //   <= 16384  one workgroup per row, bitonic network in 64 KiB of LDS
 //   larger    one workgroup per row, bitonic network in global memory, using
@@ -113,7 +113,10 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_lane(RowMap m, const uint3
     if (r >= m.rows) return;
     const RowRef x = row_ref(m, r);
     if (x.len > static_cast<uint32_t>(N)) {
-        if (x.len <= kWaveCap) {
+        if (x.len <= 64) {
+            const uint32_t at = atomicAdd(&counts[2], 1u);
+            lists[2 * m.rows + at] = static_cast<uint32_t>(r);
+        } else if (x.len <= kWaveCap) {
             const uint32_t at = atomicAdd(&counts[0], 1u);
             lists[at] = static_cast<uint32_t>(r);
         } else {
@@ -138,23 +141,21 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_lane(RowMap m, const uint3
 // consecutive lanes at consecutive addresses.
 __global__ __launch_bounds__(kThreads) void k_rowsort_group16(RowMap m, const uint32_t *__restrict__ out_j,
                                                                uint2 *__restrict__ pairs,
-                                                               uint32_t *__restrict__ lists,
-                                                               uint32_t *__restrict__ counts) {
-    const uint64_t r = (blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x) >> 4;
+                                                               const uint32_t *__restrict__ list,
+                                                               const uint32_t *__restrict__ count) {
+    const uint32_t nrows = *count;
+    const uint32_t groups = gridDim.x * (kThreads / 16);
     const uint32_t l = threadIdx.x & 15u;
-    const bool valid = r < m.rows;
+    // the loop bound is uniform across the wave, so all 16-lane groups of a
+    // wave take part in every shuffle
+    const uint32_t first = blockIdx.x * (kThreads / 16) + (threadIdx.x >> 4);
+    const uint32_t wave_first = blockIdx.x * (kThreads / 16) + ((threadIdx.x >> 6) << 2);
+    for (uint32_t base = wave_first; base < nrows; base += groups) {
+    const uint32_t g = first + (base - wave_first);
+    const bool valid = g < nrows;
     RowRef x{0, 0, 0, 0};
-    if (valid) x = row_ref(m, r);
-    const bool big = valid && x.len > 64;
-    if (big && l == 0) {
-        if (x.len <= kWaveCap) {
-            const uint32_t at = atomicAdd(&counts[0], 1u);
-            lists[at] = static_cast<uint32_t>(r);
-        } else {
-            const uint32_t at = atomicAdd(&counts[1], 1u);
-            lists[m.rows + at] = static_cast<uint32_t>(r);
-        }
-    }
+    if (valid) x = row_ref(m, list[g]);
+    const bool big = false;
     const bool mine = valid && !big;
     uint32_t v[4];
 #pragma unroll
@@ -197,6 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_group16(RowMap m, const ui
     for (int k = 0; k < 4; ++k) {
         const uint32_t e = static_cast<uint32_t>(k) * 16 + l;
         if (mine && e < x.len) pairs[x.out + e] = make_uint2(x.id, v[k]);
+    }
     }
 }
 
@@ -301,8 +303,8 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_big(RowMap m,
     }
 }
 
-__global__ void k_zero2(uint32_t *p) {
-    if (threadIdx.x < 2) p[threadIdx.x] = 0;
+__global__ void k_zero3(uint32_t *p) {
+    if (threadIdx.x < 3) p[threadIdx.x] = 0;
 }
 
 template <int N>
@@ -318,15 +320,18 @@ void rowsort(const RowMap &m, uint32_t *out_j, uint32_t *pairs, uint32_t *lists,
              uint32_t max_len, hipStream_t s) {
     if (m.rows == 0) return;
     if (m.rows > 0x7fffffffULL) throw Error(SJ_EINVAL, "row sort: too many rows");
-    k_zero2<<<1, 64, 0, s>>>(counts);
+    k_zero3<<<1, 64, 0, s>>>(counts);
     SJ_LAUNCH_CHECK();
     uint2 *p2 = reinterpret_cast<uint2 *>(pairs);
-    if (max_len <= 16) {
+    if (max_len <= 16)
         launch_lane<16>(m, out_j, p2, lists, counts, s);
-    } else {
-        const uint64_t nb = (m.rows * 16 + kThreads - 1) / kThreads;
+    else
+        launch_lane<32>(m, out_j, p2, lists, counts, s);
+    if (max_len > 32) {
         KTimer kt_("rowsort_group16", s);
-        k_rowsort_group16<<<static_cast<unsigned>(nb), kThreads, 0, s>>>(m, out_j, p2, lists, counts);
+        const uint64_t want = (m.rows + 15) / 16;
+        k_rowsort_group16<<<static_cast<unsigned>(std::min<uint64_t>(want, 4096)), kThreads, 0, s>>>(
+            m, out_j, p2, lists + 2 * m.rows, counts + 2);
         SJ_LAUNCH_CHECK();
     }
     if (max_len > 64) {

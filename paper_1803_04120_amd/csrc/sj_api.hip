@@ -526,8 +526,8 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
         }
         sj::launch_join(a, ix.d, 0, sj::kFill, ix.band_used, s);
     }
-    sc.big_list.ensure(2 * std::max<uint64_t>(1, i1 - i0));
-    sc.big_count.ensure(2);
+    sc.big_list.ensure(3 * std::max<uint64_t>(1, i1 - i0));
+    sc.big_count.ensure(3);
     if (whole)
         sj::launch_rowsort_cells(ix.off_cell.ptr, ix.off_orig.ptr, ix.perm.ptr, n, out_j, pairs,
                                  sc.big_list.ptr, sc.big_count.ptr, ix.max_row, s);
@@ -868,6 +868,7 @@ int sj_index_export_size(const sj_index *idx, int what, uint64_t *bytes) {
             *bytes = idx->last_ranges >= 0 ? idx->ranges[idx->last_ranges].count * 2 * sizeof(uint32_t) : 0;
             break;
         case SJ_EXPORT_GRID: *bytes = (2 * sj::kMaxDim + 1) * sizeof(double); break;
+        case SJ_EXPORT_ROW_OFFSETS: *bytes = (idx->counted && idx->n) ? (idx->n + 1) * sizeof(uint64_t) : 0; break;
         default: set_error("unknown export"); return SJ_EINVAL;
     }
     return SJ_OK;
@@ -895,6 +896,7 @@ int sj_index_export(const sj_index *idx, int what, void *host_dst, uint64_t byte
             case SJ_EXPORT_MASKS: src = idx->masks.ptr; break;
             case SJ_EXPORT_RANGE_OFF: src = idx->ranges[idx->last_ranges].roff.ptr; break;
             case SJ_EXPORT_RANGES: src = idx->ranges[idx->last_ranges].rng; break;
+            case SJ_EXPORT_ROW_OFFSETS: src = idx->off_orig.ptr; break;
             case SJ_EXPORT_GRID: {
                 double g[2 * sj::kMaxDim + 1] = {};
                 for (uint32_t j = 0; j < idx->d; ++j) {

@@ -231,14 +231,14 @@ void launch_batch_bounds(const uint64_t *off, uint64_t n, uint64_t total, uint32
 // ---------------------------------------------------------------------
 // Sorts each row's neighbour ids and writes interleaved (i, j) pairs.
 // Rows [i0, i1); row i occupies [off[i] - base, off[i+1] - base) of out_j
-// and of pairs. lists (2 * (i1 - i0) entries) and counts (2) are scratch;
+// and of pairs. lists (3 * (i1 - i0) entries) and counts (3) are scratch;
 // max_len is the longest row.
 void launch_rowsort(const uint64_t *off, uint64_t i0, uint64_t i1, uint64_t base,
                     uint32_t *out_j, uint32_t *pairs, uint32_t *lists, uint32_t *counts,
                     uint32_t max_len, hipStream_t s);
 // Whole result filled in cell order: row r (cell-ordered point r) occupies
 // out_j[off_cell[r], off_cell[r+1]) and goes to pairs[off_orig[perm[r]], ...)
-// with i = perm[r]. lists holds 2 n entries.
+// with i = perm[r]. lists holds 3 n entries, counts 3.
 void launch_rowsort_cells(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,
                           uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t *lists,
                           uint32_t *counts, uint32_t max_len, hipStream_t s);

@@ -1,0 +1,143 @@
+"""Parity at the full workload sizes (GPU).
+
+The brute-force oracle cannot produce whole results of millions of points,
+so each full-size join is checked on a seeded sample of result rows that the
+oracle computes one by one (all n candidates for each sampled row), plus
+exact equalities that hold at any size: unicomp on = off, FP32 pre-test =
+FP64, batched = unbatched, row lengths summing to P, symmetry of the row
+lengths with the oracle's counts. The joins run through the same entry
+points and launch configuration as bench.py (count pass, whole-result fill).
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import reference as ref
+from paper_1803_04120_amd import datagen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+CALIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "eps_calibration.json")
+SAMPLE_ROWS = 256
+
+
+@pytest.fixture(scope="module")
+def sj():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1803_04120_amd as m
+    m._lib.load()
+    return m
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _calib():
+    with open(CALIB) as f:
+        return json.load(f)
+
+
+def _join(sj, x, eps, **kw):
+    ix = sj.Index(x, eps)
+    P = ix.count(**kw)
+    out = torch.empty((P, 2), dtype=torch.int32, device="cuda")
+    ix.fill(out)
+    off = ix.export(sj._lib.SJ_EXPORT_ROW_OFFSETS).astype(np.int64)
+    stats = ix.stats()
+    ix.close()
+    return out, off, stats
+
+
+def _check_rows(pts, eps, out, off, seed):
+    n = pts.shape[0]
+    rows = np.sort(np.random.default_rng(seed).choice(n, SAMPLE_ROWS, replace=False))
+    roff, js = ref.rows_neighbors(pts, eps, rows)
+    for k, i in enumerate(rows):
+        a, b = int(off[i]), int(off[i + 1])
+        seg = out[a:b].cpu().numpy().astype(np.int64)
+        want = js[roff[k]:roff[k + 1]].astype(np.int64)
+        assert np.all(seg[:, 0] == i), f"row {i}: wrong row ids"
+        np.testing.assert_array_equal(seg[:, 1], want, err_msg=f"row {i} differs")
+    return rows
+
+
+def test_uniform_2d_2M_eps_sweep(sj):
+    """The 2-D workload: 2,000,000 uniform points, eps 0.04 .. 0.2."""
+    pts = datagen.uniform(2_000_000, 2, seed=2)
+    x = torch.from_numpy(pts).cuda()
+    for e in (0.04, 0.08, 0.12, 0.16, 0.2):
+        _say(f"uniform 2d n=2M eps={e}")
+        out, off, st = _join(sj, x, e, unicomp=True)
+        assert off[-1] == out.shape[0] == st["pairs"]
+        _check_rows(pts, e, out, off, seed=int(e * 1000))
+        out0, off0, _ = _join(sj, x, e, unicomp=False)
+        assert torch.equal(out, out0)
+        np.testing.assert_array_equal(off, off0)
+        del out, out0
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("key", ["d3_k32", "d3_k256", "d4_k32", "d4_k256",
+                                 "d5_k32", "d5_k256", "d6_k32", "d6_k256"])
+def test_uniform_10M(sj, key):
+    """10,000,000 uniform points in 3..6-D at eps for mean 32 / 256
+    neighbours; unicomp on vs off must agree exactly."""
+    c = _calib()["uniform_n10M"][key]
+    _say(f"uniform n=10M {key} eps={c['eps']}")
+    pts = datagen.uniform(c["n"], c["d"], seed=c["seed"])
+    x = torch.from_numpy(pts).cuda()
+    out, off, st = _join(sj, x, c["eps"], unicomp=True)
+    assert off[-1] == out.shape[0]
+    mean_k = out.shape[0] / c["n"] - 1
+    assert abs(mean_k - c["k_mean"]) < 0.05 * c["k_mean"]
+    _check_rows(pts, c["eps"], out, off, seed=7)
+    out0, _, st0 = _join(sj, x, c["eps"], unicomp=False)
+    assert torch.equal(out, out0)
+    # the paper's factor ~2: unicomp evaluates (T + n) / 2 candidates
+    assert 2 * st["evals"] == st0["evals"] + c["n"]
+    del out, out0, x
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("key", ["d2", "d3"])
+def test_clustered_5M_fp32_band_equals_fp64(sj, key):
+    """5,000,000 clustered points (median 50 neighbours): the FP32 pre-test
+    with FP64 band re-decision gives exactly the FP64 pair set."""
+    c = _calib()["clustered_n5M"][key]
+    _say(f"clustered n=5M {key} eps={c['eps']}")
+    pts = datagen.clustered(c["n"], c["d"], seed=c["seed"])
+    x = torch.from_numpy(pts).cuda()
+    out, off, st = _join(sj, x, c["eps"], precision="fp64")
+    out32, off32, st32 = _join(sj, x, c["eps"], precision="fp32_band")
+    assert st32["precision_used"] == 1
+    assert torch.equal(out, out32)
+    assert st32["band_rechecks"] > 0
+    rows = _check_rows(pts, c["eps"], out, off, seed=11)
+    counts = np.diff(off)
+    assert np.median(counts[rows] - 1) == pytest.approx(c["k_median"], rel=0.35)
+    del out, out32, x
+    torch.cuda.empty_cache()
+
+
+def test_batched_equals_unbatched_at_scale(sj):
+    """Result larger than one batch buffer (2^27 pairs): the batches'
+    concatenation equals the single-buffer result."""
+    c = _calib()["uniform_n10M"]["d3_k32"]
+    _say("batched 10M d3 k32")
+    pts = datagen.uniform(c["n"], c["d"], seed=c["seed"])
+    x = torch.from_numpy(pts).cuda()
+    out, off, _ = _join(sj, x, c["eps"], unicomp=True)
+    with sj.Index(x, c["eps"]) as ix:
+        got, info = ix.join_batched(unicomp=True, batch_capacity_pairs=1 << 27, min_batches=3)
+    assert len(info) >= 3
+    assert all(npairs <= (1 << 27) for _, _, _, npairs in info)
+    assert torch.equal(got, out)
+    del out, got, x
+    torch.cuda.empty_cache()
