@@ -80,31 +80,6 @@ __device__ __forceinline__ void bitonic_pair(uint32_t q, uint32_t j, uint32_t k,
 }
 
 template <int N>
-__device__ __forceinline__ void register_bitonic(uint32_t (&v)[N]) {
-#pragma unroll
-    for (int k = 2; k <= N; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint32_t a = v[i], b = v[l];
-                    const uint32_t mn = a < b ? a : b, mx = a < b ? b : a;
-                    if ((i & k) == 0) {
-                        v[i] = mn;
-                        v[l] = mx;
-                    } else {
-                        v[i] = mx;
-                        v[l] = mn;
-                    }
-                }
-            }
-        }
-    }
-}
-
-template <int N>
 __global__ __launch_bounds__(kThreads) void k_rowsort_lane(RowMap m, const uint32_t *__restrict__ out_j,
                                                             uint2 *__restrict__ pairs,
                                                             uint32_t *__restrict__ lists,
@@ -358,6 +333,39 @@ void launch_rowsort(const uint64_t *off, uint64_t i0, uint64_t i1, uint64_t base
     if (i1 <= i0) return;
     RowMap m{off + i0, base, off, base, nullptr, i0, i1 - i0};
     rowsort(m, out_j, pairs, lists, counts, max_len, s);
+}
+
+void launch_rowsort_queued(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,
+                           uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t *lists,
+                           uint32_t *counts, uint32_t max_len, uint32_t sorted_len, hipStream_t s) {
+    RowMap m{off_cell, 0, off_orig, 0, perm, 0, n};
+    uint2 *p2 = reinterpret_cast<uint2 *>(pairs);
+    if (max_len > sorted_len) {
+        KTimer kt_("rowsort_group16", s);
+        const uint64_t want = (n + 15) / 16;
+        k_rowsort_group16<<<static_cast<unsigned>(std::min<uint64_t>(want, 4096)), kThreads, 0, s>>>(
+            m, out_j, p2, lists + 2 * n, counts + 2);
+        SJ_LAUNCH_CHECK();
+    }
+    if (max_len > 64) {
+        {
+            KTimer kt_("rowsort_wave", s);
+            const uint64_t want = (n + kWaves - 1) / kWaves;
+            k_rowsort_wave<<<static_cast<unsigned>(std::min<uint64_t>(want, 8192)), kThreads, 0, s>>>(
+                m, out_j, p2, lists, counts);
+            SJ_LAUNCH_CHECK();
+        }
+        if (max_len > kWaveCap) {
+            KTimer kt_("rowsort_big", s);
+            k_rowsort_big<<<512, kThreads, 0, s>>>(m, out_j, p2, lists + n, counts + 1);
+            SJ_LAUNCH_CHECK();
+        }
+    }
+}
+
+void clear_rowsort_counts(uint32_t *counts, hipStream_t s) {
+    k_zero3<<<1, 64, 0, s>>>(counts);
+    SJ_LAUNCH_CHECK();
 }
 
 void launch_rowsort_cells(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,

@@ -74,7 +74,7 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int D, bool kUni, int kMode, bool kBand>
+template <int D, bool kUni, int kMode, bool kBand, int NS>
 __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t) {
     constexpr int TS = TileSize<D>::value;
     using CT = typename std::conditional<kBand, float, double>::type;
@@ -246,6 +246,32 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             }
         }
         if (kMode == kCount && active) a.own_cnt[p] = own;
+        if (kMode == kFill && NS > 0 && !kUni && active) {
+            // the row of p is complete: sort it in registers and write the
+            // pairs, or queue it for the row-sort kernels if it is longer
+            const uint32_t len = own;
+            if (len <= static_cast<uint32_t>(NS)) {
+                constexpr int kNs = NS > 0 ? NS : 1;
+                uint32_t v[kNs];
+#pragma unroll
+                for (int k = 0; k < NS; ++k)
+                    v[k] = static_cast<uint32_t>(k) < len ? a.out_j[my_row + k] : 0xffffffffu;
+                register_bitonic<kNs>(v);
+                const uint64_t o = a.off_orig[perm_p];
+#pragma unroll
+                for (int k = 0; k < NS; ++k)
+                    if (static_cast<uint32_t>(k) < len) a.pairs[o + k] = make_uint2(perm_p, v[k]);
+            } else if (len <= 64) {
+                const uint32_t at = atomicAdd(&a.sort_counts[2], 1u);
+                a.sort_lists[2ull * a.n + at] = p;
+            } else if (len <= 1024) {
+                const uint32_t at = atomicAdd(&a.sort_counts[0], 1u);
+                a.sort_lists[at] = p;
+            } else {
+                const uint32_t at = atomicAdd(&a.sort_counts[1], 1u);
+                a.sort_lists[static_cast<uint64_t>(a.n) + at] = p;
+            }
+        }
     }
     if (kMode == kCount) {
         add_counter(a.evals, evals);
@@ -258,28 +284,35 @@ const char *const kTiledNames[8] = {"tiled_count_full_fp64", "tiled_count_full_f
                                     "tiled_fill_full_fp64", "tiled_fill_full_fp32band",
                                     "tiled_fill_unicomp_fp64", "tiled_fill_unicomp_fp32band"};
 
-template <int D, bool U, int M, bool BD>
+template <int D, bool U, int M, bool BD, int NS>
 void launch_tiled_one(const JoinArgs &a, const TileArgs &t, hipStream_t s) {
     const unsigned nb = (t.nchunks + kWaves - 1) / kWaves;
     if (nb == 0) return;
-    KTimer kt_(kTiledNames[M * 4 + (U ? 2 : 0) + (BD ? 1 : 0)], s);
-    k_join_tiled<D, U, M, BD><<<nb, kThreads, 0, s>>>(a, t);
+    KTimer kt_(NS ? (BD ? "tiled_fill_sort_full_fp32band" : "tiled_fill_sort_full_fp64")
+                  : kTiledNames[M * 4 + (U ? 2 : 0) + (BD ? 1 : 0)],
+               s);
+    k_join_tiled<D, U, M, BD, NS><<<nb, kThreads, 0, s>>>(a, t);
     SJ_LAUNCH_CHECK();
 }
 
 template <int D>
 void launch_tiled_d(const JoinArgs &a, const TileArgs &t, int unicomp, int mode, int band,
-                    hipStream_t s) {
+                    hipStream_t s, uint32_t fused_sort) {
     const int sel = (mode == kFill ? 4 : 0) + (unicomp ? 2 : 0) + (band ? 1 : 0);
+    if (sel == 4 && fused_sort == 16) return launch_tiled_one<D, false, kFill, false, 16>(a, t, s);
+    if (sel == 4 && fused_sort == 32) return launch_tiled_one<D, false, kFill, false, 32>(a, t, s);
+    if (sel == 5 && fused_sort == 16) return launch_tiled_one<D, false, kFill, true, 16>(a, t, s);
+    if (sel == 5 && fused_sort == 32) return launch_tiled_one<D, false, kFill, true, 32>(a, t, s);
+    if (fused_sort) throw Error(SJ_EINVAL, "tiled join: fused sort needs a full fill");
     switch (sel) {
-        case 0: launch_tiled_one<D, false, kCount, false>(a, t, s); break;
-        case 1: launch_tiled_one<D, false, kCount, true>(a, t, s); break;
-        case 2: launch_tiled_one<D, true, kCount, false>(a, t, s); break;
-        case 3: launch_tiled_one<D, true, kCount, true>(a, t, s); break;
-        case 4: launch_tiled_one<D, false, kFill, false>(a, t, s); break;
-        case 5: launch_tiled_one<D, false, kFill, true>(a, t, s); break;
-        case 6: launch_tiled_one<D, true, kFill, false>(a, t, s); break;
-        case 7: launch_tiled_one<D, true, kFill, true>(a, t, s); break;
+        case 0: launch_tiled_one<D, false, kCount, false, 0>(a, t, s); break;
+        case 1: launch_tiled_one<D, false, kCount, true, 0>(a, t, s); break;
+        case 2: launch_tiled_one<D, true, kCount, false, 0>(a, t, s); break;
+        case 3: launch_tiled_one<D, true, kCount, true, 0>(a, t, s); break;
+        case 4: launch_tiled_one<D, false, kFill, false, 0>(a, t, s); break;
+        case 5: launch_tiled_one<D, false, kFill, true, 0>(a, t, s); break;
+        case 6: launch_tiled_one<D, true, kFill, false, 0>(a, t, s); break;
+        case 7: launch_tiled_one<D, true, kFill, true, 0>(a, t, s); break;
         default: throw Error(SJ_EINVAL, "tiled join: bad mode");
     }
 }
@@ -428,16 +461,16 @@ void build_chunk_segments(const TileArgs &t, const uint32_t *cell_of, const uint
 }
 
 void launch_join_tiled(const JoinArgs &a, const TileArgs &t, uint32_t d, int unicomp, int mode,
-                       int band, hipStream_t s) {
+                       int band, hipStream_t s, uint32_t fused_sort) {
     switch (d) {
-        case 1: launch_tiled_d<1>(a, t, unicomp, mode, band, s); break;
-        case 2: launch_tiled_d<2>(a, t, unicomp, mode, band, s); break;
-        case 3: launch_tiled_d<3>(a, t, unicomp, mode, band, s); break;
-        case 4: launch_tiled_d<4>(a, t, unicomp, mode, band, s); break;
-        case 5: launch_tiled_d<5>(a, t, unicomp, mode, band, s); break;
-        case 6: launch_tiled_d<6>(a, t, unicomp, mode, band, s); break;
-        case 7: launch_tiled_d<7>(a, t, unicomp, mode, band, s); break;
-        case 8: launch_tiled_d<8>(a, t, unicomp, mode, band, s); break;
+        case 1: launch_tiled_d<1>(a, t, unicomp, mode, band, s, fused_sort); break;
+        case 2: launch_tiled_d<2>(a, t, unicomp, mode, band, s, fused_sort); break;
+        case 3: launch_tiled_d<3>(a, t, unicomp, mode, band, s, fused_sort); break;
+        case 4: launch_tiled_d<4>(a, t, unicomp, mode, band, s, fused_sort); break;
+        case 5: launch_tiled_d<5>(a, t, unicomp, mode, band, s, fused_sort); break;
+        case 6: launch_tiled_d<6>(a, t, unicomp, mode, band, s, fused_sort); break;
+        case 7: launch_tiled_d<7>(a, t, unicomp, mode, band, s, fused_sort); break;
+        case 8: launch_tiled_d<8>(a, t, unicomp, mode, band, s, fused_sort); break;
         default: throw Error(SJ_EINVAL, "tiled join: d out of range");
     }
 }

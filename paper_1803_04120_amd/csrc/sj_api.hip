@@ -349,6 +349,13 @@ sj::TileArgs tile_args(sj_index &ix) {
     return t;
 }
 
+// Row sort fused into the full fill (default) or run as its own kernels
+// (SJ_FUSED_SORT=0).
+bool use_fused_sort() {
+    const char *e = std::getenv("SJ_FUSED_SORT");
+    return !(e && std::strcmp(e, "0") == 0);
+}
+
 void ensure_chunks(sj_index &ix, hipStream_t s) {
     if (ix.chunks_ready) return;
     ix.cx.ensure(ix.n);
@@ -510,8 +517,27 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
         sj::launch_fill_u32(ix.cur.ptr, n, 0u, s);
         a.cur = ix.cur.ptr;
     }
+    sc.big_list.ensure(3 * std::max<uint64_t>(1, i1 - i0));
+    sc.big_count.ensure(3);
+    // whole result, full fill: each point's row is complete when its own
+    // evaluation ends, so the row sort runs inside the fill kernel
+    const bool fused = tiled && !unicomp_fill && whole && use_fused_sort();
     if (tiled) {
-        sj::launch_join_tiled(a, tile_args(ix), ix.d, mode, sj::kFill, ix.band_used, s);
+        uint32_t ns = 0;
+        if (fused) {
+            ns = ix.max_row <= 16 ? 16 : 32;
+            a.off_orig = ix.off_orig.ptr;
+            a.pairs = reinterpret_cast<uint2 *>(pairs);
+            a.sort_lists = sc.big_list.ptr;
+            a.sort_counts = sc.big_count.ptr;
+            sj::clear_rowsort_counts(sc.big_count.ptr, s);
+        }
+        sj::launch_join_tiled(a, tile_args(ix), ix.d, mode, sj::kFill, ix.band_used, s, ns);
+        if (fused) {
+            sj::launch_rowsort_queued(ix.off_cell.ptr, ix.off_orig.ptr, ix.perm.ptr, n, out_j, pairs,
+                                      sc.big_list.ptr, sc.big_count.ptr, ix.max_row, ns, s);
+            return;
+        }
     } else if (unicomp_fill) {
         sj::launch_join(a, ix.d, 1, sj::kFill, ix.band_used, s);
     } else {
@@ -526,8 +552,6 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
         }
         sj::launch_join(a, ix.d, 0, sj::kFill, ix.band_used, s);
     }
-    sc.big_list.ensure(3 * std::max<uint64_t>(1, i1 - i0));
-    sc.big_count.ensure(3);
     if (whole)
         sj::launch_rowsort_cells(ix.off_cell.ptr, ix.off_orig.ptr, ix.perm.ptr, n, out_j, pairs,
                                  sc.big_list.ptr, sc.big_count.ptr, ix.max_row, s);

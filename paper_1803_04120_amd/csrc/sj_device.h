@@ -66,6 +66,33 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *total, T *lds) {
     return before + incl - v;
 }
 
+// Sorts N values held in registers ascending with a fully unrolled bitonic
+// network (all register indices are compile-time constants).
+template <int N>
+__device__ __forceinline__ void register_bitonic(uint32_t (&v)[N]) {
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint32_t a = v[i], b = v[l];
+                    const uint32_t mn = a < b ? a : b, mx = a < b ? b : a;
+                    if ((i & k) == 0) {
+                        v[i] = mn;
+                        v[l] = mx;
+                    } else {
+                        v[i] = mx;
+                        v[l] = mn;
+                    }
+                }
+            }
+        }
+    }
+}
+
 // Counters that many workgroups add to are spread over kCounterSlots
 // addresses, one 128-byte line apart, so the additions do not serialise on a
 // single L2 line; the host sums the slots.

@@ -181,6 +181,14 @@ struct JoinArgs {
     // counters
     unsigned long long *evals;
     unsigned long long *band_rechecks;
+    // fill with the row sort fused in (each point's row is complete when its
+    // own evaluation ends): rows of at most the kernel's register-sort size
+    // are sorted and written as (i, j) pairs at off_orig[perm[p]]; longer
+    // rows stay in out_j and are queued (lists/counts as in the row sort)
+    const uint64_t *off_orig;
+    uint2 *pairs;
+    uint32_t *sort_lists;
+    uint32_t *sort_counts;
 };
 enum JoinMode { kCount = 0, kFill = 1 };
 void launch_join(const JoinArgs &a, uint32_t d, int unicomp, int mode, int band, hipStream_t s);
@@ -208,7 +216,7 @@ uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, const uint
 void build_chunk_segments(const TileArgs &t, const uint32_t *cell_of, const uint32_t *starts,
                           uint32_t d, uint2 *segs, hipStream_t s);
 void launch_join_tiled(const JoinArgs &a, const TileArgs &t, uint32_t d, int unicomp, int mode,
-                       int band, hipStream_t s);
+                       int band, hipStream_t s, uint32_t fused_sort = 0);
 
 // row lengths in original order, exclusive offsets (u64, n+1), row offsets
 // in cell order, max row length (device).
@@ -239,6 +247,11 @@ void launch_rowsort(const uint64_t *off, uint64_t i0, uint64_t i1, uint64_t base
 // Whole result filled in cell order: row r (cell-ordered point r) occupies
 // out_j[off_cell[r], off_cell[r+1]) and goes to pairs[off_orig[perm[r]], ...)
 // with i = perm[r]. lists holds 3 n entries, counts 3.
+// Sorts only the rows queued by a fused fill (longer than sorted_len).
+void launch_rowsort_queued(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,
+                           uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t *lists,
+                           uint32_t *counts, uint32_t max_len, uint32_t sorted_len, hipStream_t s);
+void clear_rowsort_counts(uint32_t *counts, hipStream_t s);
 void launch_rowsort_cells(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,
                           uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t *lists,
                           uint32_t *counts, uint32_t max_len, hipStream_t s);

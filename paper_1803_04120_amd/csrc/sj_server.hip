@@ -72,6 +72,7 @@ struct sj_server {
     uint64_t peak_mem = 0;
     uint32_t running = 0;
     uint32_t holders = 0;  // requests holding memory (running or results not released)
+    uint32_t waiting_mem = 0;  // running requests waiting for result memory
     uint64_t over_estimate = 0;
     uint64_t completed = 0;
     bool stop = false;
@@ -102,9 +103,17 @@ void run_request_dry(sj_server *S, Request *r, uint32_t slot) {
         if (need > r->held_bytes) {
             const uint64_t extra = need - r->held_bytes;
             ++S->over_estimate;
+            // Waits until the extra memory fits, or until no other request
+            // can free memory (it is the only holder, or every running
+            // request is itself waiting here): the budget is soft, progress
+            // is guaranteed.
+            ++S->waiting_mem;
+            S->cv_mem.notify_all();
             S->cv_mem.wait(lk, [&] {
-                return S->stop || S->mem_used + extra <= S->opts.mem_budget_bytes || S->holders <= 1;
+                return S->stop || S->mem_used + extra <= S->opts.mem_budget_bytes || S->holders <= 1 ||
+                       S->waiting_mem >= S->running;
             });
+            --S->waiting_mem;
             S->mem_used += extra;
             r->held_bytes += extra;
             S->peak_mem = std::max(S->peak_mem, S->mem_used);
@@ -141,9 +150,17 @@ void run_request(sj_server *S, Request *r, uint32_t slot, hipStream_t stream) {
         if (need > r->held_bytes) {
             const uint64_t extra = need - r->held_bytes;
             ++S->over_estimate;
+            // Waits until the extra memory fits, or until no other request
+            // can free memory (it is the only holder, or every running
+            // request is itself waiting here): the budget is soft, progress
+            // is guaranteed.
+            ++S->waiting_mem;
+            S->cv_mem.notify_all();
             S->cv_mem.wait(lk, [&] {
-                return S->stop || S->mem_used + extra <= S->opts.mem_budget_bytes || S->holders <= 1;
+                return S->stop || S->mem_used + extra <= S->opts.mem_budget_bytes || S->holders <= 1 ||
+                       S->waiting_mem >= S->running;
             });
+            --S->waiting_mem;
             S->mem_used += extra;
             r->held_bytes += extra;
             S->peak_mem = std::max(S->peak_mem, S->mem_used);

@@ -93,3 +93,23 @@ def test_open_loop_stream_latency_accounting(serve):
         assert c["latency_ms"] >= c["service_ms"] >= 0
         assert abs(c["latency_ms"] - c["queue_ms"] - c["service_ms"]) < 1e-6
     assert span > 0
+
+
+def test_no_deadlock_when_every_running_request_waits_for_memory(serve):
+    # four equal requests whose estimates exactly fill the budget; the even
+    # ids then need twice their estimated result and nobody releases until
+    # all are done: the waiting requests must still make progress
+    n, exp = 20000, 200000
+    per = None
+    with serve.Server(slots=4, mem_budget_bytes=1 << 40, dry_run=True) as probe:
+        rid = probe.submit(np.zeros((n, 2)), 1.0, expected_pairs=exp)
+        _drain(probe, 1)
+        per = probe.info()["peak_mem_bytes"]
+        probe.release(rid)
+    with serve.Server(slots=4, mem_budget_bytes=4 * per, dry_run=True) as srv:
+        ids = [srv.submit(np.zeros((n, 2)), 1.0, expected_pairs=exp) for _ in range(4)]
+        done = _drain(srv, 4)
+        assert sorted(done) == sorted(ids)
+        assert srv.info()["over_estimate"] >= 2
+        for i in ids:
+            srv.release(i)
