@@ -33,9 +33,12 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
-template <int D>
+// Candidates staged per tile; the fused fill keeps its rows in LDS too and
+// stages half as many.
+template <int D, int NS>
 struct TileSize {
-    static constexpr int value = D <= 3 ? 256 : (D <= 6 ? 128 : 64);
+    static constexpr int base = D <= 3 ? 256 : (D <= 6 ? 128 : 64);
+    static constexpr int value = NS > 0 ? base / 2 : base;
 };
 
 __device__ __forceinline__ uint32_t lb_u64(const uint64_t *__restrict__ B, uint32_t n, uint64_t key) {
@@ -76,18 +79,21 @@ __device__ __forceinline__ void wave_sync_lds() {
 
 template <int D, bool kUni, int kMode, bool kBand, int NS>
 __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t) {
-    constexpr int TS = TileSize<D>::value;
+    constexpr int TS = TileSize<D, NS>::value;
+    constexpr int kRowStride = NS + 1;  // padded so lanes' slots fall in different banks
     using CT = typename std::conditional<kBand, float, double>::type;
     constexpr bool kAgg = (kMode == kCount) && kUni;  // mirrored counts summed in LDS
     constexpr bool kPerm = (kMode == kFill);          // candidate ids staged in LDS
     __shared__ CT sx_all[kWaves][TS * D];
     __shared__ uint32_t sc_all[kWaves][TS];
     __shared__ uint32_t sa_all[kWaves][(kAgg || kPerm) ? TS : 1];
+    __shared__ uint32_t sr_all[kWaves][NS > 0 ? 64 * kRowStride : 1];
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
     CT *sx = sx_all[wave];
     uint32_t *scx = sc_all[wave];
     uint32_t *saux = sa_all[wave];
+    uint32_t *srow = sr_all[wave] + lane * (NS > 0 ? kRowStride : 0);
 
     uint32_t own = 0, evals = 0, rechecks = 0;
     const uint32_t chunk = blockIdx.x * kWaves + wave;
@@ -100,6 +106,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         uint32_t c0p = 0;
         uint64_t my_row = 0;
         uint32_t perm_p = 0;
+        uint32_t row_len = 0;  // fused fill: the row length from the count pass
         if (active) {
 #pragma unroll
             for (int j = 0; j < D; ++j) {
@@ -113,8 +120,11 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             if (kMode == kFill) {
                 my_row = a.offc[p] - a.out_base;
                 perm_p = a.perm[p];
+                if (NS > 0) row_len = static_cast<uint32_t>(a.offc[p + 1] - a.offc[p]);
             }
         }
+        // fused fill: rows that fit stay in the lane's LDS slot
+        const bool row_in_lds = NS > 0 && row_len <= static_cast<uint32_t>(NS);
         // chunk geometry (uniform)
         const uint32_t h_first = a.cell_of[ch.x];
         uint32_t c[D];
@@ -153,6 +163,12 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             if (kMode == kCount) {
                 ++own;
                 if (mirror) atomicAdd(&saux[i], 1u);
+            } else if (NS > 0 && row_in_lds) {
+                if (own < static_cast<uint32_t>(NS))
+                    srow[own] = saux[i];
+                else
+                    atomicOr(a.overflow, 1u);
+                ++own;
             } else {
                 const uint64_t at = my_row + own;
                 if (at < a.out_cap)
@@ -250,12 +266,12 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             // the row of p is complete: sort it in registers and write the
             // pairs, or queue it for the row-sort kernels if it is longer
             const uint32_t len = own;
-            if (len <= static_cast<uint32_t>(NS)) {
+            if (row_in_lds) {
                 constexpr int kNs = NS > 0 ? NS : 1;
                 uint32_t v[kNs];
 #pragma unroll
                 for (int k = 0; k < NS; ++k)
-                    v[k] = static_cast<uint32_t>(k) < len ? a.out_j[my_row + k] : 0xffffffffu;
+                    v[k] = static_cast<uint32_t>(k) < len ? srow[k] : 0xffffffffu;
                 register_bitonic<kNs>(v);
                 const uint64_t o = a.off_orig[perm_p];
 #pragma unroll
