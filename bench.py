@@ -73,6 +73,10 @@ def kernel_bytes(name, n, d, cells, ranges, pairs):
     if name.startswith("join_count") or name.startswith("tiled_count"):
         # X (d doubles) + cell of each point + its row length; cell range table
         return n * (8 * d + 4 + 4) + 8 * (cells + 1) + 8 * ranges
+    if name.startswith("tiled_fill_sort"):
+        # X + cell + cell-order row offset + permutation entry + the row's
+        # final offset per point, one (i, j) pair (8 bytes) per result pair
+        return n * (8 * d + 4 + 8 + 4 + 8) + 8 * pairs
     if name.startswith("join_fill") or name.startswith("tiled_fill"):
         # X + cell + row offset + permutation entry per point, range table,
         # one 4-byte neighbour id per pair
@@ -81,6 +85,48 @@ def kernel_bytes(name, n, d, cells, ranges, pairs):
         # row offsets, neighbour ids in, (i, j) pairs out
         return 8 * (n + 1) + 4 * pairs + 8 * pairs
     return None
+
+
+# Sources compiled into each family of modelled kernels: a traffic figure
+# measured with hardware counters is only reported while these are unchanged.
+KERNEL_SOURCES = {
+    "tiled_": ["k_tile.hip", "sj_device.h", "sj_internal.h"],
+    "join_": ["k_join.hip", "sj_device.h", "sj_internal.h"],
+    "rowsort_": ["k_rowsort.hip", "sj_device.h", "sj_internal.h"],
+}
+
+
+def kernel_source_hash(name):
+    import hashlib
+    for prefix, files in KERNEL_SOURCES.items():
+        if name.startswith(prefix):
+            h = hashlib.sha256()
+            for f in files:
+                with open(os.path.join(ROOT, "paper_1803_04120_amd", "csrc", f), "rb") as fh:
+                    h.update(fh.read())
+            return h.hexdigest()[:16]
+    return None
+
+
+def measured_traffic(name, workload):
+    """HBM bytes per launch of `name` on `workload` from the counter summary
+    under profiles/ (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
+    there is none or the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{name}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source_sha256_16") != kernel_source_hash(name):
+        return None
+    try:
+        return int(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def pipeline_bytes(n, d, cells, pairs):
@@ -261,7 +307,8 @@ def main():
     cnt, ms, byts = modelled[dom]
     achieved = byts / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dom, args.workload),
                 "avg_launch_us": round(1e3 * ms / cnt, 3),
                 "bytes_per_launch": int(byts / cnt)}
     pipe = sum(pipeline_bytes(n, d, i["cells"], i["pairs"]) for i in info)

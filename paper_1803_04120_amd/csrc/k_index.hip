@@ -22,10 +22,12 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Per-block partials: [min x kMaxDim][max x kMaxDim][non-finite flag].
+constexpr int kBboxPart = 2 * kMaxDim + 1;
+
 __global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *__restrict__ pts,
                                                             uint64_t n, uint32_t d,
-                                                            double *__restrict__ part,
-                                                            uint32_t *__restrict__ bad) {
+                                                            double *__restrict__ part) {
     double mn[kMaxDim], mx[kMaxDim];
 #pragma unroll
     for (int j = 0; j < kMaxDim; ++j) {
@@ -60,8 +62,12 @@ __global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *__restr
             smx[wave][j] = b;
         }
     }
-    if (ballot(flag != 0) != 0 && lane_id() == 0) atomicOr(bad, 1u);
+    __shared__ uint32_t sbad;
+    if (threadIdx.x == 0) sbad = 0;
     __syncthreads();
+    if (ballot(flag != 0) != 0 && lane_id() == 0) sbad = 1;
+    __syncthreads();
+    double *mine = part + static_cast<size_t>(blockIdx.x) * kBboxPart;
     if (threadIdx.x < kMaxDim) {
         const int j = threadIdx.x;
         double a = smn[0][j], b = smx[0][j];
@@ -69,23 +75,31 @@ __global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *__restr
             a = fmin(a, smn[w][j]);
             b = fmax(b, smx[w][j]);
         }
-        part[blockIdx.x * 2 * kMaxDim + j] = a;
-        part[blockIdx.x * 2 * kMaxDim + kMaxDim + j] = b;
+        mine[j] = a;
+        mine[kMaxDim + j] = b;
     }
+    if (threadIdx.x == 0) mine[2 * kMaxDim] = sbad ? 1.0 : 0.0;
 }
 
 // Second stage: one workgroup reduces the per-block partials (all threads
 // stride over the partials, then a wave/LDS reduction per dimension).
 __global__ __launch_bounds__(kThreads) void k_bbox_final(const double *__restrict__ part,
                                                           uint32_t nblocks, uint32_t d,
-                                                          double *__restrict__ out) {
+                                                          double *__restrict__ out,
+                                                          uint32_t *__restrict__ bad) {
     __shared__ double smn[kThreads / 64][kMaxDim], smx[kThreads / 64][kMaxDim];
     const int wave = threadIdx.x >> 6;
+    {
+        double f = 0.0;
+        for (uint32_t k = threadIdx.x; k < nblocks; k += kThreads) f = fmax(f, part[k * kBboxPart + 2 * kMaxDim]);
+        const bool any = __syncthreads_or(f != 0.0);
+        if (threadIdx.x == 0) *bad = any ? 1u : 0u;
+    }
     for (uint32_t j = 0; j < d; ++j) {
         double a = INFINITY, b = -INFINITY;
         for (uint32_t k = threadIdx.x; k < nblocks; k += kThreads) {
-            a = fmin(a, part[k * 2 * kMaxDim + j]);
-            b = fmax(b, part[k * 2 * kMaxDim + kMaxDim + j]);
+            a = fmin(a, part[k * kBboxPart + j]);
+            b = fmax(b, part[k * kBboxPart + kMaxDim + j]);
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -126,14 +140,6 @@ __global__ __launch_bounds__(kThreads) void k_cell_keys(const double *__restrict
     }
     keys[i] = static_cast<K>(key);
     ids[i] = static_cast<uint32_t>(i);
-}
-
-template <typename K>
-__global__ __launch_bounds__(kThreads) void k_head_flags(const K *__restrict__ k, uint64_t n,
-                                                          uint32_t *__restrict__ flag) {
-    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
-    if (r >= n) return;
-    flag[r] = (r == 0 || k[r] != k[r - 1]) ? 1u : 0u;
 }
 
 template <typename K>
@@ -202,10 +208,15 @@ __global__ __launch_bounds__(kThreads) void k_cell_coords(const uint64_t *__rest
             if (lmask[i]) atomicOr(&masks[i], lmask[i]);
 }
 
-__global__ void k_zero_u32(uint32_t *p, uint64_t n) {
-    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
-        p[i] = 0;
+// Zeroes p[0..n) and q[0..m) in one launch.
+__global__ void k_zero2_u32(uint32_t *p, uint64_t n, uint32_t *q, uint64_t m) {
+    const uint64_t step = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n + m; i += step) {
+        if (i < n)
+            p[i] = 0;
+        else
+            q[i - n] = 0;
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_gather_soa(const double *__restrict__ pts,
@@ -240,6 +251,23 @@ inline unsigned blocks_for(uint64_t n) {
 
 }  // namespace
 
+// Zeroes up to four word ranges with one launch.
+__global__ void k_zero_spans(ZeroSpans z) {
+    const uint64_t step = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    const uint64_t tid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+    for (int k = 0; k < z.count; ++k)
+        for (uint64_t i = tid; i < z.words[k]; i += step) z.p[k][i] = 0;
+}
+
+void launch_zero_spans(const ZeroSpans &z, hipStream_t s) {
+    uint64_t most = 0;
+    for (int k = 0; k < z.count; ++k) most = std::max<uint64_t>(most, z.words[k]);
+    if (!most) return;
+    const unsigned nb = static_cast<unsigned>(std::min<uint64_t>(2048, (most + kThreads - 1) / kThreads));
+    k_zero_spans<<<nb, kThreads, 0, s>>>(z);
+    SJ_LAUNCH_CHECK();
+}
+
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
     if (!n) return;
     const unsigned nb = static_cast<unsigned>(std::min<uint64_t>(4096, (n + kThreads - 1) / kThreads));
@@ -269,15 +297,13 @@ void launch_make_f32(const double *X, uint64_t n, uint32_t d, const double *shif
 void launch_bbox(const double *pts, uint64_t n, uint32_t d, double *bbox_out, uint32_t *bad,
                  hipStream_t s) {
     const uint32_t nb = static_cast<uint32_t>(std::min<uint64_t>(1024, (n + kThreads - 1) / kThreads));
-    DevBuf<double> part(static_cast<size_t>(nb) * 2 * kMaxDim);
-    k_zero_u32<<<1, 64, 0, s>>>(bad, 1);
-    SJ_LAUNCH_CHECK();
+    DevBuf<double> part(static_cast<size_t>(nb) * kBboxPart);
     {
         KTimer kt_("bbox", s);
-        k_bbox_partial<<<nb, kThreads, 0, s>>>(pts, n, d, part.ptr, bad);
+        k_bbox_partial<<<nb, kThreads, 0, s>>>(pts, n, d, part.ptr);
         SJ_LAUNCH_CHECK();
     }
-    k_bbox_final<<<1, kThreads, 0, s>>>(part.ptr, nb, d, bbox_out);
+    k_bbox_final<<<1, kThreads, 0, s>>>(part.ptr, nb, d, bbox_out, bad);
     SJ_LAUNCH_CHECK();
 }
 
@@ -302,9 +328,7 @@ void launch_cell_keys_u32(const double *pts, uint64_t n, const GridParams &g, ui
 template <typename K>
 uint64_t build_cells(const K *sorted_keys, uint64_t n, uint32_t *cell_of, uint64_t *B,
                      uint32_t *starts, hipStream_t s) {
-    k_head_flags<K><<<blocks_for(n), kThreads, 0, s>>>(sorted_keys, n, cell_of);
-    SJ_LAUNCH_CHECK();
-    scan_inclusive_u32(cell_of, n, s);
+    scan_head_flags_inclusive<K>(sorted_keys, cell_of, n, s);
     uint32_t ncells = 0;
     SJ_HIP(hipMemcpyAsync(&ncells, cell_of + (n - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     {
@@ -325,11 +349,8 @@ void launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_
                               const GridParams &g, uint32_t *coords, uint32_t *masks,
                               const uint32_t *mask_off, uint32_t mask_words, uint32_t *max_pts,
                               hipStream_t s) {
-    if (masks) {
-        k_zero_u32<<<64, 256, 0, s>>>(masks, mask_words);
-        SJ_LAUNCH_CHECK();
-    }
-    k_zero_u32<<<1, 64, 0, s>>>(max_pts, 1);
+    const uint64_t mw = masks ? mask_words : 0;
+    k_zero2_u32<<<static_cast<unsigned>(std::min<uint64_t>(64, mw / 256 + 1)), 256, 0, s>>>(masks, mw, max_pts, 1);
     SJ_LAUNCH_CHECK();
     const unsigned nb = static_cast<unsigned>(std::min<uint64_t>(256, (ncells + kThreads - 1) / kThreads));
     {

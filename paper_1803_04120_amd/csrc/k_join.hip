@@ -435,6 +435,49 @@ void launch_row_lengths(const uint32_t *own_cnt, const uint32_t *in_cnt, const u
     SJ_LAUNCH_CHECK();
 }
 
+// out[0] = P (off_orig[n]), out[1] = longest row, out[2] = evaluations,
+// out[3] = band re-checks (both summed over the counter slots), out[4] =
+// chunk count (0 without chunks): the count pass reads these back at once.
+__global__ __launch_bounds__(256) void k_count_summary(const uint64_t *__restrict__ off_orig, uint64_t n,
+                                                        const uint32_t *__restrict__ max_len,
+                                                        const unsigned long long *__restrict__ counters,
+                                                        const uint32_t *__restrict__ nchunks,
+                                                        uint64_t *__restrict__ out) {
+    __shared__ unsigned long long part[2][256 / 64];
+    const int k = threadIdx.x;  // one counter slot per thread
+    unsigned long long e = counters[static_cast<size_t>(k) * kCounterStride];
+    unsigned long long b = counters[static_cast<size_t>(kCounterSlots + k) * kCounterStride];
+    for (int off = 32; off > 0; off >>= 1) {
+        e += __shfl_xor(e, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    if (lane_id() == 0) {
+        part[0][k >> 6] = e;
+        part[1][k >> 6] = b;
+    }
+    __syncthreads();
+    if (k == 0) {
+        unsigned long long se = 0, sb = 0;
+        for (int w = 0; w < 256 / 64; ++w) {
+            se += part[0][w];
+            sb += part[1][w];
+        }
+        out[0] = off_orig[n];
+        out[1] = *max_len;
+        out[2] = se;
+        out[3] = sb;
+        out[4] = nchunks ? *nchunks : 0;
+    }
+}
+
+void launch_count_summary(const uint64_t *off_orig, uint64_t n, const uint32_t *max_len,
+                          const unsigned long long *counters, const uint32_t *nchunks, uint64_t *out,
+                          hipStream_t s) {
+    static_assert(kCounterSlots == 256, "one thread per counter slot");
+    k_count_summary<<<1, 256, 0, s>>>(off_orig, n, max_len, counters, nchunks, out);
+    SJ_LAUNCH_CHECK();
+}
+
 void launch_gather_offsets(const uint64_t *off_orig, const uint32_t *perm, uint64_t n,
                            uint64_t *offc, hipStream_t s) {
     KTimer kt_("row_offsets_gather", s);

@@ -17,8 +17,9 @@
 //   <= 16384  one workgroup per row, bitonic network in 64 KiB of LDS
 //   larger    one workgroup per row, bitonic network in global memory, using
 //             the row's own output segment (twice the row's size) as scratch
-// Rows too long for the lane kernel are queued (device-side lists) for the
-// wave and workgroup kernels, whose grids loop over the queues.
+// Each longer-row kernel scans the row offsets for the rows of its own size
+// class (64 rows per wave and ballot), so no kernel appends rows to a shared
+// queue: a queue counter is one address that every producer hits.
 //
 // Row r's neighbour ids are read from out_j[in_off[r] - in_base, +len) and
 // its pairs are written at pairs[out_off[id] - out_base, +len) with
@@ -81,25 +82,12 @@ __device__ __forceinline__ void bitonic_pair(uint32_t q, uint32_t j, uint32_t k,
 
 template <int N>
 __global__ __launch_bounds__(kThreads) void k_rowsort_lane(RowMap m, const uint32_t *__restrict__ out_j,
-                                                            uint2 *__restrict__ pairs,
-                                                            uint32_t *__restrict__ lists,
-                                                            uint32_t *__restrict__ counts) {
+                                                            uint2 *__restrict__ pairs) {
     const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
     if (r >= m.rows) return;
+    const uint32_t len = static_cast<uint32_t>(m.in_off[r + 1] - m.in_off[r]);
+    if (len > static_cast<uint32_t>(N)) return;  // a longer-row kernel sorts it
     const RowRef x = row_ref(m, r);
-    if (x.len > static_cast<uint32_t>(N)) {
-        if (x.len <= 64) {
-            const uint32_t at = atomicAdd(&counts[2], 1u);
-            lists[2 * m.rows + at] = static_cast<uint32_t>(r);
-        } else if (x.len <= kWaveCap) {
-            const uint32_t at = atomicAdd(&counts[0], 1u);
-            lists[at] = static_cast<uint32_t>(r);
-        } else {
-            const uint32_t at = atomicAdd(&counts[1], 1u);
-            lists[m.rows + at] = static_cast<uint32_t>(r);
-        }
-        return;
-    }
     uint32_t v[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) v[k] = static_cast<uint32_t>(k) < x.len ? out_j[x.in + k] : kPad;
@@ -109,29 +97,45 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_lane(RowMap m, const uint3
         if (static_cast<uint32_t>(k) < x.len) pairs[x.out + k] = make_uint2(x.id, v[k]);
 }
 
+// Rows of 64 consecutive row indices per wave: the mask of those whose
+// length lies in (lo, hi]. Uniform across the wave.
+__device__ __forceinline__ uint64_t class_mask(const RowMap &m, uint64_t base, uint32_t lo, uint32_t hi) {
+    const uint64_t r = base + static_cast<uint64_t>(lane_id());
+    uint32_t len = 0;
+    if (r < m.rows) len = static_cast<uint32_t>(m.in_off[r + 1] - m.in_off[r]);
+    return ballot(len > lo && len <= hi);
+}
+
 // Rows of up to 64 entries, 16 lanes per row (4 rows per wave): lane l holds
 // elements e = 16 k + l, k = 0..3; bitonic stages with a partner distance of
 // 16 or more exchange registers within the lane, shorter ones exchange with
 // lane l ^ j of the same 16-lane group. Each row is read and written by 16
 // consecutive lanes at consecutive addresses.
 __global__ __launch_bounds__(kThreads) void k_rowsort_group16(RowMap m, const uint32_t *__restrict__ out_j,
-                                                               uint2 *__restrict__ pairs,
-                                                               const uint32_t *__restrict__ list,
-                                                               const uint32_t *__restrict__ count) {
-    const uint32_t nrows = *count;
-    const uint32_t groups = gridDim.x * (kThreads / 16);
+                                                               uint2 *__restrict__ pairs, uint32_t lo) {
     const uint32_t l = threadIdx.x & 15u;
-    // the loop bound is uniform across the wave, so all 16-lane groups of a
-    // wave take part in every shuffle
-    const uint32_t first = blockIdx.x * (kThreads / 16) + (threadIdx.x >> 4);
-    const uint32_t wave_first = blockIdx.x * (kThreads / 16) + ((threadIdx.x >> 6) << 2);
-    for (uint32_t base = wave_first; base < nrows; base += groups) {
-    const uint32_t g = first + (base - wave_first);
-    const bool valid = g < nrows;
+    const uint32_t grp = (threadIdx.x >> 4) & 3u;  // 16-lane group within the wave
+    const uint64_t waves = static_cast<uint64_t>(gridDim.x) * kWaves;
+    for (uint64_t base = (blockIdx.x * static_cast<uint64_t>(kWaves) + (threadIdx.x >> 6)) * 64; base < m.rows;
+         base += waves * 64) {
+    uint64_t mask = class_mask(m, base, lo, 64);
+    // four rows of the class per pass, one per 16-lane group; the loop is
+    // uniform across the wave, so every group takes part in every shuffle
+    while (mask) {
+    uint64_t take = mask;
+    int pick = -1;
+#pragma unroll
+    for (uint32_t g = 0; g < 4; ++g) {
+        if (take) {
+            const int b0 = __builtin_ctzll(take);
+            if (g == grp) pick = b0;
+            take &= take - 1;
+        }
+    }
+    mask = take;
+    const bool mine = pick >= 0;
     RowRef x{0, 0, 0, 0};
-    if (valid) x = row_ref(m, list[g]);
-    const bool big = false;
-    const bool mine = valid && !big;
+    if (mine) x = row_ref(m, base + static_cast<uint64_t>(pick));
     uint32_t v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -175,20 +179,21 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_group16(RowMap m, const ui
         if (mine && e < x.len) pairs[x.out + e] = make_uint2(x.id, v[k]);
     }
     }
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_rowsort_wave(RowMap m,
                                                             const uint32_t *__restrict__ out_j,
-                                                            uint2 *__restrict__ pairs,
-                                                            const uint32_t *__restrict__ list,
-                                                            const uint32_t *__restrict__ count) {
+                                                            uint2 *__restrict__ pairs) {
     __shared__ uint32_t slot[kWaves][kWaveCap];
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
-    const uint32_t nrows = *count;
     volatile uint32_t *sh = slot[wave];
-    for (uint32_t w = blockIdx.x * kWaves + wave; w < nrows; w += gridDim.x * kWaves) {
-        const RowRef x = row_ref(m, list[w]);
+    const uint64_t waves = static_cast<uint64_t>(gridDim.x) * kWaves;
+    for (uint64_t base = (blockIdx.x * static_cast<uint64_t>(kWaves) + wave) * 64; base < m.rows;
+         base += waves * 64)
+    for (uint64_t mask = class_mask(m, base, 64, kWaveCap); mask; mask &= mask - 1) {
+        const RowRef x = row_ref(m, base + static_cast<uint64_t>(__builtin_ctzll(mask)));
         const uint32_t len = x.len;
         const uint32_t N = next_pow2(len);
         for (uint32_t e = lane; e < N; e += 64) sh[e] = e < len ? out_j[x.in + e] : kPad;
@@ -215,13 +220,22 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_wave(RowMap m,
 
 __global__ __launch_bounds__(kThreads) void k_rowsort_big(RowMap m,
                                                            uint32_t *__restrict__ out_j,
-                                                           uint2 *__restrict__ pairs,
-                                                           const uint32_t *__restrict__ big_list,
-                                                           const uint32_t *__restrict__ big_count) {
+                                                           uint2 *__restrict__ pairs) {
     __shared__ uint32_t sh[kBlockCap];
-    const uint32_t nbig = *big_count;
-    for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
-        const RowRef x = row_ref(m, big_list[b]);
+    __shared__ uint32_t sel[kThreads];
+    __shared__ uint32_t nsel;
+    for (uint64_t base = blockIdx.x * static_cast<uint64_t>(kThreads); base < m.rows;
+         base += static_cast<uint64_t>(gridDim.x) * kThreads) {
+    if (threadIdx.x == 0) nsel = 0;
+    __syncthreads();
+    {
+        const uint64_t r = base + threadIdx.x;
+        if (r < m.rows && m.in_off[r + 1] - m.in_off[r] > kWaveCap) sel[atomicAdd(&nsel, 1u)] = threadIdx.x;
+    }
+    __syncthreads();
+    const uint32_t count = nsel;
+    for (uint32_t b = 0; b < count; ++b) {
+        const RowRef x = row_ref(m, base + sel[b]);
         const uint64_t s = x.in, so = x.out;
         const uint32_t len = x.len;
         const uint32_t N = next_pow2(len);
@@ -276,103 +290,73 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_big(RowMap m,
         for (uint32_t e = threadIdx.x; e < len; e += kThreads) pairs[so + e] = make_uint2(r32, out_j[s + e]);
         __syncthreads();
     }
-}
-
-__global__ void k_zero3(uint32_t *p) {
-    if (threadIdx.x < 3) p[threadIdx.x] = 0;
+    __syncthreads();  // sel and nsel are rewritten for the next 256 rows
+    }
 }
 
 template <int N>
-void launch_lane(const RowMap &m, const uint32_t *out_j, uint2 *pairs, uint32_t *lists,
-                 uint32_t *counts, hipStream_t s) {
+void launch_lane(const RowMap &m, const uint32_t *out_j, uint2 *pairs, hipStream_t s) {
     const uint64_t nb = (m.rows + kThreads - 1) / kThreads;
     KTimer kt_("rowsort_lane", s);
-    k_rowsort_lane<N><<<static_cast<unsigned>(nb), kThreads, 0, s>>>(m, out_j, pairs, lists, counts);
+    k_rowsort_lane<N><<<static_cast<unsigned>(nb), kThreads, 0, s>>>(m, out_j, pairs);
     SJ_LAUNCH_CHECK();
 }
 
-void rowsort(const RowMap &m, uint32_t *out_j, uint32_t *pairs, uint32_t *lists, uint32_t *counts,
-             uint32_t max_len, hipStream_t s) {
-    if (m.rows == 0) return;
-    if (m.rows > 0x7fffffffULL) throw Error(SJ_EINVAL, "row sort: too many rows");
-    k_zero3<<<1, 64, 0, s>>>(counts);
-    SJ_LAUNCH_CHECK();
-    uint2 *p2 = reinterpret_cast<uint2 *>(pairs);
-    if (max_len <= 16)
-        launch_lane<16>(m, out_j, p2, lists, counts, s);
-    else
-        launch_lane<32>(m, out_j, p2, lists, counts, s);
-    if (max_len > 32) {
+// Rows longer than `sorted` (already sorted by the lane kernel or the fill).
+void rowsort_long(const RowMap &m, uint32_t *out_j, uint2 *p2, uint32_t max_len, uint32_t sorted,
+                  hipStream_t s) {
+    const uint64_t chunks64 = (m.rows + 63) / 64;
+    const unsigned grid = static_cast<unsigned>(std::min<uint64_t>((chunks64 + kWaves - 1) / kWaves, 8192));
+    if (max_len > sorted && sorted < 64) {
         KTimer kt_("rowsort_group16", s);
-        const uint64_t want = (m.rows + 15) / 16;
-        k_rowsort_group16<<<static_cast<unsigned>(std::min<uint64_t>(want, 4096)), kThreads, 0, s>>>(
-            m, out_j, p2, lists + 2 * m.rows, counts + 2);
+        k_rowsort_group16<<<grid, kThreads, 0, s>>>(m, out_j, p2, sorted);
         SJ_LAUNCH_CHECK();
     }
     if (max_len > 64) {
-        {
-            KTimer kt_("rowsort_wave", s);
-            const uint64_t want = (m.rows + kWaves - 1) / kWaves;
-            k_rowsort_wave<<<static_cast<unsigned>(std::min<uint64_t>(want, 8192)), kThreads, 0, s>>>(
-                m, out_j, p2, lists, counts);
-            SJ_LAUNCH_CHECK();
-        }
-        if (max_len > kWaveCap) {
-            KTimer kt_("rowsort_big", s);
-            k_rowsort_big<<<512, kThreads, 0, s>>>(m, out_j, p2, lists + m.rows, counts + 1);
-            SJ_LAUNCH_CHECK();
-        }
+        KTimer kt_("rowsort_wave", s);
+        k_rowsort_wave<<<grid, kThreads, 0, s>>>(m, out_j, p2);
+        SJ_LAUNCH_CHECK();
     }
+    if (max_len > kWaveCap) {
+        KTimer kt_("rowsort_big", s);
+        const unsigned gb = static_cast<unsigned>(std::min<uint64_t>((m.rows + kThreads - 1) / kThreads, 2048));
+        k_rowsort_big<<<gb, kThreads, 0, s>>>(m, out_j, p2);
+        SJ_LAUNCH_CHECK();
+    }
+}
+
+void rowsort(const RowMap &m, uint32_t *out_j, uint32_t *pairs, uint32_t max_len, hipStream_t s) {
+    if (m.rows == 0) return;
+    if (m.rows > 0x7fffffffULL) throw Error(SJ_EINVAL, "row sort: too many rows");
+    uint2 *p2 = reinterpret_cast<uint2 *>(pairs);
+    if (max_len <= 16)
+        launch_lane<16>(m, out_j, p2, s);
+    else
+        launch_lane<32>(m, out_j, p2, s);
+    rowsort_long(m, out_j, p2, max_len, max_len <= 16 ? 16 : 32, s);
 }
 
 }  // namespace
 
 void launch_rowsort(const uint64_t *off, uint64_t i0, uint64_t i1, uint64_t base, uint32_t *out_j,
-                    uint32_t *pairs, uint32_t *lists, uint32_t *counts, uint32_t max_len,
-                    hipStream_t s) {
+                    uint32_t *pairs, uint32_t max_len, hipStream_t s) {
     if (i1 <= i0) return;
     RowMap m{off + i0, base, off, base, nullptr, i0, i1 - i0};
-    rowsort(m, out_j, pairs, lists, counts, max_len, s);
+    rowsort(m, out_j, pairs, max_len, s);
 }
 
-void launch_rowsort_queued(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,
-                           uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t *lists,
-                           uint32_t *counts, uint32_t max_len, uint32_t sorted_len, hipStream_t s) {
+void launch_rowsort_long(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,
+                         uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t max_len, uint32_t sorted_len,
+                         hipStream_t s) {
+    if (n == 0) return;
     RowMap m{off_cell, 0, off_orig, 0, perm, 0, n};
-    uint2 *p2 = reinterpret_cast<uint2 *>(pairs);
-    if (max_len > sorted_len) {
-        KTimer kt_("rowsort_group16", s);
-        const uint64_t want = (n + 15) / 16;
-        k_rowsort_group16<<<static_cast<unsigned>(std::min<uint64_t>(want, 4096)), kThreads, 0, s>>>(
-            m, out_j, p2, lists + 2 * n, counts + 2);
-        SJ_LAUNCH_CHECK();
-    }
-    if (max_len > 64) {
-        {
-            KTimer kt_("rowsort_wave", s);
-            const uint64_t want = (n + kWaves - 1) / kWaves;
-            k_rowsort_wave<<<static_cast<unsigned>(std::min<uint64_t>(want, 8192)), kThreads, 0, s>>>(
-                m, out_j, p2, lists, counts);
-            SJ_LAUNCH_CHECK();
-        }
-        if (max_len > kWaveCap) {
-            KTimer kt_("rowsort_big", s);
-            k_rowsort_big<<<512, kThreads, 0, s>>>(m, out_j, p2, lists + n, counts + 1);
-            SJ_LAUNCH_CHECK();
-        }
-    }
-}
-
-void clear_rowsort_counts(uint32_t *counts, hipStream_t s) {
-    k_zero3<<<1, 64, 0, s>>>(counts);
-    SJ_LAUNCH_CHECK();
+    rowsort_long(m, out_j, reinterpret_cast<uint2 *>(pairs), max_len, sorted_len, s);
 }
 
 void launch_rowsort_cells(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,
-                          uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t *lists,
-                          uint32_t *counts, uint32_t max_len, hipStream_t s) {
+                          uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t max_len, hipStream_t s) {
     RowMap m{off_cell, 0, off_orig, 0, perm, 0, n};
-    rowsort(m, out_j, pairs, lists, counts, max_len, s);
+    rowsort(m, out_j, pairs, max_len, s);
 }
 
 }  // namespace sj

@@ -1,6 +1,13 @@
-// Device-wide prefix sums (reduce, scan the tile sums, rescan the tiles).
-// Used for the cell table (head flags), candidate-range offsets, result-row
-// offsets and the radix-sort digit tables.
+// Device-wide prefix sums. Used for the cell table (head flags), chunk and
+// row offsets, and the radix-sort digit tables.
+//
+// Two kernels: (1) every tile of 2048 inputs writes its sum; (2) every tile
+// adds up the sums of the tiles before it (all threads of the workgroup
+// share that reduction; at most 2048 tiles, ~4M inputs) and scans itself.
+// Longer inputs first scan the tile sums in place with a third kernel.
+// Inputs come through a loader, so a scan can consume a value computed on
+// the fly (the head flag of a sorted key, key[r] != key[r-1]) instead of a
+// materialised array.
 #include "sj_internal.h"
 #include "sj_device.h"
 
@@ -10,17 +17,44 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kItems = 8;
 constexpr int kTile = kThreads * kItems;
+constexpr size_t kInlineTiles = 2048;
 
-template <typename Tin, typename Tacc>
-__global__ __launch_bounds__(kThreads) void k_tile_sum(const Tin *__restrict__ in, size_t n,
-                                                        Tacc *__restrict__ part) {
+template <typename T>
+struct ArrayLoad {
+    const T *p;
+    __device__ __forceinline__ T operator()(size_t i) const { return p[i]; }
+};
+
+template <typename K>
+struct HeadFlagLoad {
+    const K *k;
+    __device__ __forceinline__ uint32_t operator()(size_t i) const {
+        return (i == 0 || k[i] != k[i - 1]) ? 1u : 0u;
+    }
+};
+
+// Up to two independent scans of the same length run in one launch
+// (blockIdx.y picks the operand set); each has its own tile-sum row.
+template <typename Tout, typename Load>
+struct ScanOps {
+    Load in[2];
+    Tout *out[2];
+    Tout *total[2];
+};
+
+template <typename Tacc, typename Load>
+__global__ __launch_bounds__(kThreads) void k_tile_sum(ScanOps<Tacc, Load> ops, size_t n,
+                                                        Tacc *__restrict__ part_all) {
     __shared__ Tacc lds[kThreads / 64];
+    const Load in = ops.in[blockIdx.y];
+    const size_t nb = (n + kTile - 1) / kTile;
+    Tacc *part = part_all + blockIdx.y * (nb + 1);
     const size_t base = static_cast<size_t>(blockIdx.x) * kTile;
     Tacc s = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const size_t i = base + static_cast<size_t>(k) * kThreads + threadIdx.x;
-        if (i < n) s += static_cast<Tacc>(in[i]);
+        if (i < n) s += static_cast<Tacc>(in(i));
     }
     Tacc tot;
     block_exclusive_scan<Tacc, kThreads>(s, &tot, lds);
@@ -29,8 +63,9 @@ __global__ __launch_bounds__(kThreads) void k_tile_sum(const Tin *__restrict__ i
 
 // Exclusive scan of part[0..m) in place by one block; part[m] gets the total.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scan_partials(T *__restrict__ part, size_t m) {
+__global__ __launch_bounds__(kThreads) void k_scan_partials(T *__restrict__ part_all, size_t m) {
     __shared__ T lds[kThreads / 64];
+    T *part = part_all + blockIdx.x * (m + 1);
     T carry = 0;
     for (size_t base = 0; base < m; base += kThreads) {
         const size_t i = base + threadIdx.x;
@@ -43,17 +78,42 @@ __global__ __launch_bounds__(kThreads) void k_scan_partials(T *__restrict__ part
     if (threadIdx.x == 0) part[m] = carry;
 }
 
-template <typename Tin, typename Tout, bool kInclusive>
-__global__ __launch_bounds__(kThreads) void k_tile_scan(const Tin *in, Tout *out, size_t n,
-                                                         const Tout *__restrict__ part,
-                                                         Tout *total_out) {
+// inline_prefix: part holds raw tile sums and every tile sums the ones before
+// it; otherwise part already holds the exclusive tile offsets (+ total at nb).
+template <typename Tout, bool kInclusive, typename Load>
+__global__ __launch_bounds__(kThreads) void k_tile_scan(ScanOps<Tout, Load> ops, size_t n,
+                                                         const Tout *__restrict__ part_all,
+                                                         int inline_prefix) {
     __shared__ Tout tile[kTile];
     __shared__ Tout lds[kThreads / 64];
+    const Load in = ops.in[blockIdx.y];
+    Tout *out = ops.out[blockIdx.y];
+    Tout *total_out = ops.total[blockIdx.y];
     const size_t base = static_cast<size_t>(blockIdx.x) * kTile;
+    const size_t nb = (n + kTile - 1) / kTile;
+    const Tout *part = part_all + blockIdx.y * (nb + 1);
+    Tout prefix = 0, grand = 0;
+    if (inline_prefix) {
+        Tout s = 0, all = 0;
+        for (size_t b = threadIdx.x; b < nb; b += kThreads) {
+            const Tout v = part[b];
+            if (b < blockIdx.x) s += v;
+            all += v;
+        }
+        Tout tot;
+        block_exclusive_scan<Tout, kThreads>(s, &tot, lds);
+        prefix = tot;
+        Tout tot2;
+        block_exclusive_scan<Tout, kThreads>(all, &tot2, lds);
+        grand = tot2;
+    } else {
+        prefix = part[blockIdx.x];
+        grand = part[nb];
+    }
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int i = k * kThreads + threadIdx.x;
-        tile[i] = (base + i < n) ? static_cast<Tout>(in[base + i]) : Tout(0);
+        tile[i] = (base + i < n) ? static_cast<Tout>(in(base + i)) : Tout(0);
     }
     __syncthreads();
     Tout loc[kItems];
@@ -64,7 +124,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(const Tin *in, Tout *out
         s += loc[k];
     }
     Tout tot;
-    Tout run = block_exclusive_scan<Tout, kThreads>(s, &tot, lds) + part[blockIdx.x];
+    Tout run = block_exclusive_scan<Tout, kThreads>(s, &tot, lds) + prefix;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         if (kInclusive) {
@@ -81,53 +141,74 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(const Tin *in, Tout *out
         const int i = k * kThreads + threadIdx.x;
         if (base + i < n) out[base + i] = tile[i];
     }
-    if (total_out && blockIdx.x == 0 && threadIdx.x == 0) {
-        const size_t nb = (n + kTile - 1) / kTile;
-        *total_out = part[nb];
-    }
+    if (total_out && blockIdx.x == 0 && threadIdx.x == 0) *total_out = grand;
 }
 
 template <typename T>
-__global__ void k_set_value(T *p, T v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+__global__ void k_set_values(T *p, T *q, T v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (p) *p = v;
+        if (q) *q = v;
+    }
 }
 
-template <typename Tin, typename Tout, bool kInclusive>
-void scan_impl(const Tin *in, Tout *out, size_t n, Tout *total_out, hipStream_t s) {
+// nscans = 1 or 2 (ops.in[1] etc. unused for one).
+template <typename Tout, bool kInclusive, typename Load>
+void scan_impl(const ScanOps<Tout, Load> &ops, unsigned nscans, size_t n, hipStream_t s) {
     if (n == 0) {
-        if (total_out) {
-            k_set_value<Tout><<<1, 64, 0, s>>>(total_out, Tout(0));
+        if (ops.total[0] || (nscans > 1 && ops.total[1])) {
+            k_set_values<Tout><<<1, 64, 0, s>>>(ops.total[0], nscans > 1 ? ops.total[1] : nullptr, Tout(0));
             SJ_LAUNCH_CHECK();
         }
         return;
     }
     const size_t nb = (n + kTile - 1) / kTile;
     if (nb > 0x7fffffffULL) throw Error(SJ_EINVAL, "scan: input too large");
-    DevBuf<Tout> part(nb + 1);
-    k_tile_sum<Tin, Tout><<<static_cast<unsigned>(nb), kThreads, 0, s>>>(in, n, part.ptr);
+    DevBuf<Tout> part(nscans * (nb + 1));
+    k_tile_sum<Tout, Load><<<dim3(static_cast<unsigned>(nb), nscans), kThreads, 0, s>>>(ops, n, part.ptr);
     SJ_LAUNCH_CHECK();
-    k_scan_partials<Tout><<<1, kThreads, 0, s>>>(part.ptr, nb);
-    SJ_LAUNCH_CHECK();
-    {
-        KTimer kt_("scan", s);
-        k_tile_scan<Tin, Tout, kInclusive><<<static_cast<unsigned>(nb), kThreads, 0, s>>>(
-            in, out, n, part.ptr, total_out);
+    const int inline_prefix = nb <= kInlineTiles ? 1 : 0;
+    if (!inline_prefix) {
+        k_scan_partials<Tout><<<nscans, kThreads, 0, s>>>(part.ptr, nb);
         SJ_LAUNCH_CHECK();
     }
+    KTimer kt_("scan", s);
+    k_tile_scan<Tout, kInclusive, Load><<<dim3(static_cast<unsigned>(nb), nscans), kThreads, 0, s>>>(
+        ops, n, part.ptr, inline_prefix);
+    SJ_LAUNCH_CHECK();
+}
+
+template <typename Tout, bool kInclusive, typename Load>
+void scan_one(Load in, Tout *out, size_t n, Tout *total, hipStream_t s) {
+    ScanOps<Tout, Load> ops{{in, in}, {out, out}, {total, nullptr}};
+    scan_impl<Tout, kInclusive, Load>(ops, 1, n, s);
 }
 
 }  // namespace
 
 void scan_exclusive_u32_to_u64(const uint32_t *in, uint64_t *out, size_t n, hipStream_t s) {
-    scan_impl<uint32_t, uint64_t, false>(in, out, n, out + n, s);
+    scan_one<uint64_t, false>(ArrayLoad<uint32_t>{in}, out, n, out + n, s);
+}
+
+void scan_exclusive_u32_to_u64_x2(const uint32_t *in0, uint64_t *out0, const uint32_t *in1,
+                                  uint64_t *out1, size_t n, hipStream_t s) {
+    ScanOps<uint64_t, ArrayLoad<uint32_t>> ops{{{in0}, {in1}}, {out0, out1}, {out0 + n, out1 + n}};
+    scan_impl<uint64_t, false>(ops, 2, n, s);
 }
 
 void scan_inclusive_u32(uint32_t *data, size_t n, hipStream_t s) {
-    scan_impl<uint32_t, uint32_t, true>(data, data, n, nullptr, s);
+    scan_one<uint32_t, true>(ArrayLoad<uint32_t>{data}, data, n, nullptr, s);
 }
 
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, hipStream_t s) {
-    scan_impl<uint32_t, uint32_t, false>(in, out, n, nullptr, s);
+    scan_one<uint32_t, false>(ArrayLoad<uint32_t>{in}, out, n, nullptr, s);
 }
+
+template <typename K>
+void scan_head_flags_inclusive(const K *sorted_keys, uint32_t *out, size_t n, hipStream_t s) {
+    scan_one<uint32_t, true>(HeadFlagLoad<K>{sorted_keys}, out, n, nullptr, s);
+}
+template void scan_head_flags_inclusive<uint32_t>(const uint32_t *, uint32_t *, size_t, hipStream_t);
+template void scan_head_flags_inclusive<uint64_t>(const uint64_t *, uint32_t *, size_t, hipStream_t);
 
 }  // namespace sj

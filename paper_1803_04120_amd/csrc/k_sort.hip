@@ -142,9 +142,9 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const K *__restrict__ ki
 }
 
 template <typename K>
-void radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, size_t n,
+bool radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, size_t n,
                      int bits, hipStream_t s) {
-    if (n <= 1 || bits <= 0) return;
+    if (n <= 1 || bits <= 0) return false;
     if (n >= 0xffffffffULL) throw Error(SJ_EINVAL, "radix sort: too many keys");
     const uint32_t ntiles = static_cast<uint32_t>((n + kTile - 1) / kTile);
     DevBuf<uint32_t> hist(static_cast<size_t>(kRadix) * ntiles);
@@ -168,22 +168,19 @@ void radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, s
         std::swap(src_v, dst_v);
         ++passes;
     }
-    if (passes & 1) {
-        SJ_HIP(hipMemcpyAsync(keys, src_k, n * sizeof(K), hipMemcpyDeviceToDevice, s));
-        SJ_HIP(hipMemcpyAsync(vals, src_v, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-    }
+    return (passes & 1) != 0;
 }
 
 }  // namespace
 
-void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
+bool radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
                     size_t n, int bits, hipStream_t s) {
-    radix_sort_impl<uint64_t>(keys, vals, keys_alt, vals_alt, n, bits, s);
+    return radix_sort_impl<uint64_t>(keys, vals, keys_alt, vals_alt, n, bits, s);
 }
 
-void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+bool radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                     size_t n, int bits, hipStream_t s) {
-    radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, bits, s);
+    return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, bits, s);
 }
 
 }  // namespace sj

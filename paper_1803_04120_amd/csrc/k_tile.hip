@@ -38,7 +38,8 @@ constexpr int kWaves = kThreads / 64;
 template <int D, int NS>
 struct TileSize {
     static constexpr int base = D <= 3 ? 256 : (D <= 6 ? 128 : 64);
-    static constexpr int value = NS > 0 ? base / 2 : base;
+    static constexpr int half = NS > 0 ? base / 2 : base;
+    static constexpr int value = half < 64 ? 64 : half;  // at least one candidate per lane
 };
 
 __device__ __forceinline__ uint32_t lb_u64(const uint64_t *__restrict__ B, uint32_t n, uint64_t key) {
@@ -84,29 +85,38 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     using CT = typename std::conditional<kBand, float, double>::type;
     constexpr bool kAgg = (kMode == kCount) && kUni;  // mirrored counts summed in LDS
     constexpr bool kPerm = (kMode == kFill);          // candidate ids staged in LDS
-    __shared__ CT sx_all[kWaves][TS * D];
+    // staged coordinates; the fused fill reuses the slot after the last
+    // tile for its write-out table (row destination, row id, length)
+    constexpr size_t kStageBytes = sizeof(CT) * TS * D;
+    constexpr size_t kOutBytes = NS > 0 ? 64 * (8 + 4 + 4) : 0;
+    __shared__ __align__(16) unsigned char sx_all[kWaves][kStageBytes > kOutBytes ? kStageBytes : kOutBytes];
     __shared__ uint32_t sc_all[kWaves][TS];
     __shared__ uint32_t sa_all[kWaves][(kAgg || kPerm) ? TS : 1];
     __shared__ uint32_t sr_all[kWaves][NS > 0 ? 64 * kRowStride : 1];
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
-    CT *sx = sx_all[wave];
+    CT *sx = reinterpret_cast<CT *>(sx_all[wave]);
+    uint64_t *swo = reinterpret_cast<uint64_t *>(sx_all[wave]);
+    uint32_t *swp = reinterpret_cast<uint32_t *>(sx_all[wave] + 64 * 8);
+    uint32_t *swl = reinterpret_cast<uint32_t *>(sx_all[wave] + 64 * 12);
     uint32_t *scx = sc_all[wave];
     uint32_t *saux = sa_all[wave];
     uint32_t *srow = sr_all[wave] + lane * (NS > 0 ? kRowStride : 0);
 
     uint32_t own = 0, evals = 0, rechecks = 0;
-    const uint32_t chunk = blockIdx.x * kWaves + wave;
-    if (chunk < t.nchunks) {  // uniform across the wave
+    const uint32_t chunk = xcd_block_index() * kWaves + wave;
+    if (chunk < *t.nchunks_dev) {  // uniform across the wave
         const uint2 ch = t.chunks[chunk];
         const uint32_t p = ch.x + static_cast<uint32_t>(lane);
         const bool active = p < ch.y;
         double xp[D];
         CT yp[D];
         uint32_t c0p = 0;
+        uint32_t p_cell_start = 0;  // first point of p's cell (unicomp)
         uint64_t my_row = 0;
         uint32_t perm_p = 0;
         uint32_t row_len = 0;  // fused fill: the row length from the count pass
+        uint64_t row_dst = 0;  // fused fill: offset of the row of p in the result
         if (active) {
 #pragma unroll
             for (int j = 0; j < D; ++j) {
@@ -117,10 +127,14 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                     yp[j] = static_cast<CT>(xp[j]);
             }
             c0p = t.cx[p];
+            if (kUni) p_cell_start = a.starts[a.cell_of[p]];
             if (kMode == kFill) {
                 my_row = a.offc[p] - a.out_base;
                 perm_p = a.perm[p];
-                if (NS > 0) row_len = static_cast<uint32_t>(a.offc[p + 1] - a.offc[p]);
+                if (NS > 0) {
+                    row_len = static_cast<uint32_t>(a.offc[p + 1] - a.offc[p]);
+                    row_dst = a.off_orig[perm_p];  // used at the end; loaded early
+                }
             }
         }
         // fused fill: rows that fit stay in the lane's LDS slot
@@ -186,49 +200,38 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 }
             }
         };
+        // candidates [i0, i1) of the staged tile, kUnroll tests in flight
+        constexpr int kUnroll = D <= 3 ? 4 : 2;
+        auto run = [&](uint32_t T0, uint32_t i0, uint32_t i1) {
+            if (i0 >= i1) return;
+            evals += i1 - i0;
+            uint32_t i = i0;
+            for (; i + kUnroll <= i1; i += kUnroll) {
+                bool h[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) h[u] = test(i + u, T0 + i + u);
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    if (h[u]) emit(i + u, T0 + i + u, kUni && T0 + i + u != p);
+            }
+            for (; i < i1; ++i)
+                if (test(i, T0 + i)) emit(i, T0 + i, kUni && T0 + i != p);
+        };
         auto evaluate_tile = [&](uint32_t T0, uint32_t len, bool own_row) {
             uint32_t lo_c = c0p > 0 ? c0p - 1 : 0, hi_c = c0p + 1;
             if (kUni && own_row && !(c0p & 1u)) lo_c = hi_c = c0p;
             if (scx[0] > hi_c || scx[len - 1] < lo_c) return;
             const uint32_t i_lo = lb_lds(scx, len, lo_c);
             const uint32_t i_hi = lb_lds(scx, len, hi_c + 1);
-            for (uint32_t i = i_lo; i < i_hi; ++i) {
-                const uint32_t q = T0 + i;
-                if (kUni && own_row && q < p && scx[i] == c0p) continue;
-                ++evals;
-                if (test(i, q)) emit(i, q, kUni && q != p);
-            }
-        };
-        // one candidate row (precomputed point segment of the chunk's window)
-        const uint2 *segs = t.segs + static_cast<size_t>(chunk) * t.rows_per_chunk;
-        auto process_row = [&](uint32_t ridx, bool own_row) {
-            const uint2 sg = segs[ridx];
-            const uint32_t P0 = sg.x, P1 = sg.y;
-            for (uint32_t T0 = P0; T0 < P1; T0 += TS) {
-                const uint32_t len = (P1 - T0) < static_cast<uint32_t>(TS) ? (P1 - T0) : TS;
-                wave_sync_lds();
-                for (uint32_t i = lane; i < len; i += 64) {
-#pragma unroll
-                    for (int j = 0; j < D; ++j) {
-                        if (kBand)
-                            sx[i * D + j] = static_cast<CT>(a.Y[static_cast<size_t>(j) * a.n + T0 + i]);
-                        else
-                            sx[i * D + j] = static_cast<CT>(a.X[static_cast<size_t>(j) * a.n + T0 + i]);
-                    }
-                    scx[i] = t.cx[T0 + i];
-                    if (kAgg) saux[i] = 0;
-                    if (kPerm) saux[i] = a.perm[T0 + i];
-                }
-                wave_sync_lds();
-                if (active) evaluate_tile(T0, len, own_row);
-                if (kAgg) {
-                    // one global add per candidate that collected mirrored hits
-                    wave_sync_lds();
-                    for (uint32_t i = lane; i < len; i += 64) {
-                        const uint32_t c = saux[i];
-                        if (c) atomicAdd(&a.in_cnt[T0 + i], c);
-                    }
-                }
+            if (kUni && own_row) {
+                // own cell as the triangle q >= p: skip q in [start of p's
+                // cell, p), a contiguous run of the tile
+                const uint32_t s_lo = p_cell_start > T0 ? (p_cell_start - T0 < len ? p_cell_start - T0 : len) : 0;
+                const uint32_t s_hi = p > T0 ? (p - T0 < len ? p - T0 : len) : 0;
+                run(T0, i_lo, i_hi < s_lo ? i_hi : s_lo);
+                run(T0, i_lo > s_hi ? i_lo : s_hi, i_hi);
+            } else {
+                run(T0, i_lo, i_hi);
             }
         };
         // Row index of an offset vector o (o_j in {-1,0,1}, j = 1..d-1):
@@ -241,51 +244,176 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 p3 *= 3;
             }
         }
-        if (!kUni) {
-            for (uint32_t r = 0; r < t.rows_per_chunk; ++r) process_row(r, r == own_idx);
-        } else {
-            process_row(own_idx, true);
-            // block k >= 1 (c_k odd): o_k = -1 or +1, o_j free for j < k, 0 above
-            uint32_t p3k = 1;  // 3^(k-1)
-            for (int k = 1; k < D; ++k) {
-                if (c[k] & 1u) {
-                    uint32_t upper = 0, p3 = p3k * 3;
-                    for (int j = k + 1; j < D; ++j) {
-                        upper += p3;  // o_j = 0 contributes 1 * 3^(j-1)
-                        p3 *= 3;
-                    }
-                    for (uint32_t side = 0; side <= 2; side += 2)
-                        for (uint32_t low = 0; low < p3k; ++low)
-                            process_row(upper + side * p3k + low, false);
-                }
-                p3k *= 3;
+        // The chunk's candidate rows as one stream of tiles. Full search: rows
+        // 0 .. 3^(d-1) - 1. unicomp: the own row, then for every k >= 1 with
+        // c_k odd the rows of block k (o_k = -1 or +1, o_j free for j < k,
+        // o_j = 0 above).
+        uint32_t odd_mask = 0;  // bit k: c_k odd
+#pragma unroll
+        for (int j = 1; j < D; ++j) odd_mask |= (c[j] & 1u) << j;
+        int st_k = 0;          // unicomp: 0 = own row next, else current block k
+        uint32_t st_p3k = 1;   // 3^(k-1)
+        uint32_t st_i = 0;     // position inside the current block (or row counter)
+        auto next_row = [&](uint32_t &ridx, bool &own_row) -> bool {
+            if (!kUni) {
+                if (st_i >= t.rows_per_chunk) return false;
+                ridx = st_i;
+                own_row = st_i == own_idx;
+                ++st_i;
+                return true;
             }
+            if (st_k == 0) {
+                st_k = 1;
+                st_p3k = 1;
+                st_i = 0;
+                ridx = own_idx;
+                own_row = true;
+                return true;
+            }
+            while (st_k < D) {
+                if (((odd_mask >> st_k) & 1u) && st_i < 2 * st_p3k) {
+                    const uint32_t upper = own_idx - (3 * st_p3k - 1) / 2;
+                    const uint32_t side = st_i < st_p3k ? 0u : 2u;
+                    const uint32_t low = st_i < st_p3k ? st_i : st_i - st_p3k;
+                    ridx = upper + side * st_p3k + low;
+                    own_row = false;
+                    ++st_i;
+                    return true;
+                }
+                ++st_k;
+                st_p3k *= 3;
+                st_i = 0;
+            }
+            return false;
+        };
+        // segment table of the chunk, 64 rows per register load
+        const uint2 *segs = t.segs + static_cast<size_t>(chunk) * t.rows_per_chunk;
+        uint32_t seg_base = 0xffffffffu;
+        uint2 seg_reg = make_uint2(0, 0);
+        auto segment = [&](uint32_t ridx) -> uint2 {
+            const uint32_t base = ridx & ~63u;
+            if (base != seg_base) {
+                seg_base = base;
+                const uint32_t r = base + static_cast<uint32_t>(lane);
+                seg_reg = r < t.rows_per_chunk ? segs[r] : make_uint2(0, 0);
+            }
+            const int l = static_cast<int>(ridx - base);
+            return make_uint2(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(seg_reg.x), l)),
+                              static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(seg_reg.y), l)));
+        };
+        // tile cursor: candidates [T0, min(T0 + TS, P1)) of row ridx
+        struct Tile {
+            uint32_t ridx, T0, P1;
+            bool own_row, valid;
+        };
+        auto advance = [&](Tile tl) -> Tile {
+            if (tl.valid && tl.T0 + TS < tl.P1) {
+                tl.T0 += TS;
+                return tl;
+            }
+            uint32_t r;
+            bool o;
+            while (next_row(r, o)) {
+                const uint2 sg = segment(r);
+                if (sg.x < sg.y) return Tile{r, sg.x, sg.y, o, true};
+            }
+            tl.valid = false;
+            return tl;
+        };
+        // candidates held in registers between their load and their LDS
+        // store, so the next tile's loads are in flight while this one is
+        // evaluated
+        constexpr int kPer = TS / 64;
+        CT rx[kPer][D];
+        uint32_t rc[kPer], ra[kPer];
+        auto load_tile = [&](const Tile &tl) {
+            const uint32_t len = (tl.P1 - tl.T0) < static_cast<uint32_t>(TS) ? (tl.P1 - tl.T0) : TS;
+#pragma unroll
+            for (int m = 0; m < kPer; ++m) {
+                const uint32_t i = static_cast<uint32_t>(lane + 64 * m);
+                if (i < len) {
+                    const size_t q = tl.T0 + i;
+#pragma unroll
+                    for (int j = 0; j < D; ++j)
+                        rx[m][j] = kBand ? static_cast<CT>(a.Y[static_cast<size_t>(j) * a.n + q])
+                                         : static_cast<CT>(a.X[static_cast<size_t>(j) * a.n + q]);
+                    rc[m] = t.cx[q];
+                    if (kPerm) ra[m] = a.perm[q];
+                }
+            }
+        };
+        // (the unicomp count adds mirrored hits to global counters after each
+        // tile; a prefetch would then wait for those atomics as well)
+        constexpr bool kPrefetch = !kAgg;
+        Tile cur = advance(Tile{0, 0, 0, false, false});
+        if (kPrefetch && cur.valid) load_tile(cur);
+        while (cur.valid) {
+            const uint32_t len = (cur.P1 - cur.T0) < static_cast<uint32_t>(TS) ? (cur.P1 - cur.T0) : TS;
+            wave_sync_lds();
+            if (!kPrefetch) load_tile(cur);
+#pragma unroll
+            for (int m = 0; m < kPer; ++m) {
+                const uint32_t i = static_cast<uint32_t>(lane + 64 * m);
+                if (i < len) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) sx[i * D + j] = rx[m][j];
+                    scx[i] = rc[m];
+                    if (kAgg) saux[i] = 0;
+                    if (kPerm) saux[i] = ra[m];
+                }
+            }
+            const Tile nxt = advance(cur);
+            if (kPrefetch && nxt.valid) load_tile(nxt);
+            wave_sync_lds();
+            if (active) evaluate_tile(cur.T0, len, cur.own_row);
+            if (kAgg) {
+                // one global add per candidate that collected mirrored hits
+                wave_sync_lds();
+                for (uint32_t i = lane; i < len; i += 64) {
+                    const uint32_t cnt = saux[i];
+                    if (cnt) atomicAdd(&a.in_cnt[cur.T0 + i], cnt);
+                }
+            }
+            cur = nxt;
         }
         if (kMode == kCount && active) a.own_cnt[p] = own;
-        if (kMode == kFill && NS > 0 && !kUni && active) {
-            // the row of p is complete: sort it in registers and write the
-            // pairs, or queue it for the row-sort kernels if it is longer
+        if (kMode == kFill && NS > 0 && !kUni) {
+            // the row of p is complete: sort it in registers, or queue it for
+            // the row-sort kernels if it is longer than the LDS slot
+            constexpr int kNs = NS > 0 ? NS : 1;
             const uint32_t len = own;
-            if (row_in_lds) {
-                constexpr int kNs = NS > 0 ? NS : 1;
+            uint32_t lds_len = 0;
+            if (active && row_in_lds) {
                 uint32_t v[kNs];
 #pragma unroll
-                for (int k = 0; k < NS; ++k)
+                for (int k = 0; k < kNs; ++k)
                     v[k] = static_cast<uint32_t>(k) < len ? srow[k] : 0xffffffffu;
                 register_bitonic<kNs>(v);
-                const uint64_t o = a.off_orig[perm_p];
 #pragma unroll
-                for (int k = 0; k < NS; ++k)
-                    if (static_cast<uint32_t>(k) < len) a.pairs[o + k] = make_uint2(perm_p, v[k]);
-            } else if (len <= 64) {
-                const uint32_t at = atomicAdd(&a.sort_counts[2], 1u);
-                a.sort_lists[2ull * a.n + at] = p;
-            } else if (len <= 1024) {
-                const uint32_t at = atomicAdd(&a.sort_counts[0], 1u);
-                a.sort_lists[at] = p;
-            } else {
-                const uint32_t at = atomicAdd(&a.sort_counts[1], 1u);
-                a.sort_lists[static_cast<uint64_t>(a.n) + at] = p;
+                for (int k = 0; k < kNs; ++k)
+                    if (static_cast<uint32_t>(k) < len) srow[k] = v[k];
+                lds_len = len;
+            }
+            wave_sync_lds();  // last tile's reads of the staging slot are done
+            swo[lane] = row_dst;
+            swp[lane] = perm_p;
+            swl[lane] = lds_len;
+            wave_sync_lds();
+            // write-out: kNs lanes per row, 64 / kNs rows per pass, so each
+            // store instruction covers whole rows (contiguous (i, j) pairs)
+            // instead of one pair in each of 64 different rows
+            constexpr int kRowsPerPass = 64 / kNs;
+            const int sub = lane / kNs, k = lane % kNs;
+            const uint32_t *srows = sr_all[wave];
+#pragma unroll 4
+            for (int r0 = 0; r0 < 64; r0 += kRowsPerPass) {
+                const int r = r0 + sub;
+                const uint32_t rl = swl[r];
+                if (static_cast<uint32_t>(k) < rl) {
+                    const uint64_t v = static_cast<uint64_t>(swp[r]) |
+                                       (static_cast<uint64_t>(srows[r * kRowStride + k]) << 32);
+                    __builtin_nontemporal_store(v, reinterpret_cast<unsigned long long *>(a.pairs + swo[r] + k));
+                }
             }
         }
     }
@@ -371,8 +499,10 @@ __global__ __launch_bounds__(kThreads) void k_row_nchunks(const uint32_t *__rest
 __global__ __launch_bounds__(kThreads) void k_emit_chunks(const uint32_t *__restrict__ row_pt,
                                                            const uint64_t *__restrict__ row_of,
                                                            const uint64_t *__restrict__ ch_off,
-                                                           uint32_t ncells, uint2 *__restrict__ chunks) {
+                                                           uint32_t ncells, uint2 *__restrict__ chunks,
+                                                           uint32_t *__restrict__ nchunks_dev) {
     const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
+    if (r == 0) *nchunks_dev = static_cast<uint32_t>(ch_off[ncells]);
     if (r >= ncells || r >= row_of[ncells]) return;
     const uint32_t s = row_pt[r], e = row_pt[r + 1];
     uint64_t k = ch_off[r];
@@ -387,7 +517,7 @@ __global__ __launch_bounds__(kThreads) void k_chunk_segments(TileArgs t, const u
                                                               const uint32_t *__restrict__ starts,
                                                               uint32_t d, uint2 *__restrict__ segs) {
     const uint64_t idx = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
-    const uint64_t total = static_cast<uint64_t>(t.nchunks) * t.rows_per_chunk;
+    const uint64_t total = static_cast<uint64_t>(*t.nchunks_dev) * t.rows_per_chunk;
     if (idx >= total) return;
     const uint32_t chunk = static_cast<uint32_t>(idx / t.rows_per_chunk);
     uint32_t r = static_cast<uint32_t>(idx % t.rows_per_chunk);
@@ -430,15 +560,25 @@ __global__ __launch_bounds__(kThreads) void k_point_c0(const uint32_t *__restric
     cx[r] = coords[static_cast<size_t>(cell_of[r]) * d];
 }
 
+__global__ void k_zero_word(uint32_t *p) {
+    if (threadIdx.x == 0) *p = 0;
+}
+
 inline unsigned nblk(uint64_t n) { return static_cast<unsigned>((n + kThreads - 1) / kThreads); }
 
 }  // namespace
 
 uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, const uint32_t *cell_of,
-                      uint32_t ncells, uint32_t n, uint32_t d, uint32_t *cx, uint2 **chunks_out,
-                      size_t *chunks_cap, hipStream_t s) {
+                      uint32_t ncells, uint32_t n, uint32_t d, uint64_t rows_bound, uint32_t *cx,
+                      uint2 **chunks_out, size_t *chunks_cap, uint32_t *nchunks_dev, hipStream_t s) {
     // chunk list only; row segments come from build_chunk_segments
-    if (ncells == 0 || n == 0) return 0;
+    if (ncells == 0 || n == 0) {
+        k_zero_word<<<1, 64, 0, s>>>(nchunks_dev);
+        SJ_LAUNCH_CHECK();
+        return 0;
+    }
+    const uint64_t bound = static_cast<uint64_t>(n) / 64 + std::min<uint64_t>(ncells, rows_bound);
+    if (bound >= 0xffffffffULL) throw Error(SJ_ECAPACITY, "too many join chunks");
     k_point_c0<<<nblk(n), kThreads, 0, s>>>(cell_of, coords, n, d, cx);
     SJ_LAUNCH_CHECK();
     // rows are bounded by the cells, so every array below is sized by ncells
@@ -452,18 +592,15 @@ uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, const uint
     k_row_nchunks<<<nblk(ncells), kThreads, 0, s>>>(row_pt.ptr, row_of.ptr, ncells, nch.ptr);
     SJ_LAUNCH_CHECK();
     scan_exclusive_u32_to_u64(nch.ptr, choff.ptr, ncells, s);
-    uint64_t total = 0;
-    SJ_HIP(hipMemcpyAsync(&total, choff.ptr + ncells, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    SJ_HIP(hipStreamSynchronize(s));
-    if (total >= 0xffffffffULL) throw Error(SJ_ECAPACITY, "too many join chunks");
-    if (total > *chunks_cap) {
+    if (bound > *chunks_cap) {
         if (*chunks_out) dev_free(*chunks_out);
-        *chunks_out = static_cast<uint2 *>(dev_alloc(total * sizeof(uint2)));
-        *chunks_cap = total;
+        *chunks_out = static_cast<uint2 *>(dev_alloc(bound * sizeof(uint2)));
+        *chunks_cap = bound;
     }
-    k_emit_chunks<<<nblk(ncells), kThreads, 0, s>>>(row_pt.ptr, row_of.ptr, choff.ptr, ncells, *chunks_out);
+    k_emit_chunks<<<nblk(ncells), kThreads, 0, s>>>(row_pt.ptr, row_of.ptr, choff.ptr, ncells, *chunks_out,
+                                                   nchunks_dev);
     SJ_LAUNCH_CHECK();
-    return static_cast<uint32_t>(total);
+    return static_cast<uint32_t>(bound);
 }
 
 void build_chunk_segments(const TileArgs &t, const uint32_t *cell_of, const uint32_t *starts,

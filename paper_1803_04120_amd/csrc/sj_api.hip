@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "sj.h"
@@ -136,7 +137,8 @@ struct sj_index {
     DevBuf<uint32_t> cx;
     uint2 *chunks = nullptr;
     size_t chunks_cap = 0;
-    uint32_t nchunks = 0;
+    uint32_t nchunks = 0;               // upper bound (launch size)
+    DevBuf<uint32_t> nchunks_dev;       // exact count
     uint32_t rows_per_chunk = 0;
     DevBuf<uint2> segs;
     bool chunks_ready = false;
@@ -153,6 +155,7 @@ struct sj_index {
     DevBuf<unsigned long long> counters;  // evals, band rechecks
     DevBuf<uint32_t> max_len;
     DevBuf<uint32_t> overflow;
+    DevBuf<uint64_t> summary;  // count pass results read back together
     uint64_t pairs = 0;
     uint32_t max_row = 0;
     sj_stats stats{};
@@ -264,12 +267,18 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
     if (ix.key_bits <= 32) {
         DevBuf<uint32_t> keys(n), keys_alt(n);
         sj::launch_cell_keys_u32(dp, n, ix.grid, keys.ptr, ix.perm.ptr, s);
-        sj::radix_sort_u32(keys.ptr, ix.perm.ptr, keys_alt.ptr, ids_alt.ptr, n, ix.key_bits, s);
+        if (sj::radix_sort_u32(keys.ptr, ix.perm.ptr, keys_alt.ptr, ids_alt.ptr, n, ix.key_bits, s)) {
+            std::swap(keys, keys_alt);
+            std::swap(ix.perm, ids_alt);
+        }
         ix.ncells = sj::build_cells<uint32_t>(keys.ptr, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
     } else {
         DevBuf<uint64_t> keys(n), keys_alt(n);
         sj::launch_cell_keys_u64(dp, n, ix.grid, keys.ptr, ix.perm.ptr, s);
-        sj::radix_sort_u64(keys.ptr, ix.perm.ptr, keys_alt.ptr, ids_alt.ptr, n, ix.key_bits, s);
+        if (sj::radix_sort_u64(keys.ptr, ix.perm.ptr, keys_alt.ptr, ids_alt.ptr, n, ix.key_bits, s)) {
+            std::swap(keys, keys_alt);
+            std::swap(ix.perm, ids_alt);
+        }
         ix.ncells = sj::build_cells<uint64_t>(keys.ptr, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
     }
     // per-cell coordinates and occupancy masks M_j (Section IV-C)
@@ -344,6 +353,7 @@ sj::TileArgs tile_args(sj_index &ix) {
     t.cx = ix.cx.ptr;
     t.chunks = ix.chunks;
     t.nchunks = ix.nchunks;
+    t.nchunks_dev = ix.nchunks_dev.ptr;
     t.rows_per_chunk = ix.rows_per_chunk;
     t.segs = ix.segs.ptr;
     return t;
@@ -359,16 +369,20 @@ bool use_fused_sort() {
 void ensure_chunks(sj_index &ix, hipStream_t s) {
     if (ix.chunks_ready) return;
     ix.cx.ensure(ix.n);
+    ix.nchunks_dev.ensure(1);
+    // grid rows: one per occupied combination of the dimension-1..d-1 cells
+    uint64_t rows_bound = 1;
+    for (uint32_t j = 1; j < ix.d; ++j)
+        rows_bound = ix.grid.dims[j] > (UINT64_MAX / 2) / rows_bound ? UINT64_MAX / 2 : rows_bound * ix.grid.dims[j];
     ix.nchunks = sj::build_chunks(ix.coords.ptr, ix.starts.ptr, ix.cell_of.ptr,
                                   static_cast<uint32_t>(ix.ncells), static_cast<uint32_t>(ix.n), ix.d,
-                                  ix.cx.ptr, &ix.chunks, &ix.chunks_cap, s);
+                                  rows_bound, ix.cx.ptr, &ix.chunks, &ix.chunks_cap, ix.nchunks_dev.ptr, s);
     uint32_t r3 = 1;
     for (uint32_t j = 1; j < ix.d; ++j) r3 *= 3;
     ix.rows_per_chunk = r3;
     ix.segs.reset(static_cast<size_t>(ix.nchunks) * r3);
     sj::build_chunk_segments(tile_args(ix), ix.cell_of.ptr, ix.starts.ptr, ix.d, ix.segs.ptr, s);
     ix.chunks_ready = true;
-    ix.stats.chunks = ix.nchunks;
 }
 
 void ensure_f32(sj_index &ix, hipStream_t s) {
@@ -439,9 +453,11 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     const size_t nctr = 2 * sj::kCounterSlots * sj::kCounterStride;
     ix.counters.ensure(nctr);
     ix.max_len.ensure(1);
-    if (uni) sj::launch_fill_u32(ix.in_cnt.ptr, n, 0u, s);
-    sj::launch_fill_u64(reinterpret_cast<uint64_t *>(ix.counters.ptr), nctr, 0ull, s);
-    sj::launch_fill_u32(ix.max_len.ptr, 1, 0u, s);
+    sj::ZeroSpans z{};
+    if (uni) z.add(ix.in_cnt.ptr, n);
+    z.add(ix.counters.ptr, 2 * nctr);
+    z.add(ix.max_len.ptr, 1);
+    sj::launch_zero_spans(z, s);
     sj::JoinArgs a = base_args(ix, uni);
     if (tiled)
         sj::launch_join_tiled(a, tile_args(ix), ix.d, uni, sj::kCount, ix.band_used, s);
@@ -449,19 +465,18 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
         sj::launch_join(a, ix.d, uni, sj::kCount, ix.band_used, s);
     sj::launch_row_lengths(ix.own_cnt.ptr, uni ? ix.in_cnt.ptr : nullptr, ix.perm.ptr, n,
                            ix.len_orig.ptr, ix.len_cell.ptr, ix.max_len.ptr, s);
-    sj::scan_exclusive_u32_to_u64(ix.len_orig.ptr, ix.off_orig.ptr, n, s);
-    sj::scan_exclusive_u32_to_u64(ix.len_cell.ptr, ix.off_cell.ptr, n, s);
-    std::vector<unsigned long long> cnt(nctr);
-    SJ_HIP(hipMemcpyAsync(&ix.pairs, ix.off_orig.ptr + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    SJ_HIP(hipMemcpyAsync(&ix.max_row, ix.max_len.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    SJ_HIP(hipMemcpyAsync(cnt.data(), ix.counters.ptr, nctr * sizeof(unsigned long long),
-                          hipMemcpyDeviceToHost, s));
+    sj::scan_exclusive_u32_to_u64_x2(ix.len_orig.ptr, ix.off_orig.ptr, ix.len_cell.ptr, ix.off_cell.ptr, n, s);
+    ix.summary.ensure(5);
+    sj::launch_count_summary(ix.off_orig.ptr, n, ix.max_len.ptr, ix.counters.ptr,
+                             tiled ? ix.nchunks_dev.ptr : nullptr, ix.summary.ptr, s);
+    uint64_t sm[5];
+    SJ_HIP(hipMemcpyAsync(sm, ix.summary.ptr, sizeof(sm), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
-    ix.stats.evals = ix.stats.band_rechecks = 0;
-    for (int k = 0; k < sj::kCounterSlots; ++k) {
-        ix.stats.evals += cnt[static_cast<size_t>(k) * sj::kCounterStride];
-        ix.stats.band_rechecks += cnt[(sj::kCounterSlots + static_cast<size_t>(k)) * sj::kCounterStride];
-    }
+    ix.pairs = sm[0];
+    ix.max_row = static_cast<uint32_t>(sm[1]);
+    ix.stats.evals = sm[2];
+    ix.stats.band_rechecks = sm[3];
+    if (tiled) ix.stats.chunks = static_cast<uint32_t>(sm[4]);
     ix.stats.pairs = ix.pairs;
     ix.stats.max_row_pairs = ix.max_row;
     ix.stats.ranges = tiled ? 0 : ix.ranges[uni].count;
@@ -481,7 +496,7 @@ void check_overflow(sj_index &ix, hipStream_t s) {
 // the single batch holding every row); otherwise the batch's own query
 // points scan all adjacent cells and write only their own rows.
 struct Scratch {
-    DevBuf<uint32_t> qlist, flags, big_list, big_count;
+    DevBuf<uint32_t> qlist, flags;
 };
 
 void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t cap,
@@ -517,8 +532,6 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
         sj::launch_fill_u32(ix.cur.ptr, n, 0u, s);
         a.cur = ix.cur.ptr;
     }
-    sc.big_list.ensure(3 * std::max<uint64_t>(1, i1 - i0));
-    sc.big_count.ensure(3);
     // whole result, full fill: each point's row is complete when its own
     // evaluation ends, so the row sort runs inside the fill kernel
     const bool fused = tiled && !unicomp_fill && whole && use_fused_sort();
@@ -528,20 +541,20 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
             ns = ix.max_row <= 16 ? 16 : 32;
             a.off_orig = ix.off_orig.ptr;
             a.pairs = reinterpret_cast<uint2 *>(pairs);
-            a.sort_lists = sc.big_list.ptr;
-            a.sort_counts = sc.big_count.ptr;
-            sj::clear_rowsort_counts(sc.big_count.ptr, s);
         }
+        if (whole) sj::launch_fill_u32(a.overflow, 1, 0u, s);
         sj::launch_join_tiled(a, tile_args(ix), ix.d, mode, sj::kFill, ix.band_used, s, ns);
         if (fused) {
-            sj::launch_rowsort_queued(ix.off_cell.ptr, ix.off_orig.ptr, ix.perm.ptr, n, out_j, pairs,
-                                      sc.big_list.ptr, sc.big_count.ptr, ix.max_row, ns, s);
+            sj::launch_rowsort_long(ix.off_cell.ptr, ix.off_orig.ptr, ix.perm.ptr, n, out_j, pairs,
+                                    ix.max_row, ns, s);
             return;
         }
     } else if (unicomp_fill) {
+        if (whole) sj::launch_fill_u32(a.overflow, 1, 0u, s);
         sj::launch_join(a, ix.d, 1, sj::kFill, ix.band_used, s);
     } else {
         if (whole) {
+            sj::launch_fill_u32(a.overflow, 1, 0u, s);
             a.qlist = nullptr;
             a.nq = static_cast<uint32_t>(n);
         } else {
@@ -554,10 +567,9 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
     }
     if (whole)
         sj::launch_rowsort_cells(ix.off_cell.ptr, ix.off_orig.ptr, ix.perm.ptr, n, out_j, pairs,
-                                 sc.big_list.ptr, sc.big_count.ptr, ix.max_row, s);
+                                 ix.max_row, s);
     else
-        sj::launch_rowsort(ix.off_orig.ptr, i0, i1, base, out_j, pairs, sc.big_list.ptr,
-                           sc.big_count.ptr, ix.max_row, s);
+        sj::launch_rowsort(ix.off_orig.ptr, i0, i1, base, out_j, pairs, ix.max_row, s);
 }
 
 // The fill pass may evaluate the unicomp subset (every mirrored pair then
@@ -580,9 +592,9 @@ void join_fill_all(sj_index &ix, uint32_t *pairs_dev, hipStream_t s) {
     DevBuf<uint32_t> out_j(ix.pairs);
     Scratch sc;
     ix.overflow.ensure(1);
-    sj::launch_fill_u32(ix.overflow.ptr, 1, 0u, s);
     const bool uni_fill = choose_unicomp_fill(ix);
     ix.stats.fill_unicomp = uni_fill ? 1u : 0u;
+    // (a whole-result fill clears the overflow flag itself)
     fill_rows(ix, 0, ix.n, 0, ix.pairs, uni_fill, out_j.ptr, pairs_dev, sc, s);
     check_overflow(ix, s);
     ix.stats.batches = 1;

@@ -94,17 +94,24 @@ struct GridParams {
 // ---------------------------------------------------------------------
 // out[i] = sum_{k<i} in[k] for i in [0, n]; out[n] is the total.
 void scan_exclusive_u32_to_u64(const uint32_t *in, uint64_t *out, size_t n, hipStream_t s);
+// Two such scans of equal length in one pair of launches.
+void scan_exclusive_u32_to_u64_x2(const uint32_t *in0, uint64_t *out0, const uint32_t *in1,
+                                  uint64_t *out1, size_t n, hipStream_t s);
 // in place inclusive scan of u32.
 void scan_inclusive_u32(uint32_t *data, size_t n, hipStream_t s);
 // exclusive scan of u32 into u32 (no total), in place allowed.
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, hipStream_t s);
+// Inclusive scan of the head flags (key[r] != key[r-1], 1 at r = 0) of a
+// sorted key array: out[r] = 1 + number of distinct keys before r.
+template <typename K>
+void scan_head_flags_inclusive(const K *sorted_keys, uint32_t *out, size_t n, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) by the low `bits` bits of key.
-// On return the sorted data is in keys/vals (the alternate buffers are
-// scratch of the same size).
-void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
+// The passes alternate between the two buffer pairs: returns false when the
+// sorted data ends in keys/vals, true when it ends in keys_alt/vals_alt.
+bool radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
                     size_t n, int bits, hipStream_t s);
-void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+bool radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                     size_t n, int bits, hipStream_t s);
 
 // ---------------------------------------------------------------------
@@ -134,6 +141,19 @@ void launch_gather_soa(const double *pts, const uint32_t *perm, uint64_t n, uint
 void launch_make_f32(const double *X, uint64_t n, uint32_t d, const double *shift, float *Y,
                      hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+// Up to four ranges of 32-bit words to clear in one launch.
+struct ZeroSpans {
+    uint32_t *p[4];
+    uint64_t words[4];
+    int count;
+    void add(void *ptr, uint64_t nwords) {
+        if (!ptr || !nwords) return;
+        p[count] = static_cast<uint32_t *>(ptr);
+        words[count] = nwords;
+        ++count;
+    }
+};
+void launch_zero_spans(const ZeroSpans &z, hipStream_t s);
 void launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 
 // ---------------------------------------------------------------------
@@ -184,11 +204,9 @@ struct JoinArgs {
     // fill with the row sort fused in (each point's row is complete when its
     // own evaluation ends): rows of at most the kernel's register-sort size
     // are sorted and written as (i, j) pairs at off_orig[perm[p]]; longer
-    // rows stay in out_j and are queued (lists/counts as in the row sort)
+    // rows stay in out_j for the row-sort kernels
     const uint64_t *off_orig;
     uint2 *pairs;
-    uint32_t *sort_lists;
-    uint32_t *sort_counts;
 };
 enum JoinMode { kCount = 0, kFill = 1 };
 void launch_join(const JoinArgs &a, uint32_t d, int unicomp, int mode, int band, hipStream_t s);
@@ -205,14 +223,18 @@ struct TileArgs {
     uint64_t stride[kMaxDim];
     const uint32_t *cx;       // dimension-0 cell coordinate of each cell-ordered point
     const uint2 *chunks;      // [first, end) point range of each chunk
-    uint32_t nchunks;
+    uint32_t nchunks;         // upper bound on the chunk count (launch size)
+    const uint32_t *nchunks_dev;  // the chunk count (device)
     uint32_t rows_per_chunk;  // 3^(d-1)
     const uint2 *segs;        // [chunk * rows_per_chunk + row] candidate point segment
 };
-// Builds cx and the chunk list; returns the number of chunks (host sync).
+// Builds cx and the chunk list without a host sync: a grid row holds p points
+// in ceil(p / 64) <= p / 64 + 1 chunks, so there are at most
+// floor(n / 64) + rows chunks, rows <= min(ncells, rows_bound). Returns that
+// bound; the exact count goes to *nchunks_dev.
 uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, const uint32_t *cell_of,
-                      uint32_t ncells, uint32_t n, uint32_t d, uint32_t *cx, uint2 **chunks_out,
-                      size_t *chunks_cap, hipStream_t s);
+                      uint32_t ncells, uint32_t n, uint32_t d, uint64_t rows_bound, uint32_t *cx,
+                      uint2 **chunks_out, size_t *chunks_cap, uint32_t *nchunks_dev, hipStream_t s);
 void build_chunk_segments(const TileArgs &t, const uint32_t *cell_of, const uint32_t *starts,
                           uint32_t d, uint2 *segs, hipStream_t s);
 void launch_join_tiled(const JoinArgs &a, const TileArgs &t, uint32_t d, int unicomp, int mode,
@@ -223,6 +245,11 @@ void launch_join_tiled(const JoinArgs &a, const TileArgs &t, uint32_t d, int uni
 void launch_row_lengths(const uint32_t *own_cnt, const uint32_t *in_cnt, const uint32_t *perm,
                         uint64_t n, uint32_t *len_orig, uint32_t *len_cell, uint32_t *max_len,
                         hipStream_t s);
+// Gathers the count pass results into out[0..5): P, longest row,
+// evaluations, band re-checks, chunk count (nchunks may be null).
+void launch_count_summary(const uint64_t *off_orig, uint64_t n, const uint32_t *max_len,
+                          const unsigned long long *counters, const uint32_t *nchunks, uint64_t *out,
+                          hipStream_t s);
 void launch_gather_offsets(const uint64_t *off_orig, const uint32_t *perm, uint64_t n,
                            uint64_t *offc, hipStream_t s);
 // cell-ordered points whose original id lies in [i0, i1), in cell order.
@@ -239,21 +266,18 @@ void launch_batch_bounds(const uint64_t *off, uint64_t n, uint64_t total, uint32
 // ---------------------------------------------------------------------
 // Sorts each row's neighbour ids and writes interleaved (i, j) pairs.
 // Rows [i0, i1); row i occupies [off[i] - base, off[i+1] - base) of out_j
-// and of pairs. lists (3 * (i1 - i0) entries) and counts (3) are scratch;
-// max_len is the longest row.
+// and of pairs. max_len is the longest row.
 void launch_rowsort(const uint64_t *off, uint64_t i0, uint64_t i1, uint64_t base,
-                    uint32_t *out_j, uint32_t *pairs, uint32_t *lists, uint32_t *counts,
-                    uint32_t max_len, hipStream_t s);
+                    uint32_t *out_j, uint32_t *pairs, uint32_t max_len, hipStream_t s);
 // Whole result filled in cell order: row r (cell-ordered point r) occupies
 // out_j[off_cell[r], off_cell[r+1]) and goes to pairs[off_orig[perm[r]], ...)
-// with i = perm[r]. lists holds 3 n entries, counts 3.
-// Sorts only the rows queued by a fused fill (longer than sorted_len).
-void launch_rowsort_queued(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,
-                           uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t *lists,
-                           uint32_t *counts, uint32_t max_len, uint32_t sorted_len, hipStream_t s);
-void clear_rowsort_counts(uint32_t *counts, hipStream_t s);
+// with i = perm[r].
 void launch_rowsort_cells(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,
-                          uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t *lists,
-                          uint32_t *counts, uint32_t max_len, hipStream_t s);
+                          uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t max_len, hipStream_t s);
+// Same layout; sorts only the rows longer than sorted_len (a fused fill has
+// written the others).
+void launch_rowsort_long(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,
+                         uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t max_len, uint32_t sorted_len,
+                         hipStream_t s);
 
 }  // namespace sj
