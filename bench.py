@@ -278,6 +278,9 @@ def main():
             host_ms[k] += 1e3 * v
     log("[bench] per-step call wall times (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in host_ms.items()))
     torch.cuda.synchronize()
+    # timed region: HIP events only around the refine kernels (count and
+    # fill), the candidates for the roofline figure
+    _lib.profile_select("tiled_")
     _lib.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -291,7 +294,14 @@ def main():
     ms_per_step = 1e3 * dt / args.steps
     value = pairs_total / dt
     log(f"[bench] {args.steps} steps in {dt:.3f}s, {ms_per_step:.3f} ms/step, {value:.4g} pairs/s")
-    for k, (cnt, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+    # every kernel of one more (untimed) step, for the log
+    _lib.profile_select("")
+    _lib.profile_enable(True)
+    step()
+    torch.cuda.synchronize()
+    _lib.profile_enable(False)
+    log("[bench] all kernels of one step:")
+    for k, (cnt, ms) in sorted(_lib.profile_read().items(), key=lambda kv: -kv[1][1]):
         log(f"[bench]   {k:28s} launches={cnt:6d} total={ms:9.3f} ms avg={1e3 * ms / cnt:9.2f} us")
 
     # roofline of the dominant kernel (largest total time among modelled ones)

@@ -275,6 +275,10 @@ typedef struct sj_kernel_time {
 } sj_kernel_time;
 int sj_profile_enable(int on);
 int sj_profile_read(sj_kernel_time *out, uint32_t cap, uint32_t *count);
+/* Restricts timing to kernels whose name starts with prefix (NULL or "":
+ * every kernel), so a timed region pays for two event records only around
+ * the kernels it reports. The string is copied. */
+int sj_profile_select(const char *prefix);
 
 /* Thread-local description of the last failure ("" if none). */
 const char *sj_last_error(void);

@@ -119,6 +119,7 @@ def load():
         "sj_band_thresholds": (ctypes.c_int, [u32, dbl, dbl, ctypes.POINTER(ctypes.c_float),
                                               ctypes.POINTER(ctypes.c_float)]),
         "sj_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+        "sj_profile_select": (ctypes.c_int, [ctypes.c_char_p]),
         "sj_profile_read": (ctypes.c_int, [ctypes.POINTER(SjKernelTime), u32,
                                            ctypes.POINTER(ctypes.c_uint32)]),
         "sj_last_error": (ctypes.c_char_p, []),
@@ -168,6 +169,11 @@ def stats_dict(st: SjStats) -> dict:
 
 def profile_enable(on: bool = True):
     load().sj_profile_enable(1 if on else 0)
+
+
+def profile_select(prefix: str = ""):
+    """Time only kernels whose name starts with prefix ("" = all)."""
+    load().sj_profile_select(prefix.encode() if prefix else None)
 
 
 def profile_read() -> dict:

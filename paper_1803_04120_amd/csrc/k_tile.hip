@@ -173,20 +173,28 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 return acc <= a.eps2;
             }
         };
-        auto emit = [&](uint32_t i, uint32_t q, bool mirror) {
+        // One tested candidate (staged index i, point q, id its point id from
+        // the staged ids, h the test result). The fused fill stores every
+        // candidate into the lane's LDS slot -- hits at the row position,
+        // misses into the slot's spare last word -- so the common path has
+        // no branch; rows that do not fit the slot also go to out_j.
+        auto emit = [&](bool h, uint32_t i, uint32_t q, uint32_t id, bool mirror) {
             if (kMode == kCount) {
-                ++own;
-                if (mirror) atomicAdd(&saux[i], 1u);
-            } else if (NS > 0 && row_in_lds) {
-                if (own < static_cast<uint32_t>(NS))
-                    srow[own] = saux[i];
-                else
-                    atomicOr(a.overflow, 1u);
-                ++own;
-            } else {
+                own += h ? 1u : 0u;
+                if (h && mirror) atomicAdd(&saux[i], 1u);
+            } else if (NS > 0) {
+                const uint32_t slot = own < static_cast<uint32_t>(NS) ? own : static_cast<uint32_t>(NS);
+                srow[h ? slot : static_cast<uint32_t>(NS)] = id;
+                if (h && !row_in_lds) {
+                    // a row that disagrees with its count is caught at the end
+                    const uint64_t at = my_row + own;
+                    a.out_j[at < a.out_cap ? at : a.out_cap - 1] = id;
+                }
+                own += h ? 1u : 0u;
+            } else if (h) {
                 const uint64_t at = my_row + own;
                 if (at < a.out_cap)
-                    a.out_j[at] = saux[i];
+                    a.out_j[at] = id;
                 else
                     atomicOr(a.overflow, 1u);
                 ++own;
@@ -200,7 +208,8 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 }
             }
         };
-        // candidates [i0, i1) of the staged tile, kUnroll tests in flight
+        // candidates [i0, i1) of the staged tile, kUnroll of them loaded and
+        // tested before any is emitted
         constexpr int kUnroll = D <= 3 ? 4 : 2;
         auto run = [&](uint32_t T0, uint32_t i0, uint32_t i1) {
             if (i0 >= i1) return;
@@ -208,14 +217,18 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             uint32_t i = i0;
             for (; i + kUnroll <= i1; i += kUnroll) {
                 bool h[kUnroll];
+                uint32_t id[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) id[u] = kPerm ? saux[i + u] : 0u;
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) h[u] = test(i + u, T0 + i + u);
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    if (h[u]) emit(i + u, T0 + i + u, kUni && T0 + i + u != p);
+                for (int u = 0; u < kUnroll; ++u) emit(h[u], i + u, T0 + i + u, id[u], kUni && T0 + i + u != p);
             }
-            for (; i < i1; ++i)
-                if (test(i, T0 + i)) emit(i, T0 + i, kUni && T0 + i != p);
+            for (; i < i1; ++i) {
+                const uint32_t id = kPerm ? saux[i] : 0u;
+                emit(test(i, T0 + i), i, T0 + i, id, kUni && T0 + i != p);
+            }
         };
         auto evaluate_tile = [&](uint32_t T0, uint32_t len, bool own_row) {
             uint32_t lo_c = c0p > 0 ? c0p - 1 : 0, hi_c = c0p + 1;
@@ -378,12 +391,13 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         }
         if (kMode == kCount && active) a.own_cnt[p] = own;
         if (kMode == kFill && NS > 0 && !kUni) {
-            // the row of p is complete: sort it in registers, or queue it for
-            // the row-sort kernels if it is longer than the LDS slot
+            // the row of p is complete: sort it in registers; a row longer
+            // than the LDS slot is in out_j for the row-sort kernels
             constexpr int kNs = NS > 0 ? NS : 1;
             const uint32_t len = own;
             uint32_t lds_len = 0;
-            if (active && row_in_lds) {
+            if (active && own != row_len) atomicOr(a.overflow, 1u);  // count and fill disagree
+            if (active && row_in_lds && len <= static_cast<uint32_t>(kNs)) {
                 uint32_t v[kNs];
 #pragma unroll
                 for (int k = 0; k < kNs; ++k)
@@ -414,6 +428,34 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                                        (static_cast<uint64_t>(srows[r * kRowStride + k]) << 32);
                     __builtin_nontemporal_store(v, reinterpret_cast<unsigned long long *>(a.pairs + swo[r] + k));
                 }
+            }
+            // rows longer than the slot but at most 64 long: in out_j (written
+            // above by this wave); the wave sorts them, one entry per lane,
+            // four rows at a time so their loads and networks overlap
+            uint64_t longm = ballot(active && !row_in_lds && row_len <= 64u);
+            if (longm) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // own stores before own loads
+            while (longm) {
+                constexpr int kG = 4;
+                uint32_t v[kG], rl[kG], rid[kG];
+                uint64_t dst[kG];
+#pragma unroll
+                for (int g = 0; g < kG; ++g) {
+                    const int l = longm ? __builtin_ctzll(longm) : 0;
+                    const bool has = longm != 0;
+                    longm &= longm - 1;
+                    rl[g] = has ? static_cast<uint32_t>(__shfl(static_cast<int>(row_len), l, 64)) : 0u;
+                    rid[g] = static_cast<uint32_t>(__shfl(static_cast<int>(perm_p), l, 64));
+                    const uint64_t src = __shfl(my_row, l, 64);
+                    dst[g] = __shfl(row_dst, l, 64);
+                    v[g] = static_cast<uint32_t>(lane) < rl[g] ? a.out_j[src + lane] : 0xffffffffu;
+                }
+#pragma unroll
+                for (int g = 0; g < kG; ++g) v[g] = wave_bitonic_sort64(v[g]);
+#pragma unroll
+                for (int g = 0; g < kG; ++g)
+                    if (static_cast<uint32_t>(lane) < rl[g])
+                        __builtin_nontemporal_store(static_cast<uint64_t>(rid[g]) | (static_cast<uint64_t>(v[g]) << 32),
+                                                    reinterpret_cast<unsigned long long *>(a.pairs + dst[g] + lane));
             }
         }
     }

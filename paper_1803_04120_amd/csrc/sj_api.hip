@@ -545,8 +545,9 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
         if (whole) sj::launch_fill_u32(a.overflow, 1, 0u, s);
         sj::launch_join_tiled(a, tile_args(ix), ix.d, mode, sj::kFill, ix.band_used, s, ns);
         if (fused) {
+            // the fused fill sorts rows of up to 64 itself
             sj::launch_rowsort_long(ix.off_cell.ptr, ix.off_orig.ptr, ix.perm.ptr, n, out_j, pairs,
-                                    ix.max_row, ns, s);
+                                    ix.max_row, 64, s);
             return;
         }
     } else if (unicomp_fill) {
@@ -964,6 +965,11 @@ int sj_profile_enable(int on) {
 
 int sj_profile_read(sj_kernel_time *out, uint32_t cap, uint32_t *count) {
     return sj::profile_read(out, cap, count);
+}
+
+int sj_profile_select(const char *prefix) {
+    sj::profile_select(prefix);
+    return SJ_OK;
 }
 
 int sj_band_thresholds(uint32_t d, double eps, double extent, float *lo, float *hi) {

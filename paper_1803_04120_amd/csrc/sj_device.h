@@ -79,6 +79,24 @@ __device__ __forceinline__ uint32_t xcd_block_index() {
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// Sorts 64 values, one per lane, ascending in lane order (bitonic network
+// over lane-index exchanges). Every lane of the wave must take part.
+__device__ __forceinline__ uint32_t wave_bitonic_sort64(uint32_t v) {
+    const uint32_t lane = static_cast<uint32_t>(lane_id());
+#pragma unroll
+    for (uint32_t k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t o = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), static_cast<int>(j), 64));
+            const bool asc = (lane & k) == 0;      // direction of this lane's block
+            const bool lower = (lane & j) == 0;    // lower element of the pair
+            const uint32_t mn = v < o ? v : o, mx = v < o ? o : v;
+            v = (lower == asc) ? mn : mx;
+        }
+    }
+    return v;
+}
+
 // Sorts N values held in registers ascending with a fully unrolled bitonic
 // network (all register indices are compile-time constants).
 template <int N>

@@ -76,6 +76,7 @@ struct KTimer {
 void profile_resolve_pending();
 void profile_reset();
 void profile_set(bool on);
+void profile_select(const char *prefix);
 int profile_read(void *out, uint32_t cap, uint32_t *count);
 
 // ---------------------------------------------------------------------

@@ -134,6 +134,7 @@ struct ProfEntry {
 std::mutex g_prof_mu;
 std::map<std::string, ProfEntry> g_prof;
 bool g_prof_on = false;
+std::string g_prof_prefix;  // written only while no call is running
 struct PendingEvent {
     const char *name;
     hipEvent_t e0, e1;
@@ -157,6 +158,7 @@ bool profiling_enabled() { return g_prof_on; }
 
 KTimer::KTimer(const char *name, hipStream_t s) : name_(name), s_(s) {
     if (!g_prof_on) return;
+    if (!g_prof_prefix.empty() && std::strncmp(name, g_prof_prefix.c_str(), g_prof_prefix.size()) != 0) return;
     e0_ = take_event();
     e1_ = take_event();
     if (!e0_ || !e1_) {
@@ -196,6 +198,7 @@ void profile_reset() {
 }
 
 void profile_set(bool on) { g_prof_on = on; }
+void profile_select(const char *prefix) { g_prof_prefix = prefix ? prefix : ""; }
 
 // out: array of {char name[48]; uint64 launches; double total_ms} records
 int profile_read(void *out, uint32_t cap, uint32_t *count) {

@@ -80,3 +80,13 @@ def test_null_arguments(lib):
     assert lib.sj_index_stats(None, None) == _lib.SJ_EINVAL
     lib.sj_destroy_index(None)
     lib.sj_free(None)
+
+
+def test_profile_select_and_read_without_device_work(lib):
+    from paper_1803_04120_amd import _lib
+    _lib.profile_select("tiled_")
+    _lib.profile_enable(True)
+    assert _lib.profile_read() == {}
+    _lib.profile_enable(False)
+    _lib.profile_select("")
+    assert lib.sj_profile_select(None) == 0
