@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--no-band", action="store_true", help="skip the FP32+band leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy three times (reference kernel "
                          "of known traffic for hardware byte counters)")
@@ -73,6 +74,9 @@ def kernel_bytes(name, n, d, cells, ranges, pairs):
     if name.startswith("join_count") or name.startswith("tiled_count"):
         # X (d doubles) + cell of each point + its row length; cell range table
         return n * (8 * d + 4 + 4) + 8 * (cells + 1) + 8 * ranges
+    if name.startswith("tiled_fill_sort") and name.endswith("fp32band"):
+        # as below, plus the FP32 copy of every point (4d bytes)
+        return n * (8 * d + 4 * d + 4 + 8 + 4 + 8) + 8 * pairs
     if name.startswith("tiled_fill_sort"):
         # X + cell + cell-order row offset + permutation entry + the row's
         # final offset per point, one (i, j) pair (8 bytes) per result pair
@@ -158,6 +162,27 @@ def cpu_baseline(pts, eps_list, target_s):
             "sample": f"{rows_per_eps} random query rows x all {n} candidates for each of "
                       f"{len(eps_list)} eps ({pairs} pairs in {dt:.1f} s); "
                       f"rate = sample pairs / sample time"}
+
+
+def cpu_grid_baseline(pts, eps_list, target_s):
+    """The host-core grid join (oracle/cpu_grid_join.c: the same grid method,
+    count then sorted fill) on the whole workload, one eps after another in
+    sweep order until about target_s seconds have passed."""
+    from oracle import reference
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    pairs, done = 0, []
+    t0 = time.perf_counter()
+    for e in eps_list:
+        counts, out = reference.grid_join(pts, e)
+        pairs += out.shape[0]
+        done.append(e)
+        del out
+        if time.perf_counter() - t0 > target_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "cpu_grid_join",
+            "sample": f"whole {pts.shape[0]}-point join with sorted (i,j) output for eps {done} "
+                      f"({pairs} pairs in {dt:.1f} s)"}
 
 
 def calibrate_eps_gpu(sj, x, k, eps0):
@@ -352,16 +377,54 @@ def main():
         log("[bench] calibration copy: 3 x 1 GiB read + 1 GiB written")
         del src, dst
 
+    # the same sweep with the FP32 pre-test and FP64 band re-decision
+    band = None
+    if not args.no_band and args.precision == "fp64":
+        def step_band():
+            total = 0
+            for e in eps_list:
+                with sj.Index(x, e) as ix:
+                    P = ix.count(unicomp=bool(args.unicomp), precision="fp32_band")
+                    ix.fill(out)
+                    total += P
+            return total
+        step_band()
+        torch.cuda.synchronize()
+        _lib.profile_select("tiled_")
+        _lib.profile_enable(True)
+        t0 = time.perf_counter()
+        bp = 0
+        for _ in range(args.steps):
+            bp += step_band()
+        torch.cuda.synchronize()
+        bdt = time.perf_counter() - t0
+        _lib.profile_enable(False)
+        _lib.profile_select("")
+        bprof = _lib.profile_read()
+        fills = {k: v for k, v in bprof.items() if k.startswith("tiled_fill")}
+        band = {"pairs_per_s": bp / bdt, "ms_per_step": 1e3 * bdt / args.steps,
+                "vs_fp64": (bp / bdt) / value, "kernels_ms": {k: round(v[1] / args.steps, 4) for k, v in bprof.items()}}
+        if fills:
+            fk = max(fills, key=lambda k: fills[k][1])
+            cnt, ms = fills[fk]
+            byts = sum(kernel_bytes(fk, n, d, i["cells"], i["ranges"], i["pairs"]) for i in info) * args.steps
+            ach = byts / (ms * 1e-3) / 1e9
+            band["roofline"] = {"kernel": fk, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_us": round(1e3 * ms / cnt, 3)}
+        log(f"[bench] fp32+band: {band['pairs_per_s']:.4g} pairs/s ({band['vs_fp64']:.3f} x fp64)")
+
     serving = None
     if not args.no_serve:
         serving = serving_leg(args, sj, torch)
         log(f"[bench] serving: p50 {serving['p50_ms']} ms p99 {serving['p99_ms']} ms at "
             f"{serving['rate_req_per_s']} req/s, {serving['pairs_per_s']:.4g} pairs/s")
 
-    cpu = None
+    cpu = cpu_grid = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pts, eps_list, args.cpu_seconds)
         log(f"[bench] cpu oracle baseline {cpu['value']:.4g} pairs/s on {cpu['cores']} threads")
+        cpu_grid = cpu_grid_baseline(pts, eps_list, args.cpu_seconds)
+        log(f"[bench] cpu grid-join baseline {cpu_grid['value']:.4g} pairs/s on {cpu_grid['cores']} threads")
 
     rec = {
         "metric": "self-join neighbor pairs/s",
@@ -381,6 +444,8 @@ def main():
                    "output": "sorted (i,j) pairs in HBM"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_grid_baseline": cpu_grid,
+        "fp32_band": band,
         "pipeline_hbm": pipeline,
         "per_eps": info,
         "batched": batched,

@@ -12,13 +12,14 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "sj_oracle.c")
+GRID_SRC = os.path.join(HERE, "cpu_grid_join.c")  # host-core grid-join baseline
 LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-           "-o", LIB + ".tmp", SRC]
+           "-o", LIB + ".tmp", SRC, GRID_SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

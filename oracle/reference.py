@@ -52,6 +52,8 @@ def _load():
         lib.sjo_count_rows_multi.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp]
         lib.sjo_d2.restype = dbl
         lib.sjo_d2.argtypes = [vp, i64, i64, i64]
+        lib.sjg_grid_join.restype = i64
+        lib.sjg_grid_join.argtypes = [vp, i64, i64, dbl, vp, vp]
         _lib = lib
     return _lib
 
@@ -166,3 +168,26 @@ def count_rows_multi(points, eps_list, rows) -> np.ndarray:
 def d2(points, i: int, j: int) -> float:
     x = _as_points(points)
     return float(_load().sjo_d2(_ptr(x), x.shape[1], int(i), int(j)))
+
+
+# --------------------------------------------------------------------------
+# CPU grid join (host-core baseline; checked against the brute force)
+# --------------------------------------------------------------------------
+def grid_join(points, eps: float, with_pairs: bool = True):
+    """The grid self-join of cpu_grid_join.c on the host's cores:
+    (row counts, pairs sorted by (i, j) as (P, 2) int32 or None)."""
+    x = _as_points(points)
+    n, d = x.shape
+    counts = np.zeros(n, dtype=np.int64)
+    if n == 0:
+        return counts, (np.zeros((0, 2), dtype=np.int32) if with_pairs else None)
+    total = _load().sjg_grid_join(_ptr(x), n, d, float(eps), _ptr(counts), None)
+    if total < 0:
+        raise MemoryError("grid join: allocation failed")
+    if not with_pairs:
+        return counts, None
+    out = np.zeros((int(total), 2), dtype=np.int32)
+    got = _load().sjg_grid_join(_ptr(x), n, d, float(eps), _ptr(counts), _ptr(out))
+    if got != total:
+        raise RuntimeError("grid join: count and fill disagree")
+    return counts, out

@@ -164,13 +164,15 @@ constexpr uint32_t kMaskLdsWords = 8192;
 
 __global__ __launch_bounds__(kThreads) void k_cell_coords(const uint64_t *__restrict__ B,
                                                            const uint32_t *__restrict__ starts,
-                                                           uint64_t ncells, GridParams g,
+                                                           const uint32_t *__restrict__ last_cell,
+                                                           GridParams g,
                                                            uint32_t *__restrict__ coords,
                                                            uint32_t *__restrict__ masks,
                                                            const uint32_t *__restrict__ mask_off,
                                                            uint32_t mask_words,
                                                            uint32_t *__restrict__ max_pts) {
     __shared__ uint32_t lmask[kMaskLdsWords];
+    const uint64_t ncells = static_cast<uint64_t>(*last_cell) + 1;  // cell of the last sorted point + 1
     const bool use_lds = masks != nullptr && mask_words <= kMaskLdsWords;
     if (use_lds)
         for (uint32_t i = threadIdx.x; i < mask_words; i += kThreads) lmask[i] = 0;
@@ -180,16 +182,25 @@ __global__ __launch_bounds__(kThreads) void k_cell_coords(const uint64_t *__rest
          h += static_cast<uint64_t>(gridDim.x) * kThreads) {
         uint64_t id = B[h];
         for (uint32_t j = 0; j < g.d; ++j) {
-            const uint32_t c = static_cast<uint32_t>(id % g.dims[j]);
-            id /= g.dims[j];
+            uint32_t c;
+            if (id < (1ull << 32) && g.dims[j] < (1ull << 32)) {  // 32-bit division when it fits
+                const uint32_t id32 = static_cast<uint32_t>(id), dj = static_cast<uint32_t>(g.dims[j]);
+                c = id32 % dj;
+                id = id32 / dj;
+            } else {
+                c = static_cast<uint32_t>(id % g.dims[j]);
+                id /= g.dims[j];
+            }
             coords[h * g.d + j] = c;
             if (!masks) continue;
             const uint32_t w = mask_off[j] + (c >> 5);
             const uint32_t bit = 1u << (c & 31u);
-            if (use_lds)
-                atomicOr(&lmask[w], bit);
-            else
+            // most bits are set by the first cells that have them: test first
+            if (use_lds) {
+                if (!(lmask[w] & bit)) atomicOr(&lmask[w], bit);
+            } else {
                 atomicOr(&masks[w], bit);
+            }
         }
         const uint32_t sz = starts[h + 1] - starts[h];
         mp = sz > mp ? sz : mp;
@@ -227,6 +238,24 @@ __global__ __launch_bounds__(kThreads) void k_gather_soa(const double *__restric
     if (r >= n) return;
     const uint64_t i = perm[r];
     for (uint32_t j = 0; j < d; ++j) X[j * n + r] = pts[i * d + j];
+}
+
+// Even d with 16-byte aligned rows: one 16-byte load per coordinate pair.
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_gather_soa_v2(const double2 *__restrict__ pts,
+                                                             const uint32_t *__restrict__ perm,
+                                                             uint64_t n, double *__restrict__ X) {
+    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (r >= n) return;
+    const uint64_t i = perm[r];
+    double2 v[D / 2];
+#pragma unroll
+    for (int k = 0; k < D / 2; ++k) v[k] = pts[i * (D / 2) + k];
+#pragma unroll
+    for (int k = 0; k < D / 2; ++k) {
+        X[(2 * k) * n + r] = v[k].x;
+        X[(2 * k + 1) * n + r] = v[k].y;
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_make_f32(const double *__restrict__ X, uint64_t n,
@@ -326,36 +355,33 @@ void launch_cell_keys_u32(const double *pts, uint64_t n, const GridParams &g, ui
 }
 
 template <typename K>
-uint64_t build_cells(const K *sorted_keys, uint64_t n, uint32_t *cell_of, uint64_t *B,
-                     uint32_t *starts, hipStream_t s) {
+void build_cells(const K *sorted_keys, uint64_t n, uint32_t *cell_of, uint64_t *B, uint32_t *starts,
+                 hipStream_t s) {
     scan_head_flags_inclusive<K>(sorted_keys, cell_of, n, s);
-    uint32_t ncells = 0;
-    SJ_HIP(hipMemcpyAsync(&ncells, cell_of + (n - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     {
         KTimer kt_("cell_tables", s);
         k_cell_tables<K><<<blocks_for(n), kThreads, 0, s>>>(sorted_keys, n, cell_of, B, starts);
         SJ_LAUNCH_CHECK();
     }
-    SJ_HIP(hipStreamSynchronize(s));
-    return ncells;
 }
 
-template uint64_t build_cells<uint64_t>(const uint64_t *, uint64_t, uint32_t *, uint64_t *,
-                                        uint32_t *, hipStream_t);
-template uint64_t build_cells<uint32_t>(const uint32_t *, uint64_t, uint32_t *, uint64_t *,
-                                        uint32_t *, hipStream_t);
+template void build_cells<uint64_t>(const uint64_t *, uint64_t, uint32_t *, uint64_t *, uint32_t *,
+                                    hipStream_t);
+template void build_cells<uint32_t>(const uint32_t *, uint64_t, uint32_t *, uint64_t *, uint32_t *,
+                                    hipStream_t);
 
-void launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_t ncells,
-                              const GridParams &g, uint32_t *coords, uint32_t *masks,
+void launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_t ncells_bound,
+                              const uint32_t *last_cell, const GridParams &g, uint32_t *coords, uint32_t *masks,
                               const uint32_t *mask_off, uint32_t mask_words, uint32_t *max_pts,
                               hipStream_t s) {
     const uint64_t mw = masks ? mask_words : 0;
     k_zero2_u32<<<static_cast<unsigned>(std::min<uint64_t>(64, mw / 256 + 1)), 256, 0, s>>>(masks, mw, max_pts, 1);
     SJ_LAUNCH_CHECK();
-    const unsigned nb = static_cast<unsigned>(std::min<uint64_t>(256, (ncells + kThreads - 1) / kThreads));
+    // few workgroups: each flushes its LDS copy of the masks with atomics
+    const unsigned nb = static_cast<unsigned>(std::min<uint64_t>(256, (ncells_bound + kThreads - 1) / kThreads));
     {
         KTimer kt_("cell_coords_masks", s);
-        k_cell_coords<<<nb, kThreads, 0, s>>>(B, starts, ncells, g, coords, masks, mask_off, mask_words,
+        k_cell_coords<<<nb, kThreads, 0, s>>>(B, starts, last_cell, g, coords, masks, mask_off, mask_words,
                                              max_pts);
         SJ_LAUNCH_CHECK();
     }
@@ -365,7 +391,18 @@ void launch_gather_soa(const double *pts, const uint32_t *perm, uint64_t n, uint
                        hipStream_t s) {
     {
         KTimer kt_("gather_soa", s);
-        k_gather_soa<<<blocks_for(n), kThreads, 0, s>>>(pts, perm, n, d, X);
+        const bool al16 = (reinterpret_cast<uintptr_t>(pts) & 15u) == 0;
+        const double2 *p2 = reinterpret_cast<const double2 *>(pts);
+        if (al16 && d == 2)
+            k_gather_soa_v2<2><<<blocks_for(n), kThreads, 0, s>>>(p2, perm, n, X);
+        else if (al16 && d == 4)
+            k_gather_soa_v2<4><<<blocks_for(n), kThreads, 0, s>>>(p2, perm, n, X);
+        else if (al16 && d == 6)
+            k_gather_soa_v2<6><<<blocks_for(n), kThreads, 0, s>>>(p2, perm, n, X);
+        else if (al16 && d == 8)
+            k_gather_soa_v2<8><<<blocks_for(n), kThreads, 0, s>>>(p2, perm, n, X);
+        else
+            k_gather_soa<<<blocks_for(n), kThreads, 0, s>>>(pts, perm, n, d, X);
         SJ_LAUNCH_CHECK();
     }
 }

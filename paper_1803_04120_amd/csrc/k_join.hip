@@ -297,29 +297,53 @@ void launch_join_d(const JoinArgs &a, int unicomp, int mode, int band, hipStream
 
 // ------------------------------------------------------------ row plans
 // Row lengths in original order (for the output offsets) and in cell order
-// (for the fill layout), and the longest row (one atomic per workgroup).
+// (for the fill layout). Every workgroup writes its longest row and its
+// numbers of rows longer than 16, 24 and 32 entries to stats[4 b .. 4 b + 4)
+// (no atomics: 512 workgroups adding to one cache line serialised).
+constexpr int kRowStatBlocks = 512;
+static_assert(kRowStatWords == 4 * static_cast<size_t>(kRowStatBlocks), "row statistics layout");
 __global__ __launch_bounds__(kThreads) void k_row_lengths(const uint32_t *__restrict__ own,
                                                            const uint32_t *__restrict__ inc,
                                                            const uint32_t *__restrict__ perm,
                                                            uint64_t n, uint32_t *__restrict__ len,
                                                            uint32_t *__restrict__ len_cell,
-                                                           uint32_t *__restrict__ max_len) {
-    uint32_t m = 0;
+                                                           uint32_t *__restrict__ stats) {
+    uint32_t m = 0, c16 = 0, c24 = 0, c32 = 0;
     for (uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x; r < n;
          r += static_cast<uint64_t>(gridDim.x) * kThreads) {
         const uint32_t l = own[r] + (inc ? inc[r] : 0u);
         len[perm[r]] = l;
         len_cell[r] = l;
         m = l > m ? l : m;
+        c16 += l > 16u;
+        c24 += l > 24u;
+        c32 += l > 32u;
     }
     m = wave_max(m);
-    __shared__ uint32_t sm[kThreads / 64];
-    if (lane_id() == 0) sm[threadIdx.x >> 6] = m;
+    c16 = wave_sum(c16);
+    c24 = wave_sum(c24);
+    c32 = wave_sum(c32);
+    __shared__ uint32_t sm[4][kThreads / 64];
+    if (lane_id() == 0) {
+        sm[0][threadIdx.x >> 6] = m;
+        sm[1][threadIdx.x >> 6] = c16;
+        sm[2][threadIdx.x >> 6] = c24;
+        sm[3][threadIdx.x >> 6] = c32;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t b = sm[0];
-        for (int w = 1; w < kThreads / 64; ++w) b = sm[w] > b ? sm[w] : b;
-        if (b) atomicMax(max_len, b);
+        uint32_t b = sm[0][0], s16 = sm[1][0], s24 = sm[2][0], s32 = sm[3][0];
+        for (int w = 1; w < kThreads / 64; ++w) {
+            b = sm[0][w] > b ? sm[0][w] : b;
+            s16 += sm[1][w];
+            s24 += sm[2][w];
+            s32 += sm[3][w];
+        }
+        uint32_t *o = stats + 4 * static_cast<size_t>(blockIdx.x);
+        o[0] = b;
+        o[1] = s16;
+        o[2] = s24;
+        o[3] = s32;
     }
 }
 
@@ -427,43 +451,67 @@ void launch_join(const JoinArgs &a, uint32_t d, int unicomp, int mode, int band,
 }
 
 void launch_row_lengths(const uint32_t *own_cnt, const uint32_t *in_cnt, const uint32_t *perm,
-                        uint64_t n, uint32_t *len_orig, uint32_t *len_cell, uint32_t *max_len,
+                        uint64_t n, uint32_t *len_orig, uint32_t *len_cell, uint32_t *row_stats,
                         hipStream_t s) {
     KTimer kt_("row_lengths", s);
-    k_row_lengths<<<static_cast<unsigned>(std::min<uint64_t>(512, blocks_for(n))), kThreads, 0, s>>>(
-        own_cnt, in_cnt, perm, n, len_orig, len_cell, max_len);
+    k_row_lengths<<<kRowStatBlocks, kThreads, 0, s>>>(own_cnt, in_cnt, perm, n, len_orig, len_cell, row_stats);
     SJ_LAUNCH_CHECK();
 }
 
 // out[0] = P (off_orig[n]), out[1] = longest row, out[2] = evaluations,
 // out[3] = band re-checks (both summed over the counter slots), out[4] =
-// chunk count (0 without chunks): the count pass reads these back at once.
+// chunk count (0 without chunks), out[5..8) = rows longer than 16, 24, 32
+// (row_stats[1..4)): the count pass reads these back at once.
 __global__ __launch_bounds__(256) void k_count_summary(const uint64_t *__restrict__ off_orig, uint64_t n,
                                                         const uint32_t *__restrict__ max_len,
                                                         const unsigned long long *__restrict__ counters,
                                                         const uint32_t *__restrict__ nchunks,
                                                         uint64_t *__restrict__ out) {
-    __shared__ unsigned long long part[2][256 / 64];
-    const int k = threadIdx.x;  // one counter slot per thread
+    __shared__ unsigned long long part[6][256 / 64];
+    const int k = threadIdx.x;  // one counter slot and two row-stat blocks per thread
     unsigned long long e = counters[static_cast<size_t>(k) * kCounterStride];
     unsigned long long b = counters[static_cast<size_t>(kCounterSlots + k) * kCounterStride];
+    unsigned long long mx = 0, c16 = 0, c24 = 0, c32 = 0;
+    for (int q = k; q < kRowStatBlocks; q += 256) {
+        const uint32_t *st = max_len + 4 * q;
+        mx = st[0] > mx ? st[0] : mx;
+        c16 += st[1];
+        c24 += st[2];
+        c32 += st[3];
+    }
     for (int off = 32; off > 0; off >>= 1) {
         e += __shfl_xor(e, off, 64);
         b += __shfl_xor(b, off, 64);
+        const unsigned long long om = __shfl_xor(mx, off, 64);
+        mx = om > mx ? om : mx;
+        c16 += __shfl_xor(c16, off, 64);
+        c24 += __shfl_xor(c24, off, 64);
+        c32 += __shfl_xor(c32, off, 64);
     }
     if (lane_id() == 0) {
         part[0][k >> 6] = e;
         part[1][k >> 6] = b;
+        part[2][k >> 6] = mx;
+        part[3][k >> 6] = c16;
+        part[4][k >> 6] = c24;
+        part[5][k >> 6] = c32;
     }
     __syncthreads();
     if (k == 0) {
-        unsigned long long se = 0, sb = 0;
+        unsigned long long se = 0, sb = 0, m = 0, s16 = 0, s24 = 0, s32 = 0;
         for (int w = 0; w < 256 / 64; ++w) {
             se += part[0][w];
             sb += part[1][w];
+            m = part[2][w] > m ? part[2][w] : m;
+            s16 += part[3][w];
+            s24 += part[4][w];
+            s32 += part[5][w];
         }
         out[0] = off_orig[n];
-        out[1] = *max_len;
+        out[1] = m;
+        out[5] = s16;
+        out[6] = s24;
+        out[7] = s32;
         out[2] = se;
         out[3] = sb;
         out[4] = nchunks ? *nchunks : 0;

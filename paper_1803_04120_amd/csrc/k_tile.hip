@@ -106,6 +106,11 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     uint32_t own = 0, evals = 0, rechecks = 0;
     const uint32_t chunk = xcd_block_index() * kWaves + wave;
     if (chunk < *t.nchunks_dev) {  // uniform across the wave
+        // segment table of the chunk, 64 rows per register load; the first
+        // load is issued before anything else (it needs only the chunk index)
+        const uint2 *segs = t.segs + static_cast<size_t>(chunk) * t.rows_per_chunk;
+        uint32_t seg_base = 0;
+        uint2 seg_reg = static_cast<uint32_t>(lane) < t.rows_per_chunk ? segs[lane] : make_uint2(0, 0);
         const uint2 ch = t.chunks[chunk];
         const uint32_t p = ch.x + static_cast<uint32_t>(lane);
         const bool active = p < ch.y;
@@ -131,10 +136,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             if (kMode == kFill) {
                 my_row = a.offc[p] - a.out_base;
                 perm_p = a.perm[p];
-                if (NS > 0) {
-                    row_len = static_cast<uint32_t>(a.offc[p + 1] - a.offc[p]);
-                    row_dst = a.off_orig[perm_p];  // used at the end; loaded early
-                }
+                if (NS > 0) row_len = static_cast<uint32_t>(a.offc[p + 1] - a.offc[p]);
             }
         }
         // fused fill: rows that fit stay in the lane's LDS slot
@@ -299,10 +301,6 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             }
             return false;
         };
-        // segment table of the chunk, 64 rows per register load
-        const uint2 *segs = t.segs + static_cast<size_t>(chunk) * t.rows_per_chunk;
-        uint32_t seg_base = 0xffffffffu;
-        uint2 seg_reg = make_uint2(0, 0);
         auto segment = [&](uint32_t ridx) -> uint2 {
             const uint32_t base = ridx & ~63u;
             if (base != seg_base) {
@@ -360,6 +358,9 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         constexpr bool kPrefetch = !kAgg;
         Tile cur = advance(Tile{0, 0, 0, false, false});
         if (kPrefetch && cur.valid) load_tile(cur);
+        // fused fill: the row's place in the result (needs perm_p; used at
+        // the end, loaded after the first tile's loads are in flight)
+        if (NS > 0 && active) row_dst = a.off_orig[perm_p];
         while (cur.valid) {
             const uint32_t len = (cur.P1 - cur.T0) < static_cast<uint32_t>(TS) ? (cur.P1 - cur.T0) : TS;
             wave_sync_lds();
@@ -393,19 +394,19 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         if (kMode == kFill && NS > 0 && !kUni) {
             // the row of p is complete: sort it in registers; a row longer
             // than the LDS slot is in out_j for the row-sort kernels
-            constexpr int kNs = NS > 0 ? NS : 1;
+            constexpr int kNs = NS <= 0 ? 1 : (NS <= 16 ? 16 : (NS <= 32 ? 32 : 64));  // sort width >= NS
             const uint32_t len = own;
             uint32_t lds_len = 0;
             if (active && own != row_len) atomicOr(a.overflow, 1u);  // count and fill disagree
-            if (active && row_in_lds && len <= static_cast<uint32_t>(kNs)) {
+            if (active && row_in_lds && len <= static_cast<uint32_t>(NS > 0 ? NS : 1)) {
                 uint32_t v[kNs];
 #pragma unroll
                 for (int k = 0; k < kNs; ++k)
-                    v[k] = static_cast<uint32_t>(k) < len ? srow[k] : 0xffffffffu;
+                    v[k] = (k < (NS > 0 ? NS : 1) && static_cast<uint32_t>(k) < len) ? srow[k] : 0xffffffffu;
                 register_bitonic<kNs>(v);
 #pragma unroll
                 for (int k = 0; k < kNs; ++k)
-                    if (static_cast<uint32_t>(k) < len) srow[k] = v[k];
+                    if (k < (NS > 0 ? NS : 1) && static_cast<uint32_t>(k) < len) srow[k] = v[k];
                 lds_len = len;
             }
             wave_sync_lds();  // last tile's reads of the staging slot are done
@@ -486,8 +487,10 @@ void launch_tiled_d(const JoinArgs &a, const TileArgs &t, int unicomp, int mode,
                     hipStream_t s, uint32_t fused_sort) {
     const int sel = (mode == kFill ? 4 : 0) + (unicomp ? 2 : 0) + (band ? 1 : 0);
     if (sel == 4 && fused_sort == 16) return launch_tiled_one<D, false, kFill, false, 16>(a, t, s);
+    if (sel == 4 && fused_sort == 24) return launch_tiled_one<D, false, kFill, false, 24>(a, t, s);
     if (sel == 4 && fused_sort == 32) return launch_tiled_one<D, false, kFill, false, 32>(a, t, s);
     if (sel == 5 && fused_sort == 16) return launch_tiled_one<D, false, kFill, true, 16>(a, t, s);
+    if (sel == 5 && fused_sort == 24) return launch_tiled_one<D, false, kFill, true, 24>(a, t, s);
     if (sel == 5 && fused_sort == 32) return launch_tiled_one<D, false, kFill, true, 32>(a, t, s);
     if (fused_sort) throw Error(SJ_EINVAL, "tiled join: fused sort needs a full fill");
     switch (sel) {

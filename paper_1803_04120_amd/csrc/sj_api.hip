@@ -158,6 +158,7 @@ struct sj_index {
     DevBuf<uint64_t> summary;  // count pass results read back together
     uint64_t pairs = 0;
     uint32_t max_row = 0;
+    uint64_t rows_longer[3] = {0, 0, 0};  // rows longer than 16, 24, 32
     sj_stats stats{};
 
     ~sj_index() {
@@ -271,7 +272,7 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
             std::swap(keys, keys_alt);
             std::swap(ix.perm, ids_alt);
         }
-        ix.ncells = sj::build_cells<uint32_t>(keys.ptr, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
+        sj::build_cells<uint32_t>(keys.ptr, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
     } else {
         DevBuf<uint64_t> keys(n), keys_alt(n);
         sj::launch_cell_keys_u64(dp, n, ix.grid, keys.ptr, ix.perm.ptr, s);
@@ -279,7 +280,7 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
             std::swap(keys, keys_alt);
             std::swap(ix.perm, ids_alt);
         }
-        ix.ncells = sj::build_cells<uint64_t>(keys.ptr, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
+        sj::build_cells<uint64_t>(keys.ptr, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
     }
     // per-cell coordinates and occupancy masks M_j (Section IV-C)
     uint64_t words = 0;
@@ -295,9 +296,11 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
     } else {
         ix.mask_words = 0;  // masks only prune; a grid this wide goes without
     }
-    ix.coords.reset(ix.ncells * d);
+    // |G| stays on the device until the end of the build: tables that depend
+    // on it are sized by n (an upper bound)
+    ix.coords.reset(n * d);
     ix.max_cell_dev.ensure(1);
-    sj::launch_cell_coords_masks(ix.B.ptr, ix.starts.ptr, ix.ncells, ix.grid, ix.coords.ptr,
+    sj::launch_cell_coords_masks(ix.B.ptr, ix.starts.ptr, n, ix.cell_of.ptr + (n - 1), ix.grid, ix.coords.ptr,
                                  ix.masks.ptr, moff.ptr, ix.mask_words, ix.max_cell_dev.ptr, s);
     // cell-ordered structure of arrays
     ix.X.reset(n * d);
@@ -307,7 +310,10 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
         ix.extent = std::max(ix.extent, std::max(std::fabs(ix.bmax[j] - ix.shift[j]),
                                                  std::fabs(ix.bmin[j] - ix.shift[j])));
     }
+    uint32_t last_cell = 0;
+    SJ_HIP(hipMemcpyAsync(&last_cell, ix.cell_of.ptr + (n - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
+    ix.ncells = static_cast<uint64_t>(last_cell) + 1;
     ix.stats.ms_build = now_ms() - t0;
 }
 
@@ -364,6 +370,23 @@ sj::TileArgs tile_args(sj_index &ix) {
 bool use_fused_sort() {
     const char *e = std::getenv("SJ_FUSED_SORT");
     return !(e && std::strcmp(e, "0") == 0);
+}
+
+// Entries per lane in the fused fill's LDS row slot (SJ_FUSED_NS=16|24|32
+// overrides). A larger slot keeps more rows out of out_j (a longer row costs
+// the wave a sort of its own) but holds more LDS per wave, so fewer waves fit
+// on a CU (5, 4, 3 for 16, 24, 32 in 2-D). The smallest slot that at most 5%
+// of the rows exceed; 32 otherwise.
+uint32_t fused_slot(const sj_index &ix) {
+    const char *e = std::getenv("SJ_FUSED_NS");
+    if (e) {
+        const int v = std::atoi(e);
+        if (v == 16 || v == 24 || v == 32) return static_cast<uint32_t>(v);
+    }
+    const double lim = 0.05 * static_cast<double>(ix.n);
+    if (static_cast<double>(ix.rows_longer[0]) <= lim) return 16u;
+    if (static_cast<double>(ix.rows_longer[1]) <= lim) return 24u;
+    return 32u;
 }
 
 void ensure_chunks(sj_index &ix, hipStream_t s) {
@@ -452,11 +475,10 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     ix.offc_ready = false;
     const size_t nctr = 2 * sj::kCounterSlots * sj::kCounterStride;
     ix.counters.ensure(nctr);
-    ix.max_len.ensure(1);
+    ix.max_len.ensure(sj::kRowStatWords);
     sj::ZeroSpans z{};
     if (uni) z.add(ix.in_cnt.ptr, n);
     z.add(ix.counters.ptr, 2 * nctr);
-    z.add(ix.max_len.ptr, 1);
     sj::launch_zero_spans(z, s);
     sj::JoinArgs a = base_args(ix, uni);
     if (tiled)
@@ -466,10 +488,10 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     sj::launch_row_lengths(ix.own_cnt.ptr, uni ? ix.in_cnt.ptr : nullptr, ix.perm.ptr, n,
                            ix.len_orig.ptr, ix.len_cell.ptr, ix.max_len.ptr, s);
     sj::scan_exclusive_u32_to_u64_x2(ix.len_orig.ptr, ix.off_orig.ptr, ix.len_cell.ptr, ix.off_cell.ptr, n, s);
-    ix.summary.ensure(5);
+    ix.summary.ensure(8);
     sj::launch_count_summary(ix.off_orig.ptr, n, ix.max_len.ptr, ix.counters.ptr,
                              tiled ? ix.nchunks_dev.ptr : nullptr, ix.summary.ptr, s);
-    uint64_t sm[5];
+    uint64_t sm[8];
     SJ_HIP(hipMemcpyAsync(sm, ix.summary.ptr, sizeof(sm), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
     ix.pairs = sm[0];
@@ -477,6 +499,7 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     ix.stats.evals = sm[2];
     ix.stats.band_rechecks = sm[3];
     if (tiled) ix.stats.chunks = static_cast<uint32_t>(sm[4]);
+    for (int k = 0; k < 3; ++k) ix.rows_longer[k] = sm[5 + k];
     ix.stats.pairs = ix.pairs;
     ix.stats.max_row_pairs = ix.max_row;
     ix.stats.ranges = tiled ? 0 : ix.ranges[uni].count;
@@ -538,7 +561,7 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
     if (tiled) {
         uint32_t ns = 0;
         if (fused) {
-            ns = ix.max_row <= 16 ? 16 : 32;
+            ns = fused_slot(ix);
             a.off_orig = ix.off_orig.ptr;
             a.pairs = reinterpret_cast<uint2 *>(pairs);
         }

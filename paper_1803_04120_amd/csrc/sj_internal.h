@@ -127,14 +127,17 @@ void launch_cell_keys_u32(const double *pts, uint64_t n, const GridParams &g, ui
                           uint32_t *ids, hipStream_t s);
 // head flags + inclusive scan + cell tables. cell_of receives the cell of
 // each cell-ordered point, B the distinct ids, starts the first point of
-// each cell (starts[|G|] is written as n). Returns |G| (host sync).
+// each cell (starts[|G|] is written as n); |G| = cell_of[n - 1] + 1 (left on
+// the device: no host sync).
 template <typename K>
-uint64_t build_cells(const K *sorted_keys, uint64_t n, uint32_t *cell_of, uint64_t *B,
-                     uint32_t *starts, hipStream_t s);
+void build_cells(const K *sorted_keys, uint64_t n, uint32_t *cell_of, uint64_t *B, uint32_t *starts,
+                 hipStream_t s);
 // per-cell coordinates (cell-major, d per cell), occupancy masks, and the
-// largest cell (written to *max_pts on the device).
-void launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_t ncells,
-                              const GridParams &g, uint32_t *coords, uint32_t *masks,
+// largest cell (written to *max_pts on the device). The cell count is read
+// on the device (*last_cell + 1, the cell of the last sorted point);
+// ncells_bound (>= it) sizes the launch.
+void launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_t ncells_bound,
+                              const uint32_t *last_cell, const GridParams &g, uint32_t *coords, uint32_t *masks,
                               const uint32_t *mask_off, uint32_t mask_words, uint32_t *max_pts,
                               hipStream_t s);
 void launch_gather_soa(const double *pts, const uint32_t *perm, uint64_t n, uint32_t d,
@@ -241,13 +244,16 @@ void build_chunk_segments(const TileArgs &t, const uint32_t *cell_of, const uint
 void launch_join_tiled(const JoinArgs &a, const TileArgs &t, uint32_t d, int unicomp, int mode,
                        int band, hipStream_t s, uint32_t fused_sort = 0);
 
-// row lengths in original order, exclusive offsets (u64, n+1), row offsets
-// in cell order, max row length (device).
+// Row lengths in original order and in cell order; row_stats
+// (4 x kRowStatWords/4 words, no clearing needed) gets per-workgroup longest
+// rows and numbers of rows longer than 16, 24 and 32.
+constexpr size_t kRowStatWords = 4 * 512;
 void launch_row_lengths(const uint32_t *own_cnt, const uint32_t *in_cnt, const uint32_t *perm,
-                        uint64_t n, uint32_t *len_orig, uint32_t *len_cell, uint32_t *max_len,
+                        uint64_t n, uint32_t *len_orig, uint32_t *len_cell, uint32_t *row_stats,
                         hipStream_t s);
-// Gathers the count pass results into out[0..5): P, longest row,
-// evaluations, band re-checks, chunk count (nchunks may be null).
+// Gathers the count pass results into out[0..8): P, longest row,
+// evaluations, band re-checks, chunk count (nchunks may be null), rows
+// longer than 16, 24, 32 (max_len = the row_stats of launch_row_lengths).
 void launch_count_summary(const uint64_t *off_orig, uint64_t n, const uint32_t *max_len,
                           const unsigned long long *counters, const uint32_t *nchunks, uint64_t *out,
                           hipStream_t s);

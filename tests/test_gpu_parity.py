@@ -95,6 +95,23 @@ def test_parity_both_kernels(sj, join_kernel, kind, d, n, eps, mode):
     assert_same(gpu_pairs(sj, pts, eps, **mode), want, f"{join_kernel} {kind}-{d}d {mode}")
 
 
+@pytest.mark.parametrize("slot", ["16", "24", "32"])
+@pytest.mark.parametrize("kind,d,n,eps", [("uniform", 2, 30011, 1.8), ("clustered", 2, 30011, 0.25),
+                                          ("uniform", 3, 20011, 6.8)])
+def test_fused_fill_slot_sizes(sj, monkeypatch, slot, kind, d, n, eps):
+    """The fused fill with each LDS row-slot size: rows that fit are sorted in
+    registers, longer ones (up to 64) by the wave, longer still by the row-sort
+    kernels; all must give the oracle's pairs."""
+    monkeypatch.setenv("SJ_FUSED_NS", slot)
+    _say(f"fused slot {slot} {kind} d={d} n={n} eps={eps}")
+    pts = datagen.make(kind, n, d, seed=3000 + d)
+    want = ref.pairs(pts, eps)
+    lens = np.bincount(want[:, 0], minlength=n)
+    assert lens.max() > 64 or kind == "uniform"
+    assert (lens > int(slot)).any()
+    assert_same(gpu_pairs(sj, pts, eps, unicomp=False), want, f"slot {slot} {kind}-{d}d")
+
+
 # ---------------------------------------------------------------- edges
 def test_empty_and_single(sj):
     _say("empty and single point")

@@ -202,3 +202,28 @@ def test_pins_catch_planted_mistakes(kind):
         if bad(pts, 1.5).shape[0] != lattice_count(k, d, num, den):
             failures += 1
     assert failures > 0, f"planted mistake {kind!r} went unnoticed"
+
+
+# ----------------------------------------------------- CPU grid-join baseline
+@pytest.mark.parametrize("kind,d,n,eps", [("uniform", 2, 20011, 0.6), ("clustered", 2, 20011, 0.3),
+                                          ("clustered", 3, 15013, 0.9), ("uniform", 4, 12007, 9.0),
+                                          ("uniform", 6, 7919, 22.0), ("uniform", 1, 5003, 0.05),
+                                          ("uniform", 8, 3001, 40.0)])
+def test_cpu_grid_join_equals_brute_force(kind, d, n, eps):
+    """The host-core grid join (the baseline the GPU is reported against)
+    gives the brute force's pairs in the same (i, j) order."""
+    pts = datagen.make(kind, n, d, seed=77 + d)
+    counts, got = ref.grid_join(pts, eps)
+    want = ref.pairs(pts, eps)
+    assert np.array_equal(got.astype(np.int64), want)
+    assert np.array_equal(counts, ref.count_rows(pts, eps))
+
+
+def test_cpu_grid_join_lattice_boundaries():
+    """Lattice points at spacing 1 with eps exactly 1: every axis neighbour
+    sits on a cell boundary and must be found."""
+    for d in (1, 2, 3):
+        g = np.stack(np.meshgrid(*[np.arange(6, dtype=np.float64)] * d, indexing="ij"), -1).reshape(-1, d)
+        _, got = ref.grid_join(g, 1.0)
+        assert np.array_equal(got.astype(np.int64), ref.pairs(g, 1.0))
+        assert got.shape[0] == g.shape[0] * (1 + 2 * d) - 2 * d * 6 ** (d - 1)
