@@ -124,6 +124,16 @@ __global__ __launch_bounds__(kThreads) void k_bbox_final(const double *__restric
     }
 }
 
+// Dimension-j cell coordinate of value v: clamp(floor((v - g_j^min) / w),
+// 0, |g_j| - 1); |g_j| < 2^31. Every kernel that needs a cell coordinate of
+// a point uses this one function, so they agree bit for bit.
+__device__ __forceinline__ uint32_t cell_coord(double v, const GridParams &g, int j) {
+    const double t = (v - g.gmin[j]) / g.w;
+    const double top = static_cast<double>(g.dims[j] - 1);
+    const double f = floor(t);
+    return static_cast<uint32_t>(f <= 0.0 ? 0 : (f >= top ? g.dims[j] - 1 : static_cast<uint64_t>(f)));
+}
+
 template <typename K>
 __global__ __launch_bounds__(kThreads) void k_cell_keys(const double *__restrict__ pts, uint64_t n,
                                                          GridParams g, K *__restrict__ keys,
@@ -131,13 +141,8 @@ __global__ __launch_bounds__(kThreads) void k_cell_keys(const double *__restrict
     const uint64_t i = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
     if (i >= n) return;
     uint64_t key = 0;
-    for (uint32_t j = 0; j < g.d; ++j) {
-        const double t = (pts[i * g.d + j] - g.gmin[j]) / g.w;
-        const double top = static_cast<double>(g.dims[j] - 1);
-        const double f = floor(t);
-        const uint64_t c = f <= 0.0 ? 0 : (f >= top ? g.dims[j] - 1 : static_cast<uint64_t>(f));
-        key += c * g.stride[j];
-    }
+    for (uint32_t j = 0; j < g.d; ++j)
+        key += static_cast<uint64_t>(cell_coord(pts[i * g.d + j], g, static_cast<int>(j))) * g.stride[j];
     keys[i] = static_cast<K>(key);
     ids[i] = static_cast<uint32_t>(i);
 }
@@ -233,18 +238,21 @@ __global__ void k_zero2_u32(uint32_t *p, uint64_t n, uint32_t *q, uint64_t m) {
 __global__ __launch_bounds__(kThreads) void k_gather_soa(const double *__restrict__ pts,
                                                           const uint32_t *__restrict__ perm,
                                                           uint64_t n, uint32_t d,
-                                                          double *__restrict__ X) {
+                                                          double *__restrict__ X, GridParams g,
+                                                          uint32_t *__restrict__ cx) {
     const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
     if (r >= n) return;
     const uint64_t i = perm[r];
     for (uint32_t j = 0; j < d; ++j) X[j * n + r] = pts[i * d + j];
+    cx[r] = cell_coord(pts[i * d], g, 0);
 }
 
 // Even d with 16-byte aligned rows: one 16-byte load per coordinate pair.
 template <int D>
 __global__ __launch_bounds__(kThreads) void k_gather_soa_v2(const double2 *__restrict__ pts,
                                                              const uint32_t *__restrict__ perm,
-                                                             uint64_t n, double *__restrict__ X) {
+                                                             uint64_t n, double *__restrict__ X, GridParams g,
+                                                             uint32_t *__restrict__ cx) {
     const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
     if (r >= n) return;
     const uint64_t i = perm[r];
@@ -256,6 +264,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_soa_v2(const double2 *__res
         X[(2 * k) * n + r] = v[k].x;
         X[(2 * k + 1) * n + r] = v[k].y;
     }
+    cx[r] = cell_coord(v[0].x, g, 0);
 }
 
 __global__ __launch_bounds__(kThreads) void k_make_f32(const double *__restrict__ X, uint64_t n,
@@ -388,21 +397,21 @@ void launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_
 }
 
 void launch_gather_soa(const double *pts, const uint32_t *perm, uint64_t n, uint32_t d, double *X,
-                       hipStream_t s) {
+                       const GridParams &g, uint32_t *cx, hipStream_t s) {
     {
         KTimer kt_("gather_soa", s);
         const bool al16 = (reinterpret_cast<uintptr_t>(pts) & 15u) == 0;
         const double2 *p2 = reinterpret_cast<const double2 *>(pts);
         if (al16 && d == 2)
-            k_gather_soa_v2<2><<<blocks_for(n), kThreads, 0, s>>>(p2, perm, n, X);
+            k_gather_soa_v2<2><<<blocks_for(n), kThreads, 0, s>>>(p2, perm, n, X, g, cx);
         else if (al16 && d == 4)
-            k_gather_soa_v2<4><<<blocks_for(n), kThreads, 0, s>>>(p2, perm, n, X);
+            k_gather_soa_v2<4><<<blocks_for(n), kThreads, 0, s>>>(p2, perm, n, X, g, cx);
         else if (al16 && d == 6)
-            k_gather_soa_v2<6><<<blocks_for(n), kThreads, 0, s>>>(p2, perm, n, X);
+            k_gather_soa_v2<6><<<blocks_for(n), kThreads, 0, s>>>(p2, perm, n, X, g, cx);
         else if (al16 && d == 8)
-            k_gather_soa_v2<8><<<blocks_for(n), kThreads, 0, s>>>(p2, perm, n, X);
+            k_gather_soa_v2<8><<<blocks_for(n), kThreads, 0, s>>>(p2, perm, n, X, g, cx);
         else
-            k_gather_soa<<<blocks_for(n), kThreads, 0, s>>>(pts, perm, n, d, X);
+            k_gather_soa<<<blocks_for(n), kThreads, 0, s>>>(pts, perm, n, d, X, g, cx);
         SJ_LAUNCH_CHECK();
     }
 }

@@ -42,6 +42,19 @@ struct ScanOps {
     Tout *total[2];
 };
 
+// Grid-row head flag of cell h: its dimension-1..d-1 coordinates differ
+// from those of cell h - 1 (cells sorted by linear id, dimension 0 fastest).
+struct RowHeadLoad {
+    const uint32_t *coords;
+    uint32_t d;
+    __device__ __forceinline__ uint32_t operator()(size_t h) const {
+        if (h == 0) return 1u;
+        uint32_t f = 0;
+        for (uint32_t j = 1; j < d; ++j) f |= coords[h * d + j] != coords[(h - 1) * d + j];
+        return f;
+    }
+};
+
 template <typename Tacc, typename Load>
 __global__ __launch_bounds__(kThreads) void k_tile_sum(ScanOps<Tacc, Load> ops, size_t n,
                                                         Tacc *__restrict__ part_all) {
@@ -202,6 +215,11 @@ void scan_inclusive_u32(uint32_t *data, size_t n, hipStream_t s) {
 
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, hipStream_t s) {
     scan_one<uint32_t, false>(ArrayLoad<uint32_t>{in}, out, n, nullptr, s);
+}
+
+void scan_row_heads_exclusive(const uint32_t *coords, uint32_t d, uint64_t *row_of, size_t ncells,
+                              hipStream_t s) {
+    scan_one<uint64_t, false>(RowHeadLoad{coords, d}, row_of, ncells, row_of + ncells, s);
 }
 
 template <typename K>

@@ -37,7 +37,7 @@ constexpr int kWaves = kThreads / 64;
 // stages half as many.
 template <int D, int NS>
 struct TileSize {
-    static constexpr int base = D <= 3 ? 256 : (D <= 6 ? 128 : 64);
+    static constexpr int base = D <= 6 ? 128 : 64;
     static constexpr int half = NS > 0 ? base / 2 : base;
     static constexpr int value = half < 64 ? 64 : half;  // at least one candidate per lane
 };
@@ -507,27 +507,14 @@ void launch_tiled_d(const JoinArgs &a, const TileArgs &t, int unicomp, int mode,
 }
 
 // ------------------------------------------------------------ chunk list
-__global__ __launch_bounds__(kThreads) void k_row_heads(const uint32_t *__restrict__ coords,
-                                                         uint32_t ncells, uint32_t d,
-                                                         uint32_t *__restrict__ flag) {
-    const uint32_t h = blockIdx.x * kThreads + threadIdx.x;
-    if (h >= ncells) return;
-    uint32_t f = h == 0 ? 1u : 0u;
-    if (h > 0)
-        for (uint32_t j = 1; j < d; ++j)
-            f |= coords[static_cast<size_t>(h) * d + j] != coords[static_cast<size_t>(h - 1) * d + j];
-    flag[h] = f;
-}
-
 // First point of every grid row (row index = exclusive scan of the row-head
 // flags, total at row_of[ncells]); row_pt[nrows] = n.
-__global__ __launch_bounds__(kThreads) void k_row_points(const uint32_t *__restrict__ flag,
-                                                          const uint64_t *__restrict__ row_of,
+__global__ __launch_bounds__(kThreads) void k_row_points(const uint64_t *__restrict__ row_of,
                                                           const uint32_t *__restrict__ starts,
                                                           uint32_t ncells, uint32_t n,
                                                           uint32_t *__restrict__ row_pt) {
     const uint32_t h = blockIdx.x * kThreads + threadIdx.x;
-    if (h < ncells && flag[h]) row_pt[row_of[h]] = starts[h];
+    if (h < ncells && row_of[h + 1] != row_of[h]) row_pt[row_of[h]] = starts[h];  // h heads a row
     if (h == 0) row_pt[row_of[ncells]] = n;
 }
 
@@ -596,15 +583,6 @@ __global__ __launch_bounds__(kThreads) void k_chunk_segments(TileArgs t, const u
     segs[idx] = sg;
 }
 
-__global__ __launch_bounds__(kThreads) void k_point_c0(const uint32_t *__restrict__ cell_of,
-                                                        const uint32_t *__restrict__ coords,
-                                                        uint32_t n, uint32_t d,
-                                                        uint32_t *__restrict__ cx) {
-    const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
-    if (r >= n) return;
-    cx[r] = coords[static_cast<size_t>(cell_of[r]) * d];
-}
-
 __global__ void k_zero_word(uint32_t *p) {
     if (threadIdx.x == 0) *p = 0;
 }
@@ -613,9 +591,9 @@ inline unsigned nblk(uint64_t n) { return static_cast<unsigned>((n + kThreads - 
 
 }  // namespace
 
-uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, const uint32_t *cell_of,
-                      uint32_t ncells, uint32_t n, uint32_t d, uint64_t rows_bound, uint32_t *cx,
-                      uint2 **chunks_out, size_t *chunks_cap, uint32_t *nchunks_dev, hipStream_t s) {
+uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, uint32_t ncells, uint32_t n, uint32_t d,
+                      uint64_t rows_bound, uint2 **chunks_out, size_t *chunks_cap, uint32_t *nchunks_dev,
+                      hipStream_t s) {
     // chunk list only; row segments come from build_chunk_segments
     if (ncells == 0 || n == 0) {
         k_zero_word<<<1, 64, 0, s>>>(nchunks_dev);
@@ -624,15 +602,11 @@ uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, const uint
     }
     const uint64_t bound = static_cast<uint64_t>(n) / 64 + std::min<uint64_t>(ncells, rows_bound);
     if (bound >= 0xffffffffULL) throw Error(SJ_ECAPACITY, "too many join chunks");
-    k_point_c0<<<nblk(n), kThreads, 0, s>>>(cell_of, coords, n, d, cx);
-    SJ_LAUNCH_CHECK();
     // rows are bounded by the cells, so every array below is sized by ncells
-    DevBuf<uint32_t> flag(ncells), row_pt(static_cast<size_t>(ncells) + 1), nch(ncells);
+    DevBuf<uint32_t> row_pt(static_cast<size_t>(ncells) + 1), nch(ncells);
     DevBuf<uint64_t> row_of(static_cast<size_t>(ncells) + 1), choff(static_cast<size_t>(ncells) + 1);
-    k_row_heads<<<nblk(ncells), kThreads, 0, s>>>(coords, ncells, d, flag.ptr);
-    SJ_LAUNCH_CHECK();
-    scan_exclusive_u32_to_u64(flag.ptr, row_of.ptr, ncells, s);
-    k_row_points<<<nblk(ncells), kThreads, 0, s>>>(flag.ptr, row_of.ptr, starts, ncells, n, row_pt.ptr);
+    scan_row_heads_exclusive(coords, d, row_of.ptr, ncells, s);
+    k_row_points<<<nblk(ncells), kThreads, 0, s>>>(row_of.ptr, starts, ncells, n, row_pt.ptr);
     SJ_LAUNCH_CHECK();
     k_row_nchunks<<<nblk(ncells), kThreads, 0, s>>>(row_pt.ptr, row_of.ptr, ncells, nch.ptr);
     SJ_LAUNCH_CHECK();

@@ -304,7 +304,8 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
                                  ix.masks.ptr, moff.ptr, ix.mask_words, ix.max_cell_dev.ptr, s);
     // cell-ordered structure of arrays
     ix.X.reset(n * d);
-    sj::launch_gather_soa(dp, ix.perm.ptr, n, d, ix.X.ptr, s);
+    ix.cx.reset(n);
+    sj::launch_gather_soa(dp, ix.perm.ptr, n, d, ix.X.ptr, ix.grid, ix.cx.ptr, s);
     for (uint32_t j = 0; j < d; ++j) {
         ix.shift[j] = 0.5 * (ix.bmin[j] + ix.bmax[j]);
         ix.extent = std::max(ix.extent, std::max(std::fabs(ix.bmax[j] - ix.shift[j]),
@@ -391,15 +392,14 @@ uint32_t fused_slot(const sj_index &ix) {
 
 void ensure_chunks(sj_index &ix, hipStream_t s) {
     if (ix.chunks_ready) return;
-    ix.cx.ensure(ix.n);
     ix.nchunks_dev.ensure(1);
     // grid rows: one per occupied combination of the dimension-1..d-1 cells
     uint64_t rows_bound = 1;
     for (uint32_t j = 1; j < ix.d; ++j)
         rows_bound = ix.grid.dims[j] > (UINT64_MAX / 2) / rows_bound ? UINT64_MAX / 2 : rows_bound * ix.grid.dims[j];
-    ix.nchunks = sj::build_chunks(ix.coords.ptr, ix.starts.ptr, ix.cell_of.ptr,
-                                  static_cast<uint32_t>(ix.ncells), static_cast<uint32_t>(ix.n), ix.d,
-                                  rows_bound, ix.cx.ptr, &ix.chunks, &ix.chunks_cap, ix.nchunks_dev.ptr, s);
+    ix.nchunks = sj::build_chunks(ix.coords.ptr, ix.starts.ptr, static_cast<uint32_t>(ix.ncells),
+                                  static_cast<uint32_t>(ix.n), ix.d, rows_bound, &ix.chunks, &ix.chunks_cap,
+                                  ix.nchunks_dev.ptr, s);
     uint32_t r3 = 1;
     for (uint32_t j = 1; j < ix.d; ++j) r3 *= 3;
     ix.rows_per_chunk = r3;

@@ -102,6 +102,11 @@ void scan_exclusive_u32_to_u64_x2(const uint32_t *in0, uint64_t *out0, const uin
 void scan_inclusive_u32(uint32_t *data, size_t n, hipStream_t s);
 // exclusive scan of u32 into u32 (no total), in place allowed.
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, hipStream_t s);
+// Exclusive scan of the grid-row head flags of the cells (coordinates
+// cell-major, d per cell): row_of[h] = rows starting before cell h,
+// row_of[ncells] = number of rows.
+void scan_row_heads_exclusive(const uint32_t *coords, uint32_t d, uint64_t *row_of, size_t ncells,
+                              hipStream_t s);
 // Inclusive scan of the head flags (key[r] != key[r-1], 1 at r = 0) of a
 // sorted key array: out[r] = 1 + number of distinct keys before r.
 template <typename K>
@@ -140,8 +145,10 @@ void launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_
                               const uint32_t *last_cell, const GridParams &g, uint32_t *coords, uint32_t *masks,
                               const uint32_t *mask_off, uint32_t mask_words, uint32_t *max_pts,
                               hipStream_t s);
-void launch_gather_soa(const double *pts, const uint32_t *perm, uint64_t n, uint32_t d,
-                       double *X, hipStream_t s);
+// Cell-ordered copy X[j][r] = pts[perm[r]][j] and the dimension-0 cell
+// coordinate of every cell-ordered point, cx[r] (the cell-key formula).
+void launch_gather_soa(const double *pts, const uint32_t *perm, uint64_t n, uint32_t d, double *X,
+                       const GridParams &g, uint32_t *cx, hipStream_t s);
 void launch_make_f32(const double *X, uint64_t n, uint32_t d, const double *shift, float *Y,
                      hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
@@ -232,13 +239,13 @@ struct TileArgs {
     uint32_t rows_per_chunk;  // 3^(d-1)
     const uint2 *segs;        // [chunk * rows_per_chunk + row] candidate point segment
 };
-// Builds cx and the chunk list without a host sync: a grid row holds p points
+// Builds the chunk list without a host sync: a grid row holds p points
 // in ceil(p / 64) <= p / 64 + 1 chunks, so there are at most
 // floor(n / 64) + rows chunks, rows <= min(ncells, rows_bound). Returns that
 // bound; the exact count goes to *nchunks_dev.
-uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, const uint32_t *cell_of,
-                      uint32_t ncells, uint32_t n, uint32_t d, uint64_t rows_bound, uint32_t *cx,
-                      uint2 **chunks_out, size_t *chunks_cap, uint32_t *nchunks_dev, hipStream_t s);
+uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, uint32_t ncells, uint32_t n, uint32_t d,
+                      uint64_t rows_bound, uint2 **chunks_out, size_t *chunks_cap, uint32_t *nchunks_dev,
+                      hipStream_t s);
 void build_chunk_segments(const TileArgs &t, const uint32_t *cell_of, const uint32_t *starts,
                           uint32_t d, uint2 *segs, hipStream_t s);
 void launch_join_tiled(const JoinArgs &a, const TileArgs &t, uint32_t d, int unicomp, int mode,
