@@ -17,9 +17,12 @@
 //   <= 16384  one workgroup per row, bitonic network in 64 KiB of LDS
 //   larger    one workgroup per row, bitonic network in global memory, using
 //             the row's own output segment (twice the row's size) as scratch
-// Each longer-row kernel scans the row offsets for the rows of its own size
-// class (64 rows per wave and ballot), so no kernel appends rows to a shared
-// queue: a queue counter is one address that every producer hits.
+// No kernel appends rows to a shared queue (a queue counter is one address
+// that every producer hits). The 33..64 class is found by scanning the row
+// offsets (64 rows per wave and ballot). Rows longer than 64 are listed in
+// row order by a stream compaction (a scan of the long-row flags) and the
+// wave and workgroup kernels walk that list, so the long rows of a dense
+// cluster -- adjacent in cell order -- spread over all waves.
 //
 // Row r's neighbour ids are read from out_j[in_off[r] - in_base, +len) and
 // its pairs are written at pairs[out_off[id] - out_base, +len) with
@@ -182,18 +185,27 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_group16(RowMap m, const ui
     }
 }
 
+// list[pos[r]] = r for every row longer than 64 entries
+__global__ __launch_bounds__(kThreads) void k_compact_long(const uint64_t *__restrict__ off, uint64_t rows,
+                                                           const uint32_t *__restrict__ pos,
+                                                           uint32_t *__restrict__ list) {
+    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (r < rows && off[r + 1] - off[r] > 64) list[pos[r]] = static_cast<uint32_t>(r);
+}
+
 __global__ __launch_bounds__(kThreads) void k_rowsort_wave(RowMap m,
                                                             const uint32_t *__restrict__ out_j,
-                                                            uint2 *__restrict__ pairs) {
+                                                            uint2 *__restrict__ pairs,
+                                                            const uint32_t *__restrict__ list,
+                                                            const uint32_t *__restrict__ count) {
     __shared__ uint32_t slot[kWaves][kWaveCap];
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
     volatile uint32_t *sh = slot[wave];
-    const uint64_t waves = static_cast<uint64_t>(gridDim.x) * kWaves;
-    for (uint64_t base = (blockIdx.x * static_cast<uint64_t>(kWaves) + wave) * 64; base < m.rows;
-         base += waves * 64)
-    for (uint64_t mask = class_mask(m, base, 64, kWaveCap); mask; mask &= mask - 1) {
-        const RowRef x = row_ref(m, base + static_cast<uint64_t>(__builtin_ctzll(mask)));
+    const uint32_t nlong = *count;
+    for (uint32_t w = blockIdx.x * kWaves + wave; w < nlong; w += gridDim.x * kWaves) {
+        const RowRef x = row_ref(m, list[w]);
+        if (x.len > kWaveCap) continue;  // the workgroup kernel's
         const uint32_t len = x.len;
         const uint32_t N = next_pow2(len);
         for (uint32_t e = lane; e < N; e += 64) sh[e] = e < len ? out_j[x.in + e] : kPad;
@@ -220,22 +232,14 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_wave(RowMap m,
 
 __global__ __launch_bounds__(kThreads) void k_rowsort_big(RowMap m,
                                                            uint32_t *__restrict__ out_j,
-                                                           uint2 *__restrict__ pairs) {
+                                                           uint2 *__restrict__ pairs,
+                                                           const uint32_t *__restrict__ list,
+                                                           const uint32_t *__restrict__ count) {
     __shared__ uint32_t sh[kBlockCap];
-    __shared__ uint32_t sel[kThreads];
-    __shared__ uint32_t nsel;
-    for (uint64_t base = blockIdx.x * static_cast<uint64_t>(kThreads); base < m.rows;
-         base += static_cast<uint64_t>(gridDim.x) * kThreads) {
-    if (threadIdx.x == 0) nsel = 0;
-    __syncthreads();
-    {
-        const uint64_t r = base + threadIdx.x;
-        if (r < m.rows && m.in_off[r + 1] - m.in_off[r] > kWaveCap) sel[atomicAdd(&nsel, 1u)] = threadIdx.x;
-    }
-    __syncthreads();
-    const uint32_t count = nsel;
-    for (uint32_t b = 0; b < count; ++b) {
-        const RowRef x = row_ref(m, base + sel[b]);
+    const uint32_t nlong = *count;
+    for (uint32_t b = blockIdx.x; b < nlong; b += gridDim.x) {
+        const RowRef x = row_ref(m, list[b]);
+        if (x.len <= kWaveCap) continue;  // the wave kernel's
         const uint64_t s = x.in, so = x.out;
         const uint32_t len = x.len;
         const uint32_t N = next_pow2(len);
@@ -290,8 +294,6 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_big(RowMap m,
         for (uint32_t e = threadIdx.x; e < len; e += kThreads) pairs[so + e] = make_uint2(r32, out_j[s + e]);
         __syncthreads();
     }
-    __syncthreads();  // sel and nsel are rewritten for the next 256 rows
-    }
 }
 
 template <int N>
@@ -312,15 +314,24 @@ void rowsort_long(const RowMap &m, uint32_t *out_j, uint2 *p2, uint32_t max_len,
         k_rowsort_group16<<<grid, kThreads, 0, s>>>(m, out_j, p2, sorted);
         SJ_LAUNCH_CHECK();
     }
-    if (max_len > 64) {
+    if (max_len <= 64) return;
+    // rows longer than 64, in row order
+    DevBuf<uint32_t> pos(m.rows + 1), list(m.rows);
+    scan_long_rows_exclusive(m.in_off, 64, pos.ptr, m.rows, s);
+    k_compact_long<<<static_cast<unsigned>((m.rows + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+        m.in_off, m.rows, pos.ptr, list.ptr);
+    SJ_LAUNCH_CHECK();
+    const uint32_t *count = pos.ptr + m.rows;
+    {
         KTimer kt_("rowsort_wave", s);
-        k_rowsort_wave<<<grid, kThreads, 0, s>>>(m, out_j, p2);
+        const unsigned gw = static_cast<unsigned>(std::min<uint64_t>((m.rows + kWaves - 1) / kWaves, 8192));
+        k_rowsort_wave<<<gw, kThreads, 0, s>>>(m, out_j, p2, list.ptr, count);
         SJ_LAUNCH_CHECK();
     }
     if (max_len > kWaveCap) {
         KTimer kt_("rowsort_big", s);
-        const unsigned gb = static_cast<unsigned>(std::min<uint64_t>((m.rows + kThreads - 1) / kThreads, 2048));
-        k_rowsort_big<<<gb, kThreads, 0, s>>>(m, out_j, p2);
+        const unsigned gb = static_cast<unsigned>(std::min<uint64_t>(m.rows, 1024));
+        k_rowsort_big<<<gb, kThreads, 0, s>>>(m, out_j, p2, list.ptr, count);
         SJ_LAUNCH_CHECK();
     }
 }

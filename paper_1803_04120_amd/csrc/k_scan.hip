@@ -55,6 +55,25 @@ struct RowHeadLoad {
     }
 };
 
+// Chunks of grid row r (ceil(points / 64)); rows past the row count (the
+// total of the row-head scan, row_of[ncells]) have none.
+struct RowChunksLoad {
+    const uint32_t *row_pt;
+    const uint64_t *row_of;
+    size_t ncells;
+    __device__ __forceinline__ uint32_t operator()(size_t r) const {
+        if (r >= row_of[ncells]) return 0u;
+        return (row_pt[r + 1] - row_pt[r] + 63u) / 64u;
+    }
+};
+
+// 1 for a row longer than lo entries (row lengths from offsets).
+struct LongRowLoad {
+    const uint64_t *off;
+    uint32_t lo;
+    __device__ __forceinline__ uint32_t operator()(size_t r) const { return off[r + 1] - off[r] > lo ? 1u : 0u; }
+};
+
 template <typename Tacc, typename Load>
 __global__ __launch_bounds__(kThreads) void k_tile_sum(ScanOps<Tacc, Load> ops, size_t n,
                                                         Tacc *__restrict__ part_all) {
@@ -220,6 +239,15 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, hipStream_t
 void scan_row_heads_exclusive(const uint32_t *coords, uint32_t d, uint64_t *row_of, size_t ncells,
                               hipStream_t s) {
     scan_one<uint64_t, false>(RowHeadLoad{coords, d}, row_of, ncells, row_of + ncells, s);
+}
+
+void scan_row_chunks_exclusive(const uint32_t *row_pt, const uint64_t *row_of, uint64_t *ch_off, size_t ncells,
+                               hipStream_t s) {
+    scan_one<uint64_t, false>(RowChunksLoad{row_pt, row_of, ncells}, ch_off, ncells, ch_off + ncells, s);
+}
+
+void scan_long_rows_exclusive(const uint64_t *off, uint32_t lo, uint32_t *pos, size_t rows, hipStream_t s) {
+    scan_one<uint32_t, false>(LongRowLoad{off, lo}, pos, rows, pos + rows, s);
 }
 
 template <typename K>

@@ -518,16 +518,6 @@ __global__ __launch_bounds__(kThreads) void k_row_points(const uint64_t *__restr
     if (h == 0) row_pt[row_of[ncells]] = n;
 }
 
-// Chunks per row (rows past the device-side row count get none).
-__global__ __launch_bounds__(kThreads) void k_row_nchunks(const uint32_t *__restrict__ row_pt,
-                                                           const uint64_t *__restrict__ row_of,
-                                                           uint32_t ncells, uint32_t *__restrict__ nch) {
-    const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
-    if (r >= ncells) return;
-    const uint64_t nrows = row_of[ncells];
-    nch[r] = r < nrows ? (row_pt[r + 1] - row_pt[r] + 63) / 64 : 0u;
-}
-
 __global__ __launch_bounds__(kThreads) void k_emit_chunks(const uint32_t *__restrict__ row_pt,
                                                            const uint64_t *__restrict__ row_of,
                                                            const uint64_t *__restrict__ ch_off,
@@ -603,14 +593,12 @@ uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, uint32_t n
     const uint64_t bound = static_cast<uint64_t>(n) / 64 + std::min<uint64_t>(ncells, rows_bound);
     if (bound >= 0xffffffffULL) throw Error(SJ_ECAPACITY, "too many join chunks");
     // rows are bounded by the cells, so every array below is sized by ncells
-    DevBuf<uint32_t> row_pt(static_cast<size_t>(ncells) + 1), nch(ncells);
+    DevBuf<uint32_t> row_pt(static_cast<size_t>(ncells) + 1);
     DevBuf<uint64_t> row_of(static_cast<size_t>(ncells) + 1), choff(static_cast<size_t>(ncells) + 1);
     scan_row_heads_exclusive(coords, d, row_of.ptr, ncells, s);
     k_row_points<<<nblk(ncells), kThreads, 0, s>>>(row_of.ptr, starts, ncells, n, row_pt.ptr);
     SJ_LAUNCH_CHECK();
-    k_row_nchunks<<<nblk(ncells), kThreads, 0, s>>>(row_pt.ptr, row_of.ptr, ncells, nch.ptr);
-    SJ_LAUNCH_CHECK();
-    scan_exclusive_u32_to_u64(nch.ptr, choff.ptr, ncells, s);
+    scan_row_chunks_exclusive(row_pt.ptr, row_of.ptr, choff.ptr, ncells, s);
     if (bound > *chunks_cap) {
         if (*chunks_out) dev_free(*chunks_out);
         *chunks_out = static_cast<uint2 *>(dev_alloc(bound * sizeof(uint2)));

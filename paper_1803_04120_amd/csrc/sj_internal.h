@@ -107,6 +107,13 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, hipStream_t
 // row_of[ncells] = number of rows.
 void scan_row_heads_exclusive(const uint32_t *coords, uint32_t d, uint64_t *row_of, size_t ncells,
                               hipStream_t s);
+// ch_off[r] = chunks of the grid rows before r (ceil(points / 64) each, from
+// the rows' first points row_pt), ch_off[ncells] = all chunks.
+void scan_row_chunks_exclusive(const uint32_t *row_pt, const uint64_t *row_of, uint64_t *ch_off, size_t ncells,
+                               hipStream_t s);
+// pos[r] = rows before r longer than lo entries (lengths off[r+1] - off[r]),
+// pos[rows] = their number.
+void scan_long_rows_exclusive(const uint64_t *off, uint32_t lo, uint32_t *pos, size_t rows, hipStream_t s);
 // Inclusive scan of the head flags (key[r] != key[r-1], 1 at r = 0) of a
 // sorted key array: out[r] = 1 + number of distinct keys before r.
 template <typename K>
