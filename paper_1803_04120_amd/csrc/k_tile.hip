@@ -104,7 +104,10 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     uint32_t *srow = sr_all[wave] + lane * (NS > 0 ? kRowStride : 0);
 
     uint32_t own = 0, evals = 0, rechecks = 0;
-    const uint32_t chunk = xcd_block_index() * kWaves + wave;
+    // chunks go to workgroups in launch order, which the hardware deals out
+    // to the XCDs round robin: a dense cluster's many heavy chunks, adjacent
+    // in cell order, spread over all XCDs
+    const uint32_t chunk = blockIdx.x * kWaves + wave;
     if (chunk < *t.nchunks_dev) {  // uniform across the wave
         // segment table of the chunk, 64 rows per register load; the first
         // load is issued before anything else (it needs only the chunk index)
@@ -355,7 +358,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         };
         // (the unicomp count adds mirrored hits to global counters after each
         // tile; a prefetch would then wait for those atomics as well)
-        constexpr bool kPrefetch = !kAgg;
+        constexpr bool kPrefetch = false;
         Tile cur = advance(Tile{0, 0, 0, false, false});
         if (kPrefetch && cur.valid) load_tile(cur);
         // fused fill: the row's place in the result (needs perm_p; used at
@@ -364,16 +367,28 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         while (cur.valid) {
             const uint32_t len = (cur.P1 - cur.T0) < static_cast<uint32_t>(TS) ? (cur.P1 - cur.T0) : TS;
             wave_sync_lds();
-            if (!kPrefetch) load_tile(cur);
+            if (kPrefetch) {
 #pragma unroll
-            for (int m = 0; m < kPer; ++m) {
-                const uint32_t i = static_cast<uint32_t>(lane + 64 * m);
-                if (i < len) {
+                for (int m = 0; m < kPer; ++m) {
+                    const uint32_t i = static_cast<uint32_t>(lane + 64 * m);
+                    if (i < len) {
 #pragma unroll
-                    for (int j = 0; j < D; ++j) sx[i * D + j] = rx[m][j];
-                    scx[i] = rc[m];
+                        for (int j = 0; j < D; ++j) sx[i * D + j] = rx[m][j];
+                        scx[i] = rc[m];
+                        if (kPerm) saux[i] = ra[m];
+                    }
+                }
+            } else {
+                // staged straight from memory (no registers held across the tile)
+                for (uint32_t i = lane; i < len; i += 64) {
+                    const size_t q = cur.T0 + i;
+#pragma unroll
+                    for (int j = 0; j < D; ++j)
+                        sx[i * D + j] = kBand ? static_cast<CT>(a.Y[static_cast<size_t>(j) * a.n + q])
+                                              : static_cast<CT>(a.X[static_cast<size_t>(j) * a.n + q]);
+                    scx[i] = t.cx[q];
                     if (kAgg) saux[i] = 0;
-                    if (kPerm) saux[i] = ra[m];
+                    if (kPerm) saux[i] = a.perm[q];
                 }
             }
             const Tile nxt = advance(cur);

@@ -366,11 +366,17 @@ sj::TileArgs tile_args(sj_index &ix) {
     return t;
 }
 
-// Row sort fused into the full fill (default) or run as its own kernels
-// (SJ_FUSED_SORT=0).
-bool use_fused_sort() {
+// Row sort fused into the full fill, or run as its own kernels after it.
+// Fused in 1..3-D: the rows stay in LDS and are written once, sorted. From
+// 4-D on the fill evaluates 27..2187 candidate rows per chunk and needs every
+// wave it can hold; the LDS row slots would cut that to 3..4 waves per SIMD
+// (measured on a mixed 2..6-D request stream: 137 ms fused vs 74 ms + 6 ms of
+// row sorts unfused). SJ_FUSED_SORT=0|1 overrides.
+bool use_fused_sort(uint32_t d) {
     const char *e = std::getenv("SJ_FUSED_SORT");
-    return !(e && std::strcmp(e, "0") == 0);
+    if (e && std::strcmp(e, "0") == 0) return false;
+    if (e && std::strcmp(e, "1") == 0) return true;
+    return d <= 3;
 }
 
 // Entries per lane in the fused fill's LDS row slot (SJ_FUSED_NS=16|24|32
@@ -557,7 +563,7 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
     }
     // whole result, full fill: each point's row is complete when its own
     // evaluation ends, so the row sort runs inside the fill kernel
-    const bool fused = tiled && !unicomp_fill && whole && use_fused_sort();
+    const bool fused = tiled && !unicomp_fill && whole && use_fused_sort(ix.d);
     if (tiled) {
         uint32_t ns = 0;
         if (fused) {

@@ -66,19 +66,6 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *total, T *lds) {
     return before + incl - v;
 }
 
-// Workgroups are handed to the 8 XCDs (each with its own L2) round robin
-// in launch order. This maps the launch index to a logical index such that
-// every XCD works through one contiguous range of logical indices, so
-// neighbouring work units (which read overlapping data) share an L2.
-// A bijection on [0, gridDim.x).
-constexpr uint32_t kNumXcd = 8;
-__device__ __forceinline__ uint32_t xcd_block_index() {
-    const uint32_t nb = gridDim.x, b = blockIdx.x;
-    const uint32_t q = nb / kNumXcd, r = nb % kNumXcd;
-    const uint32_t xcd = b % kNumXcd, idx = b / kNumXcd;
-    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
-}
-
 // Sorts 64 values, one per lane, ascending in lane order (bitonic network
 // over lane-index exchanges). Every lane of the wave must take part.
 __device__ __forceinline__ uint32_t wave_bitonic_sort64(uint32_t v) {

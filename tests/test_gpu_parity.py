@@ -112,6 +112,19 @@ def test_fused_fill_slot_sizes(sj, monkeypatch, slot, kind, d, n, eps):
     assert_same(gpu_pairs(sj, pts, eps, unicomp=False), want, f"slot {slot} {kind}-{d}d")
 
 
+@pytest.mark.parametrize("fused", ["0", "1"])
+@pytest.mark.parametrize("kind,d,n,eps", [("uniform", 4, 12007, 14.0), ("clustered", 5, 9001, 3.0),
+                                          ("uniform", 2, 20011, 1.5)])
+def test_fused_and_unfused_fill(sj, monkeypatch, fused, kind, d, n, eps):
+    """The row sort fused into the fill (default up to 3-D) and run after it
+    (default from 4-D) give the same pairs, forced either way."""
+    monkeypatch.setenv("SJ_FUSED_SORT", fused)
+    _say(f"fused={fused} {kind} d={d} n={n} eps={eps}")
+    pts = datagen.make(kind, n, d, seed=4000 + d)
+    want = ref.pairs(pts, eps)
+    assert_same(gpu_pairs(sj, pts, eps, unicomp=False), want, f"fused={fused} {kind}-{d}d")
+
+
 # ---------------------------------------------------------------- edges
 def test_empty_and_single(sj):
     _say("empty and single point")
