@@ -334,65 +334,27 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             tl.valid = false;
             return tl;
         };
-        // candidates held in registers between their load and their LDS
-        // store, so the next tile's loads are in flight while this one is
-        // evaluated
-        constexpr int kPer = TS / 64;
-        CT rx[kPer][D];
-        uint32_t rc[kPer], ra[kPer];
-        auto load_tile = [&](const Tile &tl) {
-            const uint32_t len = (tl.P1 - tl.T0) < static_cast<uint32_t>(TS) ? (tl.P1 - tl.T0) : TS;
-#pragma unroll
-            for (int m = 0; m < kPer; ++m) {
-                const uint32_t i = static_cast<uint32_t>(lane + 64 * m);
-                if (i < len) {
-                    const size_t q = tl.T0 + i;
-#pragma unroll
-                    for (int j = 0; j < D; ++j)
-                        rx[m][j] = kBand ? static_cast<CT>(a.Y[static_cast<size_t>(j) * a.n + q])
-                                         : static_cast<CT>(a.X[static_cast<size_t>(j) * a.n + q]);
-                    rc[m] = t.cx[q];
-                    if (kPerm) ra[m] = a.perm[q];
-                }
-            }
-        };
-        // (the unicomp count adds mirrored hits to global counters after each
-        // tile; a prefetch would then wait for those atomics as well)
-        constexpr bool kPrefetch = false;
         Tile cur = advance(Tile{0, 0, 0, false, false});
-        if (kPrefetch && cur.valid) load_tile(cur);
         // fused fill: the row's place in the result (needs perm_p; used at
-        // the end, loaded after the first tile's loads are in flight)
+        // the end)
         if (NS > 0 && active) row_dst = a.off_orig[perm_p];
         while (cur.valid) {
             const uint32_t len = (cur.P1 - cur.T0) < static_cast<uint32_t>(TS) ? (cur.P1 - cur.T0) : TS;
             wave_sync_lds();
-            if (kPrefetch) {
+            // stage the tile straight from memory (holding a prefetched next
+            // tile in registers was measured slower: it costs waves per SIMD,
+            // and the unicomp count would wait on its own atomics for it)
+            for (uint32_t i = lane; i < len; i += 64) {
+                const size_t q = cur.T0 + i;
 #pragma unroll
-                for (int m = 0; m < kPer; ++m) {
-                    const uint32_t i = static_cast<uint32_t>(lane + 64 * m);
-                    if (i < len) {
-#pragma unroll
-                        for (int j = 0; j < D; ++j) sx[i * D + j] = rx[m][j];
-                        scx[i] = rc[m];
-                        if (kPerm) saux[i] = ra[m];
-                    }
-                }
-            } else {
-                // staged straight from memory (no registers held across the tile)
-                for (uint32_t i = lane; i < len; i += 64) {
-                    const size_t q = cur.T0 + i;
-#pragma unroll
-                    for (int j = 0; j < D; ++j)
-                        sx[i * D + j] = kBand ? static_cast<CT>(a.Y[static_cast<size_t>(j) * a.n + q])
-                                              : static_cast<CT>(a.X[static_cast<size_t>(j) * a.n + q]);
-                    scx[i] = t.cx[q];
-                    if (kAgg) saux[i] = 0;
-                    if (kPerm) saux[i] = a.perm[q];
-                }
+                for (int j = 0; j < D; ++j)
+                    sx[i * D + j] = kBand ? static_cast<CT>(a.Y[static_cast<size_t>(j) * a.n + q])
+                                          : static_cast<CT>(a.X[static_cast<size_t>(j) * a.n + q]);
+                scx[i] = t.cx[q];
+                if (kAgg) saux[i] = 0;
+                if (kPerm) saux[i] = a.perm[q];
             }
             const Tile nxt = advance(cur);
-            if (kPrefetch && nxt.valid) load_tile(nxt);
             wave_sync_lds();
             if (active) evaluate_tile(cur.T0, len, cur.own_row);
             if (kAgg) {
