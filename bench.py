@@ -12,7 +12,19 @@ in {0.04, 0.08, 0.12, 0.16, 0.2} -- the shape of the paper's 2-D synthetic
 sets (Section VI-A). Prints ONE JSON line on stdout; everything else goes to
 stderr.
 
+Beside `value` (pairs/s of the timed steps) the line carries:
+  roofline           the refine kernel with the largest time: algorithmic
+                     bytes per launch over its event-timed average duration,
+                     against 8 TB/s, and the counted HBM traffic from the
+                     summary under profiles/ while its sources are unchanged;
+  cpu_baseline       the brute-force oracle on a sample of query rows;
+  cpu_grid_baseline  the host-core grid join on the whole workload;
+  fp32_band          the same sweep with the FP32 pre-test and FP64 band;
+  batched            delivery in 2^24-pair batches;
+  serving            a Poisson request stream through the server (p50/p99).
+
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+                  [--no-serve] [--no-band] [--no-batched]
 """
 from __future__ import annotations
 
