@@ -145,37 +145,7 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_group16(RowMap m, const ui
         const uint32_t e = static_cast<uint32_t>(k) * 16 + l;
         v[k] = (mine && e < x.len) ? out_j[x.in + e] : kPad;
     }
-#pragma unroll
-    for (int kk = 2; kk <= 64; kk <<= 1) {
-#pragma unroll
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            if (j >= 16) {
-                const int jr = j >> 4;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int kp = k ^ jr;
-                    if (kp > k) {
-                        const uint32_t e = static_cast<uint32_t>(k) * 16 + l;
-                        const bool asc = (e & static_cast<uint32_t>(kk)) == 0;
-                        const uint32_t a = v[k], b = v[kp];
-                        const uint32_t mn = a < b ? a : b, mx = a < b ? b : a;
-                        v[k] = asc ? mn : mx;
-                        v[kp] = asc ? mx : mn;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint32_t p = __shfl_xor(v[k], j, 16);
-                    const uint32_t e = static_cast<uint32_t>(k) * 16 + l;
-                    const bool asc = (e & static_cast<uint32_t>(kk)) == 0;
-                    const bool lower = (l & static_cast<uint32_t>(j)) == 0;
-                    const uint32_t mn = v[k] < p ? v[k] : p, mx = v[k] < p ? p : v[k];
-                    v[k] = (lower == asc) ? mn : mx;
-                }
-            }
-        }
-    }
+    group16_bitonic64(v);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const uint32_t e = static_cast<uint32_t>(k) * 16 + l;

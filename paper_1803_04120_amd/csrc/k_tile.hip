@@ -408,32 +408,45 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 }
             }
             // rows longer than the slot but at most 64 long: in out_j (written
-            // above by this wave); the wave sorts them, one entry per lane,
-            // four rows at a time so their loads and networks overlap
+            // above by this wave); sorted four at a time, one row per 16-lane
+            // group with 4 entries per lane
             uint64_t longm = ballot(active && !row_in_lds && row_len <= 64u);
             if (longm) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // own stores before own loads
+            const uint32_t grp = static_cast<uint32_t>(lane) >> 4, gl = static_cast<uint32_t>(lane) & 15u;
             while (longm) {
-                constexpr int kG = 4;
-                uint32_t v[kG], rl[kG], rid[kG];
-                uint64_t dst[kG];
+                // the group's row: the grp-th lowest remaining long row
+                uint64_t take = longm;
+                int pick = -1;
 #pragma unroll
-                for (int g = 0; g < kG; ++g) {
-                    const int l = longm ? __builtin_ctzll(longm) : 0;
-                    const bool has = longm != 0;
-                    longm &= longm - 1;
-                    rl[g] = has ? static_cast<uint32_t>(__shfl(static_cast<int>(row_len), l, 64)) : 0u;
-                    rid[g] = static_cast<uint32_t>(__shfl(static_cast<int>(perm_p), l, 64));
-                    const uint64_t src = __shfl(my_row, l, 64);
-                    dst[g] = __shfl(row_dst, l, 64);
-                    v[g] = static_cast<uint32_t>(lane) < rl[g] ? a.out_j[src + lane] : 0xffffffffu;
+                for (uint32_t g = 0; g < 4; ++g) {
+                    if (take) {
+                        const int b0 = __builtin_ctzll(take);
+                        if (g == grp) pick = b0;
+                        take &= take - 1;
+                    }
                 }
+                longm = take;
+                // every lane takes part in every shuffle (a lane that skipped
+                // one would leave its own value unreadable to the others)
+                const int src_lane = pick >= 0 ? pick : 0;
+                const uint32_t rl_any = static_cast<uint32_t>(__shfl(static_cast<int>(row_len), src_lane, 64));
+                const uint32_t rid = static_cast<uint32_t>(__shfl(static_cast<int>(perm_p), src_lane, 64));
+                const uint64_t src = __shfl(my_row, src_lane, 64), dst = __shfl(row_dst, src_lane, 64);
+                const uint32_t rl = pick >= 0 ? rl_any : 0u;
+                uint32_t v[4];
 #pragma unroll
-                for (int g = 0; g < kG; ++g) v[g] = wave_bitonic_sort64(v[g]);
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t e = static_cast<uint32_t>(k) * 16 + gl;
+                    v[k] = e < rl ? a.out_j[src + e] : 0xffffffffu;
+                }
+                group16_bitonic64(v);
 #pragma unroll
-                for (int g = 0; g < kG; ++g)
-                    if (static_cast<uint32_t>(lane) < rl[g])
-                        __builtin_nontemporal_store(static_cast<uint64_t>(rid[g]) | (static_cast<uint64_t>(v[g]) << 32),
-                                                    reinterpret_cast<unsigned long long *>(a.pairs + dst[g] + lane));
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t e = static_cast<uint32_t>(k) * 16 + gl;
+                    if (e < rl)
+                        __builtin_nontemporal_store(static_cast<uint64_t>(rid) | (static_cast<uint64_t>(v[k]) << 32),
+                                                    reinterpret_cast<unsigned long long *>(a.pairs + dst + e));
+                }
             }
         }
     }

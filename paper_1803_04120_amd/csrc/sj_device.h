@@ -66,22 +66,44 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *total, T *lds) {
     return before + incl - v;
 }
 
-// Sorts 64 values, one per lane, ascending in lane order (bitonic network
-// over lane-index exchanges). Every lane of the wave must take part.
-__device__ __forceinline__ uint32_t wave_bitonic_sort64(uint32_t v) {
-    const uint32_t lane = static_cast<uint32_t>(lane_id());
+// Sorts one 64-entry row per 16-lane group (4 rows per wave): lane l of a
+// group holds entries e = 16 k + l in v[k], k = 0..3. Bitonic network: stages
+// with a partner distance of 16 or more exchange registers within the lane,
+// shorter ones exchange with lane l ^ j of the same group. Every lane of the
+// wave must take part.
+__device__ __forceinline__ void group16_bitonic64(uint32_t (&v)[4]) {
+    const uint32_t l = static_cast<uint32_t>(lane_id()) & 15u;
 #pragma unroll
-    for (uint32_t k = 2; k <= 64; k <<= 1) {
+    for (int kk = 2; kk <= 64; kk <<= 1) {
 #pragma unroll
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            const uint32_t o = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), static_cast<int>(j), 64));
-            const bool asc = (lane & k) == 0;      // direction of this lane's block
-            const bool lower = (lane & j) == 0;    // lower element of the pair
-            const uint32_t mn = v < o ? v : o, mx = v < o ? o : v;
-            v = (lower == asc) ? mn : mx;
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j >= 16) {
+                const int jr = j >> 4;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int kp = k ^ jr;
+                    if (kp > k) {
+                        const uint32_t e = static_cast<uint32_t>(k) * 16 + l;
+                        const bool asc = (e & static_cast<uint32_t>(kk)) == 0;
+                        const uint32_t a = v[k], b = v[kp];
+                        const uint32_t mn = a < b ? a : b, mx = a < b ? b : a;
+                        v[k] = asc ? mn : mx;
+                        v[kp] = asc ? mx : mn;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t p = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v[k]), j, 16));
+                    const uint32_t e = static_cast<uint32_t>(k) * 16 + l;
+                    const bool asc = (e & static_cast<uint32_t>(kk)) == 0;
+                    const bool lower = (l & static_cast<uint32_t>(j)) == 0;
+                    const uint32_t mn = v[k] < p ? v[k] : p, mx = v[k] < p ? p : v[k];
+                    v[k] = (lower == asc) ? mn : mx;
+                }
+            }
         }
     }
-    return v;
 }
 
 // Sorts N values held in registers ascending with a fully unrolled bitonic

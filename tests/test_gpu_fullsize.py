@@ -84,6 +84,23 @@ def test_uniform_2d_2M_eps_sweep(sj):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("eps", [0.04, 0.2])
+def test_uniform_2d_2M_whole_result_vs_cpu_grid_join(sj, eps):
+    """Whole result, not a sample: the 2M-point 2-D join against the host-core
+    grid join (itself checked against the brute force), pair for pair."""
+    pts = datagen.uniform(2_000_000, 2, seed=2)
+    x = torch.from_numpy(pts).cuda()
+    _say(f"uniform 2d n=2M eps={eps} whole result vs CPU grid join")
+    out, off, _ = _join(sj, x, eps, unicomp=True)
+    got = out.cpu().numpy()
+    del out, x
+    counts, want = ref.grid_join(pts, eps)
+    assert got.shape == want.shape
+    np.testing.assert_array_equal(np.diff(off), counts)
+    assert np.array_equal(got, want)
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("key", ["d3_k32", "d3_k256", "d4_k32", "d4_k256",
                                  "d5_k32", "d5_k256", "d6_k32", "d6_k256"])
 def test_uniform_10M(sj, key):
