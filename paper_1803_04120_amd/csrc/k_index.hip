@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kThreads) void k_cell_coords(const uint64_t *__rest
                                                            GridParams g,
                                                            uint32_t *__restrict__ coords,
                                                            uint32_t *__restrict__ masks,
-                                                           const uint32_t *__restrict__ mask_off,
+                                                           MaskOffsets mask_off,
                                                            uint32_t mask_words,
                                                            uint32_t *__restrict__ max_pts) {
     __shared__ uint32_t lmask[kMaskLdsWords];
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_cell_coords(const uint64_t *__rest
             }
             coords[h * g.d + j] = c;
             if (!masks) continue;
-            const uint32_t w = mask_off[j] + (c >> 5);
+            const uint32_t w = mask_off.off[j] + (c >> 5);
             const uint32_t bit = 1u << (c & 31u);
             // most bits are set by the first cells that have them: test first
             if (use_lds) {
@@ -381,7 +381,7 @@ template void build_cells<uint32_t>(const uint32_t *, uint64_t, uint32_t *, uint
 
 void launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_t ncells_bound,
                               const uint32_t *last_cell, const GridParams &g, uint32_t *coords, uint32_t *masks,
-                              const uint32_t *mask_off, uint32_t mask_words, uint32_t *max_pts,
+                              const MaskOffsets &mask_off, uint32_t mask_words, uint32_t *max_pts,
                               hipStream_t s) {
     const uint64_t mw = masks ? mask_words : 0;
     k_zero2_u32<<<static_cast<unsigned>(std::min<uint64_t>(64, mw / 256 + 1)), 256, 0, s>>>(masks, mw, max_pts, 1);

@@ -417,9 +417,10 @@ uint64_t build_ranges(const SearchArgs &a, int unicomp, uint64_t *roff, uint32_t
         SJ_LAUNCH_CHECK();
     }
     scan_exclusive_u32_to_u64(cnt.ptr, roff, a.ncells, s);
-    uint64_t total = 0;
-    SJ_HIP(hipMemcpyAsync(&total, roff + a.ncells, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HostStage hs;
+    SJ_HIP(hipMemcpyAsync(hs.p, roff + a.ncells, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
+    const uint64_t total = *hs.as<uint64_t>();
     if (total > *rng_cap) {
         if (*rng_out) dev_free(*rng_out);
         const size_t cap = total + total / 8 + 64;

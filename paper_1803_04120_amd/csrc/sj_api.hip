@@ -245,15 +245,14 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
         dp = staged.ptr;
     }
     // bounding box (Section IV-B)
-    DevBuf<double> bb(2 * sj::kMaxDim);
-    DevBuf<uint32_t> bad(1);
-    sj::launch_bbox(dp, n, d, bb.ptr, bad.ptr, s);
-    double hb[2 * sj::kMaxDim];
-    uint32_t hbad = 0;
-    SJ_HIP(hipMemcpyAsync(hb, bb.ptr, sizeof(hb), hipMemcpyDeviceToHost, s));
-    SJ_HIP(hipMemcpyAsync(&hbad, bad.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    // [0, 2 kMaxDim): min and max; the word after them: the NaN/Inf flag
+    DevBuf<double> bb(2 * sj::kMaxDim + 1);
+    sj::launch_bbox(dp, n, d, bb.ptr, reinterpret_cast<uint32_t *>(bb.ptr + 2 * sj::kMaxDim), s);
+    sj::HostStage hs;
+    SJ_HIP(hipMemcpyAsync(hs.p, bb.ptr, bb.bytes(), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
-    if (hbad) throw Error(SJ_EINVAL, "coordinates contain NaN or Inf");
+    const double *hb = hs.as<double>();
+    if (*reinterpret_cast<const uint32_t *>(hb + 2 * sj::kMaxDim)) throw Error(SJ_EINVAL, "coordinates contain NaN or Inf");
     for (uint32_t j = 0; j < d; ++j) {
         ix.bmin[j] = hb[j];
         ix.bmax[j] = hb[sj::kMaxDim + j];
@@ -288,11 +287,11 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
         ix.mask_off[j] = static_cast<uint32_t>(words);
         words += (ix.grid.dims[j] + 31) / 32;
     }
-    DevBuf<uint32_t> moff(sj::kMaxDim);
+    sj::MaskOffsets moff{};
+    for (uint32_t j = 0; j < d; ++j) moff.off[j] = ix.mask_off[j];
     if (words <= (1ull << 26)) {
         ix.mask_words = static_cast<uint32_t>(words);
         ix.masks.reset(words);
-        SJ_HIP(hipMemcpyAsync(moff.ptr, ix.mask_off, sizeof(ix.mask_off), hipMemcpyHostToDevice, s));
     } else {
         ix.mask_words = 0;  // masks only prune; a grid this wide goes without
     }
@@ -301,7 +300,7 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
     ix.coords.reset(n * d);
     ix.max_cell_dev.ensure(1);
     sj::launch_cell_coords_masks(ix.B.ptr, ix.starts.ptr, n, ix.cell_of.ptr + (n - 1), ix.grid, ix.coords.ptr,
-                                 ix.masks.ptr, moff.ptr, ix.mask_words, ix.max_cell_dev.ptr, s);
+                                 ix.masks.ptr, moff, ix.mask_words, ix.max_cell_dev.ptr, s);
     // cell-ordered structure of arrays
     ix.X.reset(n * d);
     ix.cx.reset(n);
@@ -311,10 +310,9 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
         ix.extent = std::max(ix.extent, std::max(std::fabs(ix.bmax[j] - ix.shift[j]),
                                                  std::fabs(ix.bmin[j] - ix.shift[j])));
     }
-    uint32_t last_cell = 0;
-    SJ_HIP(hipMemcpyAsync(&last_cell, ix.cell_of.ptr + (n - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(hs.p, ix.cell_of.ptr + (n - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
-    ix.ncells = static_cast<uint64_t>(last_cell) + 1;
+    ix.ncells = static_cast<uint64_t>(*hs.as<uint32_t>()) + 1;
     ix.stats.ms_build = now_ms() - t0;
 }
 
@@ -497,9 +495,10 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     ix.summary.ensure(8);
     sj::launch_count_summary(ix.off_orig.ptr, n, ix.max_len.ptr, ix.counters.ptr,
                              tiled ? ix.nchunks_dev.ptr : nullptr, ix.summary.ptr, s);
-    uint64_t sm[8];
-    SJ_HIP(hipMemcpyAsync(sm, ix.summary.ptr, sizeof(sm), hipMemcpyDeviceToHost, s));
+    sj::HostStage hs;
+    SJ_HIP(hipMemcpyAsync(hs.p, ix.summary.ptr, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
+    const uint64_t *sm = hs.as<uint64_t>();
     ix.pairs = sm[0];
     ix.max_row = static_cast<uint32_t>(sm[1]);
     ix.stats.evals = sm[2];
@@ -514,10 +513,10 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
 }
 
 void check_overflow(sj_index &ix, hipStream_t s) {
-    uint32_t ov = 0;
-    SJ_HIP(hipMemcpyAsync(&ov, ix.overflow.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    sj::HostStage hs;
+    SJ_HIP(hipMemcpyAsync(hs.p, ix.overflow.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
-    if (ov) throw Error(SJ_EDEVICE, "internal: the fill pass disagreed with the count pass");
+    if (*hs.as<uint32_t>()) throw Error(SJ_EDEVICE, "internal: the fill pass disagreed with the count pass");
 }
 
 // Fill + row sort of result rows [i0, i1) into out_j / pairs (batch-relative).

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <exception>
 #include <stdexcept>
 #include <string>
 
@@ -31,6 +32,26 @@ void hip_check(hipError_t e, const char *what, const char *file, int line);
 // ---------------------------------------------------------------------
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
+
+// Page-locked host blocks of kStageBytes for small device-to-host readbacks
+// (a copy into pageable memory goes through the runtime's own staging and
+// returns later). Pooled for the life of the process.
+constexpr size_t kStageBytes = 4096;
+void *stage_acquire();
+void stage_release(void *p);
+// One staging block for the scope. If the scope ends by an exception, a copy
+// into the block may still be in flight: the block is then not reused.
+struct HostStage {
+    void *p;
+    HostStage() : p(stage_acquire()) {}
+    ~HostStage() {
+        if (std::uncaught_exceptions() == 0) stage_release(p);
+    }
+    HostStage(const HostStage &) = delete;
+    HostStage &operator=(const HostStage &) = delete;
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
 void pool_trim();
 void pool_enter();
 void pool_leave_after_sync();
@@ -144,13 +165,17 @@ void launch_cell_keys_u32(const double *pts, uint64_t n, const GridParams &g, ui
 template <typename K>
 void build_cells(const K *sorted_keys, uint64_t n, uint32_t *cell_of, uint64_t *B, uint32_t *starts,
                  hipStream_t s);
+// Word offset of each dimension's occupancy mask.
+struct MaskOffsets {
+    uint32_t off[kMaxDim];
+};
 // per-cell coordinates (cell-major, d per cell), occupancy masks, and the
 // largest cell (written to *max_pts on the device). The cell count is read
 // on the device (*last_cell + 1, the cell of the last sorted point);
 // ncells_bound (>= it) sizes the launch.
 void launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_t ncells_bound,
                               const uint32_t *last_cell, const GridParams &g, uint32_t *coords, uint32_t *masks,
-                              const uint32_t *mask_off, uint32_t mask_words, uint32_t *max_pts,
+                              const MaskOffsets &mask_off, uint32_t mask_words, uint32_t *max_pts,
                               hipStream_t s);
 // Cell-ordered copy X[j][r] = pts[perm[r]][j] and the dimension-0 cell
 // coordinate of every cell-ordered point, cx[r] (the cell-key formula).

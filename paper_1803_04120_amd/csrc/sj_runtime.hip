@@ -65,6 +65,39 @@ void release_now(void *p) {
 
 }  // namespace
 
+namespace {
+struct StagePool {
+    std::mutex mu;
+    std::vector<void *> free_blocks;
+};
+StagePool &stage_pool() {
+    static StagePool *p = new StagePool;  // never destroyed: may be used during process exit
+    return *p;
+}
+}  // namespace
+
+void *stage_acquire() {
+    StagePool &P = stage_pool();
+    {
+        std::lock_guard<std::mutex> lk(P.mu);
+        if (!P.free_blocks.empty()) {
+            void *p = P.free_blocks.back();
+            P.free_blocks.pop_back();
+            return p;
+        }
+    }
+    void *p = nullptr;
+    SJ_HIP(hipHostMalloc(&p, kStageBytes, hipHostMallocDefault));
+    return p;
+}
+
+void stage_release(void *p) {
+    if (!p) return;
+    StagePool &P = stage_pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.free_blocks.push_back(p);
+}
+
 void *dev_alloc(size_t bytes) {
     int dev = 0;
     SJ_HIP(hipGetDevice(&dev));
