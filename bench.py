@@ -106,9 +106,9 @@ def kernel_bytes(name, n, d, cells, ranges, pairs):
 # Sources compiled into each family of modelled kernels: a traffic figure
 # measured with hardware counters is only reported while these are unchanged.
 KERNEL_SOURCES = {
-    "tiled_": ["k_tile.hip", "sj_device.h", "sj_internal.h"],
-    "join_": ["k_join.hip", "sj_device.h", "sj_internal.h"],
-    "rowsort_": ["k_rowsort.hip", "sj_device.h", "sj_internal.h"],
+    "tiled_": ["k_tile.hip", "sj_device.h", "sj_args.h"],
+    "join_": ["k_join.hip", "sj_device.h", "sj_args.h"],
+    "rowsort_": ["k_rowsort.hip", "sj_device.h", "sj_args.h"],
 }
 
 

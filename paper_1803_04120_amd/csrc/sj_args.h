@@ -1,0 +1,91 @@
+// Argument blocks passed by value to the join kernels, and the constants
+// their layout depends on. Kept apart from the host-side declarations so
+// that a kernel's definition is its own source file, sj_device.h and this
+// header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sj {
+
+constexpr int kMaxDim = 8;
+
+// ---------------------------------------------------------------------
+// Grid description (Section IV-B), passed by value to kernels.
+// ---------------------------------------------------------------------
+struct GridParams {
+    double gmin[kMaxDim];
+    double w;
+    uint64_t dims[kMaxDim];
+    uint64_t stride[kMaxDim];
+    uint32_t d;
+};
+
+struct SearchArgs {
+    const uint64_t *B;
+    const uint32_t *starts;
+    const uint32_t *coords;
+    const uint32_t *masks;
+    uint32_t mask_off[kMaxDim];
+    uint64_t dims[kMaxDim];
+    uint64_t stride[kMaxDim];
+    uint32_t ncells;
+    uint32_t d;
+};
+
+struct JoinArgs {
+    const double *X;          // d x n, cell order
+    const float *Y;           // d x n, cell order, shifted (band path) or null
+    uint32_t n;
+    const uint32_t *cell_of;
+    const uint32_t *starts;
+    const uint64_t *roff;
+    const uint2 *rng;
+    const uint32_t *qlist;    // query points (cell order) or null for all
+    uint32_t nq;
+    double eps2;
+    float lo, hi;
+    // count outputs
+    uint32_t *own_cnt;
+    uint32_t *in_cnt;
+    // fill
+    const uint64_t *offc;     // row offset of each cell-ordered point's row
+    uint64_t out_base;
+    uint64_t out_cap;         // entries of out_j; writes at or past it set *overflow
+    uint32_t *overflow;
+    uint32_t *cur;
+    uint32_t *out_j;
+    const uint32_t *perm;     // A
+    // counters
+    unsigned long long *evals;
+    unsigned long long *band_rechecks;
+    // fill with the row sort fused in (each point's row is complete when its
+    // own evaluation ends): rows of at most the kernel's register-sort size
+    // are sorted and written as (i, j) pairs at off_orig[perm[p]]; longer
+    // rows stay in out_j for the row-sort kernels
+    const uint64_t *off_orig;
+    uint2 *pairs;
+};
+enum JoinMode { kCount = 0, kFill = 1 };
+
+// Grid-row tiled join (k_tile.hip): chunks of <= 64 cell-ordered points of
+// one grid row, candidate rows staged in LDS.
+struct TileArgs {
+    const uint64_t *B;
+    uint32_t ncells;
+    const uint32_t *coords;
+    const uint32_t *masks;
+    uint32_t mask_off[kMaxDim];
+    uint64_t dims[kMaxDim];
+    uint64_t stride[kMaxDim];
+    const uint32_t *cx;       // dimension-0 cell coordinate of each cell-ordered point
+    const uint2 *chunks;      // [first, end) point range of each chunk
+    uint32_t nchunks;         // upper bound on the chunk count (launch size)
+    const uint32_t *nchunks_dev;  // the chunk count (device)
+    uint32_t rows_per_chunk;  // 3^(d-1)
+    const uint2 *segs;        // [chunk * rows_per_chunk + row] candidate point segment
+};
+
+}  // namespace sj

@@ -10,10 +10,9 @@
 #include <string>
 
 #include "sj.h"
+#include "sj_args.h"
 
 namespace sj {
-
-constexpr int kMaxDim = 8;
 
 // Error carried from the internals to the C ABI boundary, where it becomes
 // a return code and the thread-local message.
@@ -99,17 +98,6 @@ void profile_reset();
 void profile_set(bool on);
 void profile_select(const char *prefix);
 int profile_read(void *out, uint32_t cap, uint32_t *count);
-
-// ---------------------------------------------------------------------
-// Grid description (Section IV-B), passed by value to kernels.
-// ---------------------------------------------------------------------
-struct GridParams {
-    double gmin[kMaxDim];
-    double w;
-    uint64_t dims[kMaxDim];
-    uint64_t stride[kMaxDim];
-    uint32_t d;
-};
 
 // ---------------------------------------------------------------------
 // Primitives (k_scan.hip, k_sort.hip)
@@ -202,75 +190,14 @@ void launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 // ---------------------------------------------------------------------
 // Search and join (k_join.hip)
 // ---------------------------------------------------------------------
-struct SearchArgs {
-    const uint64_t *B;
-    const uint32_t *starts;
-    const uint32_t *coords;
-    const uint32_t *masks;
-    uint32_t mask_off[kMaxDim];
-    uint64_t dims[kMaxDim];
-    uint64_t stride[kMaxDim];
-    uint32_t ncells;
-    uint32_t d;
-};
 // Candidate point ranges of every cell: counts, scan, fill. Returns the
 // number of ranges R (host sync); roff gets |G|+1 entries, rng 2R values.
 uint64_t build_ranges(const SearchArgs &a, int unicomp, uint64_t *roff /*[ncells+1]*/,
                       uint32_t **rng_out, size_t *rng_cap, hipStream_t s);
 
-struct JoinArgs {
-    const double *X;          // d x n, cell order
-    const float *Y;           // d x n, cell order, shifted (band path) or null
-    uint32_t n;
-    const uint32_t *cell_of;
-    const uint32_t *starts;
-    const uint64_t *roff;
-    const uint2 *rng;
-    const uint32_t *qlist;    // query points (cell order) or null for all
-    uint32_t nq;
-    double eps2;
-    float lo, hi;
-    // count outputs
-    uint32_t *own_cnt;
-    uint32_t *in_cnt;
-    // fill
-    const uint64_t *offc;     // row offset of each cell-ordered point's row
-    uint64_t out_base;
-    uint64_t out_cap;         // entries of out_j; writes at or past it set *overflow
-    uint32_t *overflow;
-    uint32_t *cur;
-    uint32_t *out_j;
-    const uint32_t *perm;     // A
-    // counters
-    unsigned long long *evals;
-    unsigned long long *band_rechecks;
-    // fill with the row sort fused in (each point's row is complete when its
-    // own evaluation ends): rows of at most the kernel's register-sort size
-    // are sorted and written as (i, j) pairs at off_orig[perm[p]]; longer
-    // rows stay in out_j for the row-sort kernels
-    const uint64_t *off_orig;
-    uint2 *pairs;
-};
-enum JoinMode { kCount = 0, kFill = 1 };
 void launch_join(const JoinArgs &a, uint32_t d, int unicomp, int mode, int band, hipStream_t s);
 
-// Grid-row tiled join (k_tile.hip): chunks of <= 64 cell-ordered points of
-// one grid row, candidate rows staged in LDS.
-struct TileArgs {
-    const uint64_t *B;
-    uint32_t ncells;
-    const uint32_t *coords;
-    const uint32_t *masks;
-    uint32_t mask_off[kMaxDim];
-    uint64_t dims[kMaxDim];
-    uint64_t stride[kMaxDim];
-    const uint32_t *cx;       // dimension-0 cell coordinate of each cell-ordered point
-    const uint2 *chunks;      // [first, end) point range of each chunk
-    uint32_t nchunks;         // upper bound on the chunk count (launch size)
-    const uint32_t *nchunks_dev;  // the chunk count (device)
-    uint32_t rows_per_chunk;  // 3^(d-1)
-    const uint2 *segs;        // [chunk * rows_per_chunk + row] candidate point segment
-};
+// Grid-row tiled join (k_tile.hip).
 // Builds the chunk list without a host sync: a grid row holds p points
 // in ceil(p / 64) <= p / 64 + 1 chunks, so there are at most
 // floor(n / 64) + rows chunks, rows <= min(ncells, rows_bound). Returns that
