@@ -54,19 +54,6 @@ __device__ __forceinline__ uint32_t lb_u64(const uint64_t *__restrict__ B, uint3
     return lo;
 }
 
-// first index in s[0..n) with s[i] >= v (s ascending)
-__device__ __forceinline__ uint32_t lb_lds(const uint32_t *s, uint32_t n, uint32_t v) {
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s[mid] < v)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ bool t_occupied(const TileArgs &t, uint32_t j, uint32_t c) {
     if (!t.masks) return true;
     return (t.masks[t.mask_off[j] + (c >> 5)] >> (c & 31u)) & 1u;
@@ -239,8 +226,18 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             uint32_t lo_c = c0p > 0 ? c0p - 1 : 0, hi_c = c0p + 1;
             if (kUni && own_row && !(c0p & 1u)) lo_c = hi_c = c0p;
             if (scx[0] > hi_c || scx[len - 1] < lo_c) return;
-            const uint32_t i_lo = lb_lds(scx, len, lo_c);
-            const uint32_t i_hi = lb_lds(scx, len, hi_c + 1);
+            // both window ends by one branchless search over the TS staged
+            // entries (those past len hold ~0u), the two chains interleaved
+            uint32_t i_lo = 0, i_hi = 0;
+#pragma unroll
+            for (uint32_t half = TS / 2; half > 0; half >>= 1) {
+                i_lo = scx[i_lo + half] < lo_c ? i_lo + half : i_lo;
+                i_hi = scx[i_hi + half] <= hi_c ? i_hi + half : i_hi;
+            }
+            i_lo += scx[i_lo] < lo_c ? 1u : 0u;
+            i_hi += scx[i_hi] <= hi_c ? 1u : 0u;
+            i_lo = i_lo < len ? i_lo : len;
+            i_hi = i_hi < len ? i_hi : len;
             if (kUni && own_row) {
                 // own cell as the triangle q >= p: skip q in [start of p's
                 // cell, p), a contiguous run of the tile
@@ -354,6 +351,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 if (kAgg) saux[i] = 0;
                 if (kPerm) saux[i] = a.perm[q];
             }
+            for (uint32_t i = len + lane; i < static_cast<uint32_t>(TS); i += 64) scx[i] = ~0u;
             const Tile nxt = advance(cur);
             wave_sync_lds();
             if (active) evaluate_tile(cur.T0, len, cur.own_row);
@@ -375,15 +373,29 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             const uint32_t len = own;
             uint32_t lds_len = 0;
             if (active && own != row_len) atomicOr(a.overflow, 1u);  // count and fill disagree
-            if (active && row_in_lds && len <= static_cast<uint32_t>(NS > 0 ? NS : 1)) {
-                uint32_t v[kNs];
+            const bool sort_here = active && row_in_lds && len <= static_cast<uint32_t>(NS > 0 ? NS : 1);
+            // network width: the wave's longest row rounded up to 4, 8, 16
+            // or kNs (entries past a row's length hold ~0u and stay last)
+            const uint32_t wlen = wave_max(sort_here ? len : 0u);
+            auto sort_row = [&](auto width) {
+                constexpr int W = decltype(width)::value;
+                uint32_t v[W];
 #pragma unroll
-                for (int k = 0; k < kNs; ++k)
-                    v[k] = (k < (NS > 0 ? NS : 1) && static_cast<uint32_t>(k) < len) ? srow[k] : 0xffffffffu;
-                register_bitonic<kNs>(v);
+                for (int k = 0; k < W; ++k) v[k] = static_cast<uint32_t>(k) < len ? srow[k] : 0xffffffffu;
+                register_bitonic<W>(v);
 #pragma unroll
-                for (int k = 0; k < kNs; ++k)
-                    if (k < (NS > 0 ? NS : 1) && static_cast<uint32_t>(k) < len) srow[k] = v[k];
+                for (int k = 0; k < W; ++k)
+                    if (static_cast<uint32_t>(k) < len) srow[k] = v[k];
+            };
+            if (sort_here) {
+                if (wlen <= 4)
+                    sort_row(std::integral_constant<int, 4>{});
+                else if (wlen <= 8)
+                    sort_row(std::integral_constant<int, 8>{});
+                else if (kNs > 16 && wlen <= 16)
+                    sort_row(std::integral_constant<int, (kNs > 16 ? 16 : kNs)>{});
+                else
+                    sort_row(std::integral_constant<int, kNs>{});
                 lds_len = len;
             }
             wave_sync_lds();  // last tile's reads of the staging slot are done
@@ -391,14 +403,15 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             swp[lane] = perm_p;
             swl[lane] = lds_len;
             wave_sync_lds();
-            // write-out: kNs lanes per row, 64 / kNs rows per pass, so each
-            // store instruction covers whole rows (contiguous (i, j) pairs)
-            // instead of one pair in each of 64 different rows
-            constexpr int kRowsPerPass = 64 / kNs;
-            const int sub = lane / kNs, k = lane % kNs;
+            // write-out: L lanes per row (the wave's longest row rounded up
+            // to a power of two), 64 / L rows per pass, so each store
+            // instruction covers whole rows (contiguous (i, j) pairs) instead
+            // of one pair in each of 64 different rows
+            const uint32_t wout = wave_max(lds_len);
+            const int lb = wout <= 1u ? 0 : 32 - __clz(static_cast<int>(wout - 1u));
+            const int sub = lane >> lb, k = lane & ((1 << lb) - 1);
             const uint32_t *srows = sr_all[wave];
-#pragma unroll 4
-            for (int r0 = 0; r0 < 64; r0 += kRowsPerPass) {
+            for (int r0 = 0; r0 < (wout ? 64 : 0); r0 += (64 >> lb)) {
                 const int r = r0 + sub;
                 const uint32_t rl = swl[r];
                 if (static_cast<uint32_t>(k) < rl) {

@@ -106,16 +106,19 @@ __device__ __forceinline__ void group16_bitonic64(uint32_t (&v)[4]) {
     }
 }
 
-// Sorts N values held in registers ascending with a fully unrolled bitonic
-// network (all register indices are compile-time constants).
-template <int N>
-__device__ __forceinline__ void register_bitonic(uint32_t (&v)[N]) {
+// Sorts the first W of N values held in registers ascending with a fully
+// unrolled bitonic network (W a power of two; all register indices are
+// compile-time constants). The stages of the N-wide network up to width W,
+// restricted to the first W entries, leave those sorted ascending.
+template <int W, int N>
+__device__ __forceinline__ void register_bitonic_first(uint32_t (&v)[N]) {
+    static_assert(W <= N && (W & (W - 1)) == 0, "sort width");
 #pragma unroll
-    for (int k = 2; k <= N; k <<= 1) {
+    for (int k = 2; k <= W; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
 #pragma unroll
-            for (int i = 0; i < N; ++i) {
+            for (int i = 0; i < W; ++i) {
                 const int l = i ^ j;
                 if (l > i) {
                     const uint32_t a = v[i], b = v[l];
@@ -131,6 +134,11 @@ __device__ __forceinline__ void register_bitonic(uint32_t (&v)[N]) {
             }
         }
     }
+}
+
+template <int N>
+__device__ __forceinline__ void register_bitonic(uint32_t (&v)[N]) {
+    register_bitonic_first<N, N>(v);
 }
 
 // Counters that many workgroups add to are spread over kCounterSlots
