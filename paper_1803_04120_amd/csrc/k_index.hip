@@ -25,9 +25,13 @@ constexpr int kThreads = 256;
 // Per-block partials: [min x kMaxDim][max x kMaxDim][non-finite flag].
 constexpr int kBboxPart = 2 * kMaxDim + 1;
 
+// D coordinates per point; each thread loads kBboxUnroll points before it
+// folds any of them in, so that many loads are in flight per thread.
+constexpr int kBboxUnroll = 4;
+
+template <int D>
 __global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *__restrict__ pts,
-                                                            uint64_t n, uint32_t d,
-                                                            double *__restrict__ part) {
+                                                            uint64_t n, double *__restrict__ part) {
     double mn[kMaxDim], mx[kMaxDim];
 #pragma unroll
     for (int j = 0; j < kMaxDim; ++j) {
@@ -35,22 +39,35 @@ __global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *__restr
         mx[j] = -INFINITY;
     }
     uint32_t flag = 0;
-    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x; i < n;
-         i += static_cast<uint64_t>(gridDim.x) * kThreads) {
+    auto fold = [&](const double (&v)[D]) {
 #pragma unroll
-        for (int j = 0; j < kMaxDim; ++j) {
-            if (j < static_cast<int>(d)) {
-                const double v = pts[i * d + j];
-                flag |= !isfinite(v);
-                mn[j] = fmin(mn[j], v);
-                mx[j] = fmax(mx[j], v);
-            }
+        for (int j = 0; j < D; ++j) {
+            flag |= !isfinite(v[j]);
+            mn[j] = fmin(mn[j], v[j]);
+            mx[j] = fmax(mx[j], v[j]);
         }
+    };
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kThreads;
+    uint64_t i = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    for (; i + (kBboxUnroll - 1) * stride < n; i += kBboxUnroll * stride) {
+        double v[kBboxUnroll][D];
+#pragma unroll
+        for (int u = 0; u < kBboxUnroll; ++u)
+#pragma unroll
+            for (int j = 0; j < D; ++j) v[u][j] = pts[(i + u * stride) * D + j];
+#pragma unroll
+        for (int u = 0; u < kBboxUnroll; ++u) fold(v[u]);
+    }
+    for (; i < n; i += stride) {
+        double v[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = pts[i * D + j];
+        fold(v);
     }
     __shared__ double smn[kThreads / 64][kMaxDim], smx[kThreads / 64][kMaxDim];
     const int wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < kMaxDim; ++j) {
+    for (int j = 0; j < D; ++j) {
         double a = mn[j], b = mx[j];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -68,7 +85,7 @@ __global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *__restr
     if (ballot(flag != 0) != 0 && lane_id() == 0) sbad = 1;
     __syncthreads();
     double *mine = part + static_cast<size_t>(blockIdx.x) * kBboxPart;
-    if (threadIdx.x < kMaxDim) {
+    if (threadIdx.x < D) {
         const int j = threadIdx.x;
         double a = smn[0][j], b = smx[0][j];
         for (int w = 1; w < kThreads / 64; ++w) {
@@ -338,7 +355,17 @@ void launch_bbox(const double *pts, uint64_t n, uint32_t d, double *bbox_out, ui
     DevBuf<double> part(static_cast<size_t>(nb) * kBboxPart);
     {
         KTimer kt_("bbox", s);
-        k_bbox_partial<<<nb, kThreads, 0, s>>>(pts, n, d, part.ptr);
+        switch (d) {
+            case 1: k_bbox_partial<1><<<nb, kThreads, 0, s>>>(pts, n, part.ptr); break;
+            case 2: k_bbox_partial<2><<<nb, kThreads, 0, s>>>(pts, n, part.ptr); break;
+            case 3: k_bbox_partial<3><<<nb, kThreads, 0, s>>>(pts, n, part.ptr); break;
+            case 4: k_bbox_partial<4><<<nb, kThreads, 0, s>>>(pts, n, part.ptr); break;
+            case 5: k_bbox_partial<5><<<nb, kThreads, 0, s>>>(pts, n, part.ptr); break;
+            case 6: k_bbox_partial<6><<<nb, kThreads, 0, s>>>(pts, n, part.ptr); break;
+            case 7: k_bbox_partial<7><<<nb, kThreads, 0, s>>>(pts, n, part.ptr); break;
+            case 8: k_bbox_partial<8><<<nb, kThreads, 0, s>>>(pts, n, part.ptr); break;
+            default: throw Error(SJ_EINVAL, "bbox: dimension out of range");
+        }
         SJ_LAUNCH_CHECK();
     }
     k_bbox_final<<<1, kThreads, 0, s>>>(part.ptr, nb, d, bbox_out, bad);
