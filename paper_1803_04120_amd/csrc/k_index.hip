@@ -200,9 +200,8 @@ __global__ __launch_bounds__(kThreads) void k_cell_coords(const uint64_t *__rest
         for (uint32_t i = threadIdx.x; i < mask_words; i += kThreads) lmask[i] = 0;
     __syncthreads();
     uint32_t mp = 0;
-    for (uint64_t h = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x; h < ncells;
-         h += static_cast<uint64_t>(gridDim.x) * kThreads) {
-        uint64_t id = B[h];
+    // cell h: coordinates decoded from its id, occupancy bits, size
+    auto cell = [&](uint64_t h, uint64_t id, uint32_t sz) {
         for (uint32_t j = 0; j < g.d; ++j) {
             uint32_t c;
             if (id < (1ull << 32) && g.dims[j] < (1ull << 32)) {  // 32-bit division when it fits
@@ -224,8 +223,26 @@ __global__ __launch_bounds__(kThreads) void k_cell_coords(const uint64_t *__rest
                 atomicOr(&masks[w], bit);
             }
         }
-        const uint32_t sz = starts[h + 1] - starts[h];
         mp = sz > mp ? sz : mp;
+    };
+    // four cells per thread and step, their loads issued before any is used
+    constexpr int kU = 4;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kThreads;
+    for (uint64_t h0 = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x; h0 < ncells;
+         h0 += kU * stride) {
+        uint64_t ids[kU];
+        uint32_t s0[kU], s1[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const uint64_t h = h0 + u * stride;
+            const bool in = h < ncells;
+            ids[u] = in ? B[h] : 0;
+            s0[u] = in ? starts[h] : 0;
+            s1[u] = in ? starts[h + 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (h0 + u * stride < ncells) cell(h0 + u * stride, ids[u], s1[u] - s0[u]);
     }
     mp = wave_max(mp);
     __shared__ uint32_t smp[kThreads / 64];
