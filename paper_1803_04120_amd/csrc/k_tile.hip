@@ -42,18 +42,6 @@ struct TileSize {
     static constexpr int value = half < 64 ? 64 : half;  // at least one candidate per lane
 };
 
-__device__ __forceinline__ uint32_t lb_u64(const uint64_t *__restrict__ B, uint32_t n, uint64_t key) {
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (B[mid] < key)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ bool t_occupied(const TileArgs &t, uint32_t j, uint32_t c) {
     if (!t.masks) return true;
     return (t.masks[t.mask_off[j] + (c >> 5)] >> (c & 31u)) & 1u;
@@ -568,9 +556,20 @@ __global__ __launch_bounds__(kThreads) void k_chunk_segments(TileArgs t, const u
         base += static_cast<uint64_t>(cj) * t.stride[j];
     }
     uint2 sg = make_uint2(0, 0);
-    if (ok) {
-        const uint32_t g_lo = lb_u64(t.B, t.ncells, base + lo0);
-        const uint32_t g_hi = lb_u64(t.B, t.ncells, base + hi0 + 1);
+    if (ok && t.ncells > 0) {
+        // lower bounds of both ends in B, the two searches interleaved
+        // (their loads are independent, so each step costs one latency)
+        const uint64_t k_lo = base + lo0, k_hi = base + hi0 + 1;
+        uint32_t g_lo = 0, g_hi = 0, len = t.ncells;
+        while (len > 1) {
+            const uint32_t half = len >> 1;
+            const uint64_t v_lo = t.B[g_lo + half], v_hi = t.B[g_hi + half];
+            g_lo = v_lo < k_lo ? g_lo + half : g_lo;
+            g_hi = v_hi < k_hi ? g_hi + half : g_hi;
+            len -= half;
+        }
+        g_lo += t.B[g_lo] < k_lo ? 1u : 0u;
+        g_hi += t.B[g_hi] < k_hi ? 1u : 0u;
         if (g_lo < g_hi) sg = make_uint2(starts[g_lo], starts[g_hi]);
     }
     segs[idx] = sg;
