@@ -288,14 +288,17 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
     uint64_t rows_bound = 1;
     for (uint32_t j = 1; j < d; ++j)
         rows_bound = ix.grid.dims[j] > (UINT64_MAX / 2) / rows_bound ? UINT64_MAX / 2 : rows_bound * ix.grid.dims[j];
-    sj::SideStream &side = sj::side_stream();
-    SideJoin side_join{s, side.s, side.ev[0]};
+    const bool use_side = sj::side_streams_on();
+    sj::SideStream *side = use_side ? &sj::side_stream() : nullptr;
+    SideJoin side_join{s, use_side ? side->s : s, use_side ? side->ev[0] : nullptr};
     auto start_chunks = [&](const auto *sorted_keys) {
-        SJ_HIP(hipEventRecord(side.ev[0], s));
-        SJ_HIP(hipStreamWaitEvent(side.s, side.ev[0], 0));
-        side_join.armed = true;
+        if (use_side) {
+            SJ_HIP(hipEventRecord(side->ev[0], s));
+            SJ_HIP(hipStreamWaitEvent(side->s, side->ev[0], 0));
+            side_join.armed = true;
+        }
         ix.nchunks = sj::build_chunks(sorted_keys, ix.grid.dims[0], static_cast<uint32_t>(n), rows_bound,
-                                      &ix.chunks, &ix.chunks_cap, side.s);
+                                      &ix.chunks, &ix.chunks_cap, use_side ? side->s : s);
     };
     // cell ids and the sort by cell (A)
     ix.perm.reset(n);

@@ -59,6 +59,11 @@ struct SideStream {
     hipEvent_t ev[2];
 };
 SideStream &side_stream();
+// Whether index builds of the calling thread may use its side stream (on by
+// default; the request server's workers, which already overlap requests,
+// turn it off).
+void set_side_streams(bool on);
+bool side_streams_on();
 
 void pool_trim();
 void pool_enter();

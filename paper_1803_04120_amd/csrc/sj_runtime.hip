@@ -112,7 +112,11 @@ struct SideStreams {
     }
 };
 thread_local SideStreams t_side;
+thread_local bool t_side_on = true;
 }  // namespace
+
+void set_side_streams(bool on) { t_side_on = on; }
+bool side_streams_on() { return t_side_on; }
 
 SideStream &side_stream() {
     int dev = 0;
