@@ -461,17 +461,16 @@ void launch_row_lengths(const uint32_t *own_cnt, const uint32_t *in_cnt, const u
 
 // out[0] = P (off_orig[n]), out[1] = longest row, out[2] = evaluations,
 // out[3] = band re-checks (both summed over the counter slots), out[4] =
-// chunks evaluated (the word after each evaluation slot; 0 for the per-point
-// kernel), out[5..8) = rows longer than 16, 24, 32
+// chunk count (0 without chunks), out[5..8) = rows longer than 16, 24, 32
 // (row_stats[1..4)): the count pass reads these back at once.
 __global__ __launch_bounds__(256) void k_count_summary(const uint64_t *__restrict__ off_orig, uint64_t n,
                                                         const uint32_t *__restrict__ max_len,
                                                         const unsigned long long *__restrict__ counters,
+                                                        const uint32_t *__restrict__ nchunks,
                                                         uint64_t *__restrict__ out) {
-    __shared__ unsigned long long part[7][256 / 64];
+    __shared__ unsigned long long part[6][256 / 64];
     const int k = threadIdx.x;  // one counter slot and two row-stat blocks per thread
     unsigned long long e = counters[static_cast<size_t>(k) * kCounterStride];
-    unsigned long long ch = counters[static_cast<size_t>(k) * kCounterStride + 1];
     unsigned long long b = counters[static_cast<size_t>(kCounterSlots + k) * kCounterStride];
     unsigned long long mx = 0, c16 = 0, c24 = 0, c32 = 0;
     for (int q = k; q < kRowStatBlocks; q += 256) {
@@ -483,7 +482,6 @@ __global__ __launch_bounds__(256) void k_count_summary(const uint64_t *__restric
     }
     for (int off = 32; off > 0; off >>= 1) {
         e += __shfl_xor(e, off, 64);
-        ch += __shfl_xor(ch, off, 64);
         b += __shfl_xor(b, off, 64);
         const unsigned long long om = __shfl_xor(mx, off, 64);
         mx = om > mx ? om : mx;
@@ -498,14 +496,12 @@ __global__ __launch_bounds__(256) void k_count_summary(const uint64_t *__restric
         part[3][k >> 6] = c16;
         part[4][k >> 6] = c24;
         part[5][k >> 6] = c32;
-        part[6][k >> 6] = ch;
     }
     __syncthreads();
     if (k == 0) {
-        unsigned long long se = 0, sb = 0, m = 0, s16 = 0, s24 = 0, s32 = 0, sch = 0;
+        unsigned long long se = 0, sb = 0, m = 0, s16 = 0, s24 = 0, s32 = 0;
         for (int w = 0; w < 256 / 64; ++w) {
             se += part[0][w];
-            sch += part[6][w];
             sb += part[1][w];
             m = part[2][w] > m ? part[2][w] : m;
             s16 += part[3][w];
@@ -519,14 +515,15 @@ __global__ __launch_bounds__(256) void k_count_summary(const uint64_t *__restric
         out[7] = s32;
         out[2] = se;
         out[3] = sb;
-        out[4] = sch;
+        out[4] = nchunks ? *nchunks : 0;
     }
 }
 
 void launch_count_summary(const uint64_t *off_orig, uint64_t n, const uint32_t *max_len,
-                          const unsigned long long *counters, uint64_t *out, hipStream_t s) {
+                          const unsigned long long *counters, const uint32_t *nchunks, uint64_t *out,
+                          hipStream_t s) {
     static_assert(kCounterSlots == 256, "one thread per counter slot");
-    k_count_summary<<<1, 256, 0, s>>>(off_orig, n, max_len, counters, out);
+    k_count_summary<<<1, 256, 0, s>>>(off_orig, n, max_len, counters, nchunks, out);
     SJ_LAUNCH_CHECK();
 }
 

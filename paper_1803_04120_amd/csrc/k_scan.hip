@@ -41,21 +41,29 @@ struct ScanOps {
     Tout *out[2];
     Tout *total[2];
 };
-// 1 where sorted point r starts a grid row: its cell id and that of point
-// r - 1 differ in the dimension-1..d-1 part, id / |g_0| (dimension 0 varies
-// fastest in the linear id).
-template <typename K>
-struct RowHeadKeyLoad {
-    const K *keys;
-    uint64_t dims0;
+
+// Grid-row head flag of cell h: its dimension-1..d-1 coordinates differ
+// from those of cell h - 1 (cells sorted by linear id, dimension 0 fastest).
+struct RowHeadLoad {
+    const uint32_t *coords;
+    uint32_t d;
+    __device__ __forceinline__ uint32_t operator()(size_t h) const {
+        if (h == 0) return 1u;
+        uint32_t f = 0;
+        for (uint32_t j = 1; j < d; ++j) f |= coords[h * d + j] != coords[(h - 1) * d + j];
+        return f;
+    }
+};
+
+// Chunks of grid row r (ceil(points / 64)); rows past the row count (the
+// total of the row-head scan, row_of[ncells]) have none.
+struct RowChunksLoad {
+    const uint32_t *row_pt;
+    const uint64_t *row_of;
+    size_t ncells;
     __device__ __forceinline__ uint32_t operator()(size_t r) const {
-        if (r == 0) return 1u;
-        if (sizeof(K) == 4) {
-            if (dims0 > 0xffffffffull) return 0u;  // every 32-bit id is below |g_0|: one row
-            const uint32_t d0 = static_cast<uint32_t>(dims0);
-            return static_cast<uint32_t>(keys[r]) / d0 != static_cast<uint32_t>(keys[r - 1]) / d0 ? 1u : 0u;
-        }
-        return static_cast<uint64_t>(keys[r]) / dims0 != static_cast<uint64_t>(keys[r - 1]) / dims0 ? 1u : 0u;
+        if (r >= row_of[ncells]) return 0u;
+        return (row_pt[r + 1] - row_pt[r] + 63u) / 64u;
     }
 };
 
@@ -228,6 +236,16 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, hipStream_t
     scan_one<uint32_t, false>(ArrayLoad<uint32_t>{in}, out, n, nullptr, s);
 }
 
+void scan_row_heads_exclusive(const uint32_t *coords, uint32_t d, uint64_t *row_of, size_t ncells,
+                              hipStream_t s) {
+    scan_one<uint64_t, false>(RowHeadLoad{coords, d}, row_of, ncells, row_of + ncells, s);
+}
+
+void scan_row_chunks_exclusive(const uint32_t *row_pt, const uint64_t *row_of, uint64_t *ch_off, size_t ncells,
+                               hipStream_t s) {
+    scan_one<uint64_t, false>(RowChunksLoad{row_pt, row_of, ncells}, ch_off, ncells, ch_off + ncells, s);
+}
+
 void scan_long_rows_exclusive(const uint64_t *off, uint32_t lo, uint32_t *pos, size_t rows, hipStream_t s) {
     scan_one<uint32_t, false>(LongRowLoad{off, lo}, pos, rows, pos + rows, s);
 }
@@ -238,12 +256,5 @@ void scan_head_flags_inclusive(const K *sorted_keys, uint32_t *out, size_t n, hi
 }
 template void scan_head_flags_inclusive<uint32_t>(const uint32_t *, uint32_t *, size_t, hipStream_t);
 template void scan_head_flags_inclusive<uint64_t>(const uint64_t *, uint32_t *, size_t, hipStream_t);
-
-template <typename K>
-void scan_row_heads_inclusive(const K *sorted_keys, uint64_t dims0, uint32_t *out, size_t n, hipStream_t s) {
-    scan_one<uint32_t, true>(RowHeadKeyLoad<K>{sorted_keys, dims0}, out, n, nullptr, s);
-}
-template void scan_row_heads_inclusive<uint32_t>(const uint32_t *, uint64_t, uint32_t *, size_t, hipStream_t);
-template void scan_row_heads_inclusive<uint64_t>(const uint64_t *, uint64_t, uint32_t *, size_t, hipStream_t);
 
 }  // namespace sj

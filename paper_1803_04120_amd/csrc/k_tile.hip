@@ -83,15 +83,13 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     // to the XCDs round robin: a dense cluster's many heavy chunks, adjacent
     // in cell order, spread over all XCDs
     const uint32_t chunk = blockIdx.x * kWaves + wave;
-    uint2 ch = chunk < t.nchunks ? t.chunks[chunk] : make_uint2(0, 0);
-    ch.x = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(ch.x)));
-    ch.y = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(ch.y)));
-    const bool chunk_used = ch.x < ch.y;  // uniform across the wave; empty slots exit
-    if (chunk_used) {
-        // segment table of the chunk, 64 rows per register load
+    if (chunk < *t.nchunks_dev) {  // uniform across the wave
+        // segment table of the chunk, 64 rows per register load; the first
+        // load is issued before anything else (it needs only the chunk index)
         const uint2 *segs = t.segs + static_cast<size_t>(chunk) * t.rows_per_chunk;
         uint32_t seg_base = 0;
         uint2 seg_reg = static_cast<uint32_t>(lane) < t.rows_per_chunk ? segs[lane] : make_uint2(0, 0);
+        const uint2 ch = t.chunks[chunk];
         const uint32_t p = ch.x + static_cast<uint32_t>(lane);
         const bool active = p < ch.y;
         double xp[D];
@@ -456,9 +454,6 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     if (kMode == kCount) {
         add_counter(a.evals, evals);
         if (kBand) add_counter(a.band_rechecks, rechecks);
-        // chunks evaluated, in the word after the evaluation slot
-        if (chunk_used && lane == 0)
-            atomicAdd(a.evals + static_cast<size_t>(blockIdx.x % kCounterSlots) * kCounterStride + 1, 1ull);
     }
 }
 
@@ -503,29 +498,28 @@ void launch_tiled_d(const JoinArgs &a, const TileArgs &t, int unicomp, int mode,
 }
 
 // ------------------------------------------------------------ chunk list
-// First point of every grid row (row of sorted point r: row_incl[r] - 1);
-// row_pt[rows] = n.
-__global__ __launch_bounds__(kThreads) void k_row_starts(const uint32_t *__restrict__ row_incl, uint32_t n,
+// First point of every grid row (row index = exclusive scan of the row-head
+// flags, total at row_of[ncells]); row_pt[nrows] = n.
+__global__ __launch_bounds__(kThreads) void k_row_points(const uint64_t *__restrict__ row_of,
+                                                          const uint32_t *__restrict__ starts,
+                                                          uint32_t ncells, uint32_t n,
                                                           uint32_t *__restrict__ row_pt) {
-    const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
-    if (r >= n) return;
-    const uint32_t row = row_incl[r] - 1u;
-    if (r == 0 || row_incl[r - 1] != row_incl[r]) row_pt[row] = r;
-    if (r == n - 1) row_pt[row + 1] = n;
+    const uint32_t h = blockIdx.x * kThreads + threadIdx.x;
+    if (h < ncells && row_of[h + 1] != row_of[h]) row_pt[row_of[h]] = starts[h];  // h heads a row
+    if (h == 0) row_pt[row_of[ncells]] = n;
 }
 
-// Every 64th point of a row (from its first) opens a chunk of <= 64 points,
-// stored in slot floor(row start / 64) + row + (r - row start) / 64.
-__global__ __launch_bounds__(kThreads) void k_emit_chunks(const uint32_t *__restrict__ row_incl,
-                                                           const uint32_t *__restrict__ row_pt, uint32_t n,
-                                                           uint2 *__restrict__ chunks) {
+__global__ __launch_bounds__(kThreads) void k_emit_chunks(const uint32_t *__restrict__ row_pt,
+                                                           const uint64_t *__restrict__ row_of,
+                                                           const uint64_t *__restrict__ ch_off,
+                                                           uint32_t ncells, uint2 *__restrict__ chunks,
+                                                           uint32_t *__restrict__ nchunks_dev) {
     const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
-    if (r >= n) return;
-    const uint32_t row = row_incl[r] - 1u;
-    const uint32_t rs = row_pt[row];
-    if ((r - rs) & 63u) return;
-    const uint32_t re = row_pt[row + 1];
-    chunks[rs / 64u + row + (r - rs) / 64u] = make_uint2(r, re - r > 64u ? r + 64u : re);
+    if (r == 0) *nchunks_dev = static_cast<uint32_t>(ch_off[ncells]);
+    if (r >= ncells || r >= row_of[ncells]) return;
+    const uint32_t s = row_pt[r], e = row_pt[r + 1];
+    uint64_t k = ch_off[r];
+    for (uint32_t q = s; q < e; q += 64, ++k) chunks[k] = make_uint2(q, q + 64 < e ? q + 64 : e);
 }
 
 // Point segment of every (chunk, row) pair: the chunk's dimension-0 window
@@ -536,16 +530,11 @@ __global__ __launch_bounds__(kThreads) void k_chunk_segments(TileArgs t, const u
                                                               const uint32_t *__restrict__ starts,
                                                               uint32_t d, uint2 *__restrict__ segs) {
     const uint64_t idx = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
-    const uint64_t total = static_cast<uint64_t>(t.nchunks) * t.rows_per_chunk;
+    const uint64_t total = static_cast<uint64_t>(*t.nchunks_dev) * t.rows_per_chunk;
     if (idx >= total) return;
     const uint32_t chunk = static_cast<uint32_t>(idx / t.rows_per_chunk);
     uint32_t r = static_cast<uint32_t>(idx % t.rows_per_chunk);
     const uint2 ch = t.chunks[chunk];
-    if (ch.x >= ch.y) {  // empty slot
-        segs[idx] = make_uint2(0, 0);
-        return;
-    }
-    const uint32_t ncells = *t.last_cell + 1u;
     const uint32_t hf = cell_of[ch.x], hl = cell_of[ch.y - 1];
     const uint32_t a0 = t.coords[static_cast<size_t>(hf) * d], b0 = t.coords[static_cast<size_t>(hl) * d];
     const uint32_t lo0 = a0 > 0 ? a0 - 1 : 0;
@@ -567,11 +556,11 @@ __global__ __launch_bounds__(kThreads) void k_chunk_segments(TileArgs t, const u
         base += static_cast<uint64_t>(cj) * t.stride[j];
     }
     uint2 sg = make_uint2(0, 0);
-    if (ok) {
+    if (ok && t.ncells > 0) {
         // lower bounds of both ends in B, the two searches interleaved
         // (their loads are independent, so each step costs one latency)
         const uint64_t k_lo = base + lo0, k_hi = base + hi0 + 1;
-        uint32_t g_lo = 0, g_hi = 0, len = ncells;
+        uint32_t g_lo = 0, g_hi = 0, len = t.ncells;
         while (len > 1) {
             const uint32_t half = len >> 1;
             const uint64_t v_lo = t.B[g_lo + half], v_hi = t.B[g_hi + half];
@@ -586,36 +575,42 @@ __global__ __launch_bounds__(kThreads) void k_chunk_segments(TileArgs t, const u
     segs[idx] = sg;
 }
 
+__global__ void k_zero_word(uint32_t *p) {
+    if (threadIdx.x == 0) *p = 0;
+}
 
 inline unsigned nblk(uint64_t n) { return static_cast<unsigned>((n + kThreads - 1) / kThreads); }
 
 }  // namespace
 
-template <typename K>
-uint32_t build_chunks(const K *sorted_keys, uint64_t dims0, uint32_t n, uint64_t rows_bound, uint2 **chunks_out,
-                      size_t *chunks_cap, hipStream_t s) {
-    if (n == 0) return 0;
-    const uint64_t bound = static_cast<uint64_t>(n) / 64 + std::min<uint64_t>(n, rows_bound);
+uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, uint32_t ncells, uint32_t n, uint32_t d,
+                      uint64_t rows_bound, uint2 **chunks_out, size_t *chunks_cap, uint32_t *nchunks_dev,
+                      hipStream_t s) {
+    // chunk list only; row segments come from build_chunk_segments
+    if (ncells == 0 || n == 0) {
+        k_zero_word<<<1, 64, 0, s>>>(nchunks_dev);
+        SJ_LAUNCH_CHECK();
+        return 0;
+    }
+    const uint64_t bound = static_cast<uint64_t>(n) / 64 + std::min<uint64_t>(ncells, rows_bound);
     if (bound >= 0xffffffffULL) throw Error(SJ_ECAPACITY, "too many join chunks");
-    DevBuf<uint32_t> row_incl(n), row_pt(static_cast<size_t>(n) + 1);
-    scan_row_heads_inclusive<K>(sorted_keys, dims0, row_incl.ptr, n, s);
-    k_row_starts<<<nblk(n), kThreads, 0, s>>>(row_incl.ptr, n, row_pt.ptr);
+    // rows are bounded by the cells, so every array below is sized by ncells
+    DevBuf<uint32_t> row_pt(static_cast<size_t>(ncells) + 1);
+    DevBuf<uint64_t> row_of(static_cast<size_t>(ncells) + 1), choff(static_cast<size_t>(ncells) + 1);
+    scan_row_heads_exclusive(coords, d, row_of.ptr, ncells, s);
+    k_row_points<<<nblk(ncells), kThreads, 0, s>>>(row_of.ptr, starts, ncells, n, row_pt.ptr);
     SJ_LAUNCH_CHECK();
+    scan_row_chunks_exclusive(row_pt.ptr, row_of.ptr, choff.ptr, ncells, s);
     if (bound > *chunks_cap) {
         if (*chunks_out) dev_free(*chunks_out);
         *chunks_out = static_cast<uint2 *>(dev_alloc(bound * sizeof(uint2)));
         *chunks_cap = bound;
     }
-    launch_fill_u64(reinterpret_cast<uint64_t *>(*chunks_out), bound, 0ull, s);  // empty slots
-    k_emit_chunks<<<nblk(n), kThreads, 0, s>>>(row_incl.ptr, row_pt.ptr, n, *chunks_out);
+    k_emit_chunks<<<nblk(ncells), kThreads, 0, s>>>(row_pt.ptr, row_of.ptr, choff.ptr, ncells, *chunks_out,
+                                                   nchunks_dev);
     SJ_LAUNCH_CHECK();
     return static_cast<uint32_t>(bound);
 }
-
-template uint32_t build_chunks<uint32_t>(const uint32_t *, uint64_t, uint32_t, uint64_t, uint2 **, size_t *,
-                                         hipStream_t);
-template uint32_t build_chunks<uint64_t>(const uint64_t *, uint64_t, uint32_t, uint64_t, uint2 **, size_t *,
-                                         hipStream_t);
 
 void build_chunk_segments(const TileArgs &t, const uint32_t *cell_of, const uint32_t *starts,
                           uint32_t d, uint2 *segs, hipStream_t s) {

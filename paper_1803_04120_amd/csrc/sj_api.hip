@@ -137,7 +137,8 @@ struct sj_index {
     DevBuf<uint32_t> cx;
     uint2 *chunks = nullptr;
     size_t chunks_cap = 0;
-    uint32_t nchunks = 0;               // chunk slots (launch size)
+    uint32_t nchunks = 0;               // upper bound (launch size)
+    DevBuf<uint32_t> nchunks_dev;       // exact count
     uint32_t rows_per_chunk = 0;
     DevBuf<uint2> segs;
     bool chunks_ready = false;
@@ -232,29 +233,6 @@ sj_join_opts resolve_opts(const sj_join_opts *o) {
     return r;
 }
 
-sj::TileArgs tile_args(sj_index &ix);
-
-// Work put on the side stream is joined back into the caller's stream (the
-// caller's stream waits for it) before the call synchronises, also when the
-// call ends by an exception, so no buffer is released while the side stream
-// may still use it.
-struct SideJoin {
-    hipStream_t s, b;
-    hipEvent_t e;
-    bool armed = false;
-    void join() {
-        if (!armed) return;
-        armed = false;
-        SJ_HIP(hipEventRecord(e, b));
-        SJ_HIP(hipStreamWaitEvent(s, e, 0));
-    }
-    ~SideJoin() {
-        if (!armed) return;
-        (void)hipEventRecord(e, b);
-        (void)hipStreamWaitEvent(s, e, 0);
-    }
-};
-
 void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
     const double t0 = now_ms();
     const uint64_t n = ix.n;
@@ -280,26 +258,6 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
         ix.bmax[j] = hb[sj::kMaxDim + j];
     }
     compute_grid(ix);
-    // The chunk list of the tiled join (grid rows: cells that agree in
-    // dimensions 1..d-1) needs only the sorted ids, so it is built on a
-    // second stream beside the cell tables, coordinates and cell-ordered copy
-    // (measured: with the chunk segments there too, the segments' binary
-    // searches slowed beside the copy and the build waited for them).
-    uint64_t rows_bound = 1;
-    for (uint32_t j = 1; j < d; ++j)
-        rows_bound = ix.grid.dims[j] > (UINT64_MAX / 2) / rows_bound ? UINT64_MAX / 2 : rows_bound * ix.grid.dims[j];
-    const bool use_side = sj::side_streams_on();
-    sj::SideStream *side = use_side ? &sj::side_stream() : nullptr;
-    SideJoin side_join{s, use_side ? side->s : s, use_side ? side->ev[0] : nullptr};
-    auto start_chunks = [&](const auto *sorted_keys) {
-        if (use_side) {
-            SJ_HIP(hipEventRecord(side->ev[0], s));
-            SJ_HIP(hipStreamWaitEvent(side->s, side->ev[0], 0));
-            side_join.armed = true;
-        }
-        ix.nchunks = sj::build_chunks(sorted_keys, ix.grid.dims[0], static_cast<uint32_t>(n), rows_bound,
-                                      &ix.chunks, &ix.chunks_cap, use_side ? side->s : s);
-    };
     // cell ids and the sort by cell (A)
     ix.perm.reset(n);
     DevBuf<uint32_t> ids_alt(n);
@@ -313,7 +271,6 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
             std::swap(keys, keys_alt);
             std::swap(ix.perm, ids_alt);
         }
-        start_chunks(keys.ptr);
         sj::build_cells<uint32_t>(keys.ptr, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
     } else {
         DevBuf<uint64_t> keys(n), keys_alt(n);
@@ -322,7 +279,6 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
             std::swap(keys, keys_alt);
             std::swap(ix.perm, ids_alt);
         }
-        start_chunks(keys.ptr);
         sj::build_cells<uint64_t>(keys.ptr, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
     }
     // per-cell coordinates and occupancy masks M_j (Section IV-C)
@@ -353,17 +309,6 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
         ix.shift[j] = 0.5 * (ix.bmin[j] + ix.bmax[j]);
         ix.extent = std::max(ix.extent, std::max(std::fabs(ix.bmax[j] - ix.shift[j]),
                                                  std::fabs(ix.bmin[j] - ix.shift[j])));
-    }
-    // candidate segments of every chunk: they need the chunk list (side
-    // stream) and the cell tables, coordinates and masks
-    side_join.join();
-    {
-        uint32_t r3 = 1;
-        for (uint32_t j = 1; j < d; ++j) r3 *= 3;
-        ix.rows_per_chunk = r3;
-        ix.segs.reset(static_cast<size_t>(ix.nchunks) * r3);
-        sj::build_chunk_segments(tile_args(ix), ix.cell_of.ptr, ix.starts.ptr, d, ix.segs.ptr, s);
-        ix.chunks_ready = true;
     }
     SJ_HIP(hipMemcpyAsync(hs.p, ix.cell_of.ptr + (n - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
@@ -402,7 +347,7 @@ bool use_tiled() {
 sj::TileArgs tile_args(sj_index &ix) {
     sj::TileArgs t{};
     t.B = ix.B.ptr;
-    t.last_cell = ix.n ? ix.cell_of.ptr + (ix.n - 1) : nullptr;
+    t.ncells = static_cast<uint32_t>(ix.ncells);
     t.coords = ix.coords.ptr;
     t.masks = ix.mask_words ? ix.masks.ptr : nullptr;
     for (uint32_t j = 0; j < ix.d; ++j) {
@@ -413,6 +358,7 @@ sj::TileArgs tile_args(sj_index &ix) {
     t.cx = ix.cx.ptr;
     t.chunks = ix.chunks;
     t.nchunks = ix.nchunks;
+    t.nchunks_dev = ix.nchunks_dev.ptr;
     t.rows_per_chunk = ix.rows_per_chunk;
     t.segs = ix.segs.ptr;
     return t;
@@ -448,10 +394,22 @@ uint32_t fused_slot(const sj_index &ix) {
     return 32u;
 }
 
-// The chunk list and its segments are built with the index (beside the
-// cell-ordered copy, on a second stream).
-void ensure_chunks(sj_index &ix) {
-    if (!ix.chunks_ready) throw Error(SJ_EDEVICE, "internal: index has no chunk list");
+void ensure_chunks(sj_index &ix, hipStream_t s) {
+    if (ix.chunks_ready) return;
+    ix.nchunks_dev.ensure(1);
+    // grid rows: one per occupied combination of the dimension-1..d-1 cells
+    uint64_t rows_bound = 1;
+    for (uint32_t j = 1; j < ix.d; ++j)
+        rows_bound = ix.grid.dims[j] > (UINT64_MAX / 2) / rows_bound ? UINT64_MAX / 2 : rows_bound * ix.grid.dims[j];
+    ix.nchunks = sj::build_chunks(ix.coords.ptr, ix.starts.ptr, static_cast<uint32_t>(ix.ncells),
+                                  static_cast<uint32_t>(ix.n), ix.d, rows_bound, &ix.chunks, &ix.chunks_cap,
+                                  ix.nchunks_dev.ptr, s);
+    uint32_t r3 = 1;
+    for (uint32_t j = 1; j < ix.d; ++j) r3 *= 3;
+    ix.rows_per_chunk = r3;
+    ix.segs.reset(static_cast<size_t>(ix.nchunks) * r3);
+    sj::build_chunk_segments(tile_args(ix), ix.cell_of.ptr, ix.starts.ptr, ix.d, ix.segs.ptr, s);
+    ix.chunks_ready = true;
 }
 
 void ensure_f32(sj_index &ix, hipStream_t s) {
@@ -507,7 +465,7 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     const int uni = o.unicomp ? 1 : 0;
     const bool tiled = use_tiled();
     if (tiled)
-        ensure_chunks(ix);
+        ensure_chunks(ix, s);
     else
         ensure_ranges(ix, uni, s);
     if (ix.band_used) ensure_f32(ix, s);
@@ -536,7 +494,7 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     sj::scan_exclusive_u32_to_u64_x2(ix.len_orig.ptr, ix.off_orig.ptr, ix.len_cell.ptr, ix.off_cell.ptr, n, s);
     ix.summary.ensure(8);
     sj::launch_count_summary(ix.off_orig.ptr, n, ix.max_len.ptr, ix.counters.ptr,
-                             ix.summary.ptr, s);
+                             tiled ? ix.nchunks_dev.ptr : nullptr, ix.summary.ptr, s);
     sj::HostStage hs;
     SJ_HIP(hipMemcpyAsync(hs.p, ix.summary.ptr, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
@@ -576,7 +534,7 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
     const bool whole = (i0 == 0 && i1 == n);
     const bool tiled = whole && use_tiled();
     if (tiled)
-        ensure_chunks(ix);
+        ensure_chunks(ix, s);
     else
         ensure_ranges(ix, mode, s);
     sj::JoinArgs a = base_args(ix, tiled ? 0 : mode);

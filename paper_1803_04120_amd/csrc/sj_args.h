@@ -74,15 +74,16 @@ enum JoinMode { kCount = 0, kFill = 1 };
 // one grid row, candidate rows staged in LDS.
 struct TileArgs {
     const uint64_t *B;
-    const uint32_t *last_cell;  // cell of the last cell-ordered point: |G| - 1 (device)
+    uint32_t ncells;
     const uint32_t *coords;
     const uint32_t *masks;
     uint32_t mask_off[kMaxDim];
     uint64_t dims[kMaxDim];
     uint64_t stride[kMaxDim];
     const uint32_t *cx;       // dimension-0 cell coordinate of each cell-ordered point
-    const uint2 *chunks;      // [first, end) point range of each chunk slot ([0, 0): empty)
-    uint32_t nchunks;         // chunk slots (launch size)
+    const uint2 *chunks;      // [first, end) point range of each chunk
+    uint32_t nchunks;         // upper bound on the chunk count (launch size)
+    const uint32_t *nchunks_dev;  // the chunk count (device)
     uint32_t rows_per_chunk;  // 3^(d-1)
     const uint2 *segs;        // [chunk * rows_per_chunk + row] candidate point segment
 };

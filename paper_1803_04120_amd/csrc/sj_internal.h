@@ -51,20 +51,6 @@ struct HostStage {
     template <typename T>
     T *as() const { return static_cast<T *>(p); }
 };
-// A second stream of the calling host thread on the current device (default
-// priority, non-blocking), with two events to order it against the caller's
-// stream; created on first use, destroyed with the thread.
-struct SideStream {
-    hipStream_t s;
-    hipEvent_t ev[2];
-};
-SideStream &side_stream();
-// Whether index builds of the calling thread may use its side stream (on by
-// default; the request server's workers, which already overlap requests,
-// turn it off).
-void set_side_streams(bool on);
-bool side_streams_on();
-
 void pool_trim();
 void pool_enter();
 void pool_leave_after_sync();
@@ -125,11 +111,15 @@ void scan_exclusive_u32_to_u64_x2(const uint32_t *in0, uint64_t *out0, const uin
 void scan_inclusive_u32(uint32_t *data, size_t n, hipStream_t s);
 // exclusive scan of u32 into u32 (no total), in place allowed.
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t n, hipStream_t s);
-// Inclusive scan of the grid-row head flags of the sorted points (a point
-// heads a row when its cell id and its predecessor's differ in id / dims0):
-// out[r] - 1 is the row of sorted point r, out[n - 1] the number of rows.
-template <typename K>
-void scan_row_heads_inclusive(const K *sorted_keys, uint64_t dims0, uint32_t *out, size_t n, hipStream_t s);
+// Exclusive scan of the grid-row head flags of the cells (coordinates
+// cell-major, d per cell): row_of[h] = rows starting before cell h,
+// row_of[ncells] = number of rows.
+void scan_row_heads_exclusive(const uint32_t *coords, uint32_t d, uint64_t *row_of, size_t ncells,
+                              hipStream_t s);
+// ch_off[r] = chunks of the grid rows before r (ceil(points / 64) each, from
+// the rows' first points row_pt), ch_off[ncells] = all chunks.
+void scan_row_chunks_exclusive(const uint32_t *row_pt, const uint64_t *row_of, uint64_t *ch_off, size_t ncells,
+                               hipStream_t s);
 // pos[r] = rows before r longer than lo entries (lengths off[r+1] - off[r]),
 // pos[rows] = their number.
 void scan_long_rows_exclusive(const uint64_t *off, uint32_t lo, uint32_t *pos, size_t rows, hipStream_t s);
@@ -208,15 +198,13 @@ uint64_t build_ranges(const SearchArgs &a, int unicomp, uint64_t *roff /*[ncells
 void launch_join(const JoinArgs &a, uint32_t d, int unicomp, int mode, int band, hipStream_t s);
 
 // Grid-row tiled join (k_tile.hip).
-// Chunk list from the sorted cell ids (dimension-0 extent dims0): every grid
-// row's points in chunks of <= 64, row r's first chunk in slot
-// floor(first point / 64) + r. Rows never overlap in that layout, so
-// floor(n / 64) + min(n, rows_bound) slots hold them all (rows_bound: grid
-// rows possible); slots between rows are empty ([0, 0)). Returns the slot
-// count; no host sync, no cell count needed.
-template <typename K>
-uint32_t build_chunks(const K *sorted_keys, uint64_t dims0, uint32_t n, uint64_t rows_bound, uint2 **chunks_out,
-                      size_t *chunks_cap, hipStream_t s);
+// Builds the chunk list without a host sync: a grid row holds p points
+// in ceil(p / 64) <= p / 64 + 1 chunks, so there are at most
+// floor(n / 64) + rows chunks, rows <= min(ncells, rows_bound). Returns that
+// bound; the exact count goes to *nchunks_dev.
+uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, uint32_t ncells, uint32_t n, uint32_t d,
+                      uint64_t rows_bound, uint2 **chunks_out, size_t *chunks_cap, uint32_t *nchunks_dev,
+                      hipStream_t s);
 void build_chunk_segments(const TileArgs &t, const uint32_t *cell_of, const uint32_t *starts,
                           uint32_t d, uint2 *segs, hipStream_t s);
 void launch_join_tiled(const JoinArgs &a, const TileArgs &t, uint32_t d, int unicomp, int mode,
@@ -230,11 +218,11 @@ void launch_row_lengths(const uint32_t *own_cnt, const uint32_t *in_cnt, const u
                         uint64_t n, uint32_t *len_orig, uint32_t *len_cell, uint32_t *row_stats,
                         hipStream_t s);
 // Gathers the count pass results into out[0..8): P, longest row,
-// evaluations, band re-checks, chunks evaluated (the word after each
-// evaluation counter slot; 0 for the per-point kernel), rows longer than 16,
-// 24, 32 (max_len = the row_stats of launch_row_lengths).
+// evaluations, band re-checks, chunk count (nchunks may be null), rows
+// longer than 16, 24, 32 (max_len = the row_stats of launch_row_lengths).
 void launch_count_summary(const uint64_t *off_orig, uint64_t n, const uint32_t *max_len,
-                          const unsigned long long *counters, uint64_t *out, hipStream_t s);
+                          const unsigned long long *counters, const uint32_t *nchunks, uint64_t *out,
+                          hipStream_t s);
 void launch_gather_offsets(const uint64_t *off_orig, const uint32_t *perm, uint64_t n,
                            uint64_t *offc, hipStream_t s);
 // cell-ordered points whose original id lies in [i0, i1), in cell order.

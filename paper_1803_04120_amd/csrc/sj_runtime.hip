@@ -98,39 +98,6 @@ void stage_release(void *p) {
     P.free_blocks.push_back(p);
 }
 
-namespace {
-struct SideStreams {
-    std::vector<SideStream> per_dev;  // index: device; s == nullptr until created
-    ~SideStreams() {
-        for (auto &x : per_dev) {
-            if (!x.s) continue;
-            (void)hipStreamSynchronize(x.s);
-            (void)hipEventDestroy(x.ev[0]);
-            (void)hipEventDestroy(x.ev[1]);
-            (void)hipStreamDestroy(x.s);
-        }
-    }
-};
-thread_local SideStreams t_side;
-thread_local bool t_side_on = true;
-}  // namespace
-
-void set_side_streams(bool on) { t_side_on = on; }
-bool side_streams_on() { return t_side_on; }
-
-SideStream &side_stream() {
-    int dev = 0;
-    SJ_HIP(hipGetDevice(&dev));
-    if (static_cast<size_t>(dev) >= t_side.per_dev.size()) t_side.per_dev.resize(dev + 1, SideStream{nullptr, {}});
-    SideStream &x = t_side.per_dev[dev];
-    if (!x.s) {
-        SJ_HIP(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
-        SJ_HIP(hipEventCreateWithFlags(&x.ev[0], hipEventDisableTiming));
-        SJ_HIP(hipEventCreateWithFlags(&x.ev[1], hipEventDisableTiming));
-    }
-    return x;
-}
-
 void *dev_alloc(size_t bytes) {
     int dev = 0;
     SJ_HIP(hipGetDevice(&dev));

@@ -203,7 +203,6 @@ void run_request(sj_server *S, Request *r, uint32_t slot, hipStream_t stream) {
 }
 
 void worker(sj_server *S, uint32_t slot) {
-    sj::set_side_streams(false);  // requests already overlap on the workers' streams
     const bool dry = (S->opts.flags & SJ_SERVER_DRY_RUN) != 0;
     hipStream_t stream = nullptr;
     if (!dry && hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return;
