@@ -223,9 +223,40 @@ def test_invalid_inputs(sj):
     ix.close()
 
 
+@pytest.mark.parametrize("d", range(1, 9))
+def test_bbox_every_dimension_count(sj, d):
+    # The bounding-box pass is compiled per dimension count, and with more
+    # than four grid strides of points (1024 workgroups x 256) each thread
+    # loads four points before folding them in: 1.1M points exercise both
+    # that loop and the remainder loop. Exact min and the cell counts that
+    # follow from the max; then a non-finite value in the last coordinate,
+    # once in each loop, must be rejected.
+    n = 1_100_000
+    pts = datagen.uniform(n, d, seed=40 + d)
+    _say(f"bbox d={d} n={n}")
+    x = torch.from_numpy(pts).cuda()
+    with sj.Index(x, 3.0) as ix:
+        grid = ix.export(sj._lib.SJ_EXPORT_GRID)
+        lo, hi = pts.min(axis=0), pts.max(axis=0)
+        w = grid[16]
+        # the grid of Section IV-B as the index lays it out: one spare cell
+        # below the minimum, floor((max - g_min) / w) + 2 cells per dimension
+        gmin = lo - w
+        np.testing.assert_array_equal(grid[:d], gmin)
+        np.testing.assert_array_equal(grid[8:8 + d].astype(np.int64), (np.floor((hi - gmin) / w) + 2).astype(np.int64))
+    for pos, bad in ((1_050_000, np.nan), (1_099_999, np.inf), (1_050_000, -np.inf)):
+        y = pts.copy()
+        y[pos, d - 1] = bad
+        with pytest.raises(sj.SjError, match="NaN"):
+            sj.selfjoin(torch.from_numpy(y).cuda(), 3.0)
+
+
 # --------------------------------------------------------- index parity
 @pytest.mark.parametrize("kind,d,n,eps", [("uniform", 2, 30011, 0.5), ("clustered", 3, 20011, 0.8),
-                                          ("uniform", 6, 10007, 25.0), ("uniform", 2, 5000, 1e-3)])
+                                          ("uniform", 6, 10007, 25.0), ("uniform", 2, 5000, 1e-3),
+                                          ("uniform", 1, 20011, 0.01), ("clustered", 4, 12007, 2.0),
+                                          ("uniform", 5, 9001, 20.0), ("uniform", 7, 6007, 40.0),
+                                          ("clustered", 8, 5003, 6.0)])
 def test_index_matches_grid_oracle(sj, kind, d, n, eps):
     _say(f"index {kind} d={d} n={n} eps={eps}")
     pts = datagen.make(kind, n, d, seed=77)
