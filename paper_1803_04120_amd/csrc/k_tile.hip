@@ -157,7 +157,8 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         // the staged ids, h the test result). The fused fill stores every
         // candidate into the lane's LDS slot -- hits at the row position,
         // misses into the slot's spare last word -- so the common path has
-        // no branch; rows that do not fit the slot also go to out_j.
+        // no branch; a row longer than the slot keeps its first entries there
+        // and writes the rest to out_j.
         auto emit = [&](bool h, uint32_t i, uint32_t q, uint32_t id, bool mirror) {
             if (kMode == kCount) {
                 own += h ? 1u : 0u;
@@ -165,8 +166,9 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             } else if (NS > 0) {
                 const uint32_t slot = own < static_cast<uint32_t>(NS) ? own : static_cast<uint32_t>(NS);
                 srow[h ? slot : static_cast<uint32_t>(NS)] = id;
-                if (h && !row_in_lds) {
-                    // a row that disagrees with its count is caught at the end
+                if (h && own >= static_cast<uint32_t>(NS)) {
+                    // past the slot: at its place in the row in out_j (a row
+                    // that disagrees with its count is caught at the end)
                     const uint64_t at = my_row + own;
                     a.out_j[at < a.out_cap ? at : a.out_cap - 1] = id;
                 }
@@ -411,6 +413,15 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             // rows longer than the slot but at most 64 long: in out_j (written
             // above by this wave); sorted four at a time, one row per 16-lane
             // group with 4 entries per lane
+            // a row longer than 64 is sorted by the row-sort kernels, from
+            // out_j: its first NS entries join the rest there
+            if (active && !row_in_lds && row_len > 64u) {
+                const uint32_t m = own < static_cast<uint32_t>(NS) ? own : static_cast<uint32_t>(NS);
+                for (uint32_t e = 0; e < m; ++e) {
+                    const uint64_t at = my_row + e;
+                    a.out_j[at < a.out_cap ? at : a.out_cap - 1] = srow[e];
+                }
+            }
             uint64_t longm = ballot(active && !row_in_lds && row_len <= 64u);
             if (longm) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // own stores before own loads
             const uint32_t grp = static_cast<uint32_t>(lane) >> 4, gl = static_cast<uint32_t>(lane) & 15u;
@@ -438,7 +449,9 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const uint32_t e = static_cast<uint32_t>(k) * 16 + gl;
-                    v[k] = e < rl ? a.out_j[src + e] : 0xffffffffu;
+                    // the first NS entries in the row's LDS slot, the rest in out_j
+                    v[k] = e < rl ? (e < static_cast<uint32_t>(NS) ? srows[src_lane * kRowStride + e] : a.out_j[src + e])
+                                  : 0xffffffffu;
                 }
                 group16_bitonic64(v);
 #pragma unroll
