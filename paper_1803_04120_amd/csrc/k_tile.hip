@@ -328,9 +328,11 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         while (cur.valid) {
             const uint32_t len = (cur.P1 - cur.T0) < static_cast<uint32_t>(TS) ? (cur.P1 - cur.T0) : TS;
             wave_sync_lds();
-            // stage the tile straight from memory (holding a prefetched next
-            // tile in registers was measured slower: it costs waves per SIMD,
-            // and the unicomp count would wait on its own atomics for it)
+            // stage the tile straight from memory. Holding the next tile in
+            // registers while this one is evaluated was measured: no faster
+            // for the fused fill or the full count, slower for the unicomp
+            // count (its loads wait behind the flush atomics) and from 4-D on
+            // (the registers cost waves per SIMD).
             for (uint32_t i = lane; i < len; i += 64) {
                 const size_t q = cur.T0 + i;
 #pragma unroll
