@@ -344,13 +344,16 @@ def main():
         raise RuntimeError(f"no modelled kernel among {sorted(all_prof)}")
     dom = max(first, key=lambda k: first[k][1])
     # timed region: HIP events (on the launch stream) only around the
-    # dominant kernel; events around every launch would slow the step
+    # dominant kernel's launches of the last timed step. A timing event
+    # costs the stream about 24 us of idle time (measured in the kernel
+    # trace), so timing every launch of every step would slow the steps.
     _lib.profile_select(dom)
-    _lib.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     pairs_total = 0
-    for _ in range(args.steps):
+    for k in range(args.steps):
+        if k == args.steps - 1:
+            _lib.profile_enable(True)
         pairs_total += step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -362,7 +365,7 @@ def main():
     log(f"[bench] {args.steps} steps in {dt:.3f}s, {ms_per_step:.3f} ms/step, {value:.4g} pairs/s")
 
     # roofline of the dominant kernel, from the timed region's events
-    modelled = modelled_of(prof, args.steps)
+    modelled = modelled_of(prof, 1)
     if dom not in modelled:
         raise RuntimeError(f"the timed region recorded no launch of {dom}")
     cnt, ms, byts = modelled[dom]
@@ -416,11 +419,12 @@ def main():
             return total
         step_band()
         torch.cuda.synchronize()
-        _lib.profile_select("tiled_fill")
-        _lib.profile_enable(True)
+        _lib.profile_select("tiled_fill")  # events on the last step's fill launches only
         t0 = time.perf_counter()
         bp = 0
-        for _ in range(args.steps):
+        for k in range(args.steps):
+            if k == args.steps - 1:
+                _lib.profile_enable(True)
             bp += step_band()
         torch.cuda.synchronize()
         bdt = time.perf_counter() - t0
@@ -429,11 +433,11 @@ def main():
         bprof = _lib.profile_read()
         fills = {k: v for k, v in bprof.items() if k.startswith("tiled_fill")}
         band = {"pairs_per_s": bp / bdt, "ms_per_step": 1e3 * bdt / args.steps,
-                "vs_fp64": (bp / bdt) / value, "kernels_ms": {k: round(v[1] / args.steps, 4) for k, v in bprof.items()}}
+                "vs_fp64": (bp / bdt) / value, "kernels_ms": {k: round(v[1], 4) for k, v in bprof.items()}}
         if fills:
             fk = max(fills, key=lambda k: fills[k][1])
             cnt, ms = fills[fk]
-            byts = sum(kernel_bytes(fk, n, d, i["cells"], i["ranges"], i["pairs"]) for i in info) * args.steps
+            byts = sum(kernel_bytes(fk, n, d, i["cells"], i["ranges"], i["pairs"]) for i in info)
             ach = byts / (ms * 1e-3) / 1e9
             band["roofline"] = {"kernel": fk, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_us": round(1e3 * ms / cnt, 3)}
