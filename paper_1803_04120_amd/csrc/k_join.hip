@@ -467,7 +467,8 @@ __global__ __launch_bounds__(256) void k_count_summary(const uint64_t *__restric
                                                         const uint32_t *__restrict__ max_len,
                                                         const unsigned long long *__restrict__ counters,
                                                         const uint32_t *__restrict__ nchunks,
-                                                        uint64_t *__restrict__ out) {
+                                                        uint64_t *__restrict__ out,
+                                                        uint32_t *__restrict__ overflow) {
     __shared__ unsigned long long part[6][256 / 64];
     const int k = threadIdx.x;  // one counter slot and two row-stat blocks per thread
     unsigned long long e = counters[static_cast<size_t>(k) * kCounterStride];
@@ -516,14 +517,15 @@ __global__ __launch_bounds__(256) void k_count_summary(const uint64_t *__restric
         out[2] = se;
         out[3] = sb;
         out[4] = nchunks ? *nchunks : 0;
+        if (overflow) *overflow = 0;  // the fill's overflow flag starts clear
     }
 }
 
 void launch_count_summary(const uint64_t *off_orig, uint64_t n, const uint32_t *max_len,
                           const unsigned long long *counters, const uint32_t *nchunks, uint64_t *out,
-                          hipStream_t s) {
+                          uint32_t *overflow, hipStream_t s) {
     static_assert(kCounterSlots == 256, "one thread per counter slot");
-    k_count_summary<<<1, 256, 0, s>>>(off_orig, n, max_len, counters, nchunks, out);
+    k_count_summary<<<1, 256, 0, s>>>(off_orig, n, max_len, counters, nchunks, out, overflow);
     SJ_LAUNCH_CHECK();
 }
 

@@ -155,6 +155,7 @@ struct sj_index {
     DevBuf<unsigned long long> counters;  // evals, band rechecks
     DevBuf<uint32_t> max_len;
     DevBuf<uint32_t> overflow;
+    bool overflow_clear = false;  // the device flag is known to be 0
     DevBuf<uint64_t> summary;  // count pass results read back together
     uint64_t pairs = 0;
     uint32_t max_row = 0;
@@ -493,8 +494,9 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
                            ix.len_orig.ptr, ix.len_cell.ptr, ix.max_len.ptr, s);
     sj::scan_exclusive_u32_to_u64_x2(ix.len_orig.ptr, ix.off_orig.ptr, ix.len_cell.ptr, ix.off_cell.ptr, n, s);
     ix.summary.ensure(8);
+    ix.overflow.ensure(1);
     sj::launch_count_summary(ix.off_orig.ptr, n, ix.max_len.ptr, ix.counters.ptr,
-                             tiled ? ix.nchunks_dev.ptr : nullptr, ix.summary.ptr, s);
+                             tiled ? ix.nchunks_dev.ptr : nullptr, ix.summary.ptr, ix.overflow.ptr, s);
     sj::HostStage hs;
     SJ_HIP(hipMemcpyAsync(hs.p, ix.summary.ptr, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
@@ -508,6 +510,7 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     ix.stats.pairs = ix.pairs;
     ix.stats.max_row_pairs = ix.max_row;
     ix.stats.ranges = tiled ? 0 : ix.ranges[uni].count;
+    ix.overflow_clear = true;
     ix.counted = true;
     ix.stats.ms_count = now_ms() - t0;
 }
@@ -517,6 +520,7 @@ void check_overflow(sj_index &ix, hipStream_t s) {
     SJ_HIP(hipMemcpyAsync(hs.p, ix.overflow.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
     if (*hs.as<uint32_t>()) throw Error(SJ_EDEVICE, "internal: the fill pass disagreed with the count pass");
+    ix.overflow_clear = true;
 }
 
 // Fill + row sort of result rows [i0, i1) into out_j / pairs (batch-relative).
@@ -570,7 +574,8 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
             a.off_orig = ix.off_orig.ptr;
             a.pairs = reinterpret_cast<uint2 *>(pairs);
         }
-        if (whole) sj::launch_fill_u32(a.overflow, 1, 0u, s);
+        if (whole && !ix.overflow_clear) sj::launch_fill_u32(a.overflow, 1, 0u, s);
+        ix.overflow_clear = false;
         sj::launch_join_tiled(a, tile_args(ix), ix.d, mode, sj::kFill, ix.band_used, s, ns);
         if (fused) {
             // the fused fill sorts rows of up to 64 itself
@@ -579,11 +584,12 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
             return;
         }
     } else if (unicomp_fill) {
-        if (whole) sj::launch_fill_u32(a.overflow, 1, 0u, s);
+        if (whole && !ix.overflow_clear) sj::launch_fill_u32(a.overflow, 1, 0u, s);
+        ix.overflow_clear = false;
         sj::launch_join(a, ix.d, 1, sj::kFill, ix.band_used, s);
     } else {
         if (whole) {
-            sj::launch_fill_u32(a.overflow, 1, 0u, s);
+            if (!ix.overflow_clear) sj::launch_fill_u32(a.overflow, 1, 0u, s);
             a.qlist = nullptr;
             a.nq = static_cast<uint32_t>(n);
         } else {
@@ -592,6 +598,7 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
             a.nq = sj::build_query_list(ix.perm.ptr, n, i0, i1, sc.flags.ptr, sc.qlist.ptr, s);
             a.qlist = sc.qlist.ptr;
         }
+        ix.overflow_clear = false;
         sj::launch_join(a, ix.d, 0, sj::kFill, ix.band_used, s);
     }
     if (whole)
@@ -693,6 +700,7 @@ int join_batched(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
     };
     ix.overflow.ensure(1);
     sj::launch_fill_u32(ix.overflow.ptr, 1, 0u, s);
+    ix.overflow_clear = false;
     for (uint32_t b = 0; b < nb && rc == 0; ++b) {
         const int k = b & 1;
         if (offs[b + 1] > offs[b])

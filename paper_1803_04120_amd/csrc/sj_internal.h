@@ -219,10 +219,11 @@ void launch_row_lengths(const uint32_t *own_cnt, const uint32_t *in_cnt, const u
                         hipStream_t s);
 // Gathers the count pass results into out[0..8): P, longest row,
 // evaluations, band re-checks, chunk count (nchunks may be null), rows
-// longer than 16, 24, 32 (max_len = the row_stats of launch_row_lengths).
+// longer than 16, 24, 32 (max_len = the row_stats of launch_row_lengths);
+// also clears the fill's overflow flag (may be null).
 void launch_count_summary(const uint64_t *off_orig, uint64_t n, const uint32_t *max_len,
                           const unsigned long long *counters, const uint32_t *nchunks, uint64_t *out,
-                          hipStream_t s);
+                          uint32_t *overflow, hipStream_t s);
 void launch_gather_offsets(const uint64_t *off_orig, const uint32_t *perm, uint64_t n,
                            uint64_t *offc, hipStream_t s);
 // cell-ordered points whose original id lies in [i0, i1), in cell order.
