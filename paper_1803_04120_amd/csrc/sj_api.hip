@@ -251,6 +251,18 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
     sj::launch_bbox(dp, n, d, bb.ptr, reinterpret_cast<uint32_t *>(bb.ptr + 2 * sj::kMaxDim), s);
     sj::HostStage hs;
     SJ_HIP(hipMemcpyAsync(hs.p, bb.ptr, bb.bytes(), hipMemcpyDeviceToHost, s));
+    // the buffers whose sizes depend only on n and d are taken from the pool
+    // while the bounding box runs (32-bit cell ids use the first half of the
+    // 64-bit key buffers)
+    ix.perm.reset(n);
+    DevBuf<uint32_t> ids_alt(n);
+    ix.cell_of.reset(n);
+    ix.B.reset(n);
+    ix.starts.reset(n + 1);
+    DevBuf<uint64_t> keys64(n), keys64_alt(n);
+    ix.coords.reset(n * d);
+    ix.X.reset(n * d);
+    ix.cx.reset(n);
     SJ_HIP(hipStreamSynchronize(s));
     const double *hb = hs.as<double>();
     if (*reinterpret_cast<const uint32_t *>(hb + 2 * sj::kMaxDim)) throw Error(SJ_EINVAL, "coordinates contain NaN or Inf");
@@ -260,27 +272,23 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
     }
     compute_grid(ix);
     // cell ids and the sort by cell (A)
-    ix.perm.reset(n);
-    DevBuf<uint32_t> ids_alt(n);
-    ix.cell_of.reset(n);
-    ix.B.reset(n);
-    ix.starts.reset(n + 1);
     if (ix.key_bits <= 32) {
-        DevBuf<uint32_t> keys(n), keys_alt(n);
-        sj::launch_cell_keys_u32(dp, n, ix.grid, keys.ptr, ix.perm.ptr, s);
-        if (sj::radix_sort_u32(keys.ptr, ix.perm.ptr, keys_alt.ptr, ids_alt.ptr, n, ix.key_bits, s)) {
+        uint32_t *keys = reinterpret_cast<uint32_t *>(keys64.ptr);
+        uint32_t *keys_alt = reinterpret_cast<uint32_t *>(keys64_alt.ptr);
+        sj::launch_cell_keys_u32(dp, n, ix.grid, keys, ix.perm.ptr, s);
+        if (sj::radix_sort_u32(keys, ix.perm.ptr, keys_alt, ids_alt.ptr, n, ix.key_bits, s)) {
             std::swap(keys, keys_alt);
             std::swap(ix.perm, ids_alt);
         }
-        sj::build_cells<uint32_t>(keys.ptr, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
+        sj::build_cells<uint32_t>(keys, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
     } else {
-        DevBuf<uint64_t> keys(n), keys_alt(n);
-        sj::launch_cell_keys_u64(dp, n, ix.grid, keys.ptr, ix.perm.ptr, s);
-        if (sj::radix_sort_u64(keys.ptr, ix.perm.ptr, keys_alt.ptr, ids_alt.ptr, n, ix.key_bits, s)) {
+        uint64_t *keys = keys64.ptr, *keys_alt = keys64_alt.ptr;
+        sj::launch_cell_keys_u64(dp, n, ix.grid, keys, ix.perm.ptr, s);
+        if (sj::radix_sort_u64(keys, ix.perm.ptr, keys_alt, ids_alt.ptr, n, ix.key_bits, s)) {
             std::swap(keys, keys_alt);
             std::swap(ix.perm, ids_alt);
         }
-        sj::build_cells<uint64_t>(keys.ptr, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
+        sj::build_cells<uint64_t>(keys, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
     }
     // per-cell coordinates and occupancy masks M_j (Section IV-C)
     uint64_t words = 0;
@@ -298,13 +306,10 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
     }
     // |G| stays on the device until the end of the build: tables that depend
     // on it are sized by n (an upper bound)
-    ix.coords.reset(n * d);
     ix.max_cell_dev.ensure(1);
     sj::launch_cell_coords_masks(ix.B.ptr, ix.starts.ptr, n, ix.cell_of.ptr + (n - 1), ix.grid, ix.coords.ptr,
                                  ix.masks.ptr, moff, ix.mask_words, ix.max_cell_dev.ptr, s);
     // cell-ordered structure of arrays
-    ix.X.reset(n * d);
-    ix.cx.reset(n);
     sj::launch_gather_soa(dp, ix.perm.ptr, n, d, ix.X.ptr, ix.grid, ix.cx.ptr, s);
     for (uint32_t j = 0; j < d; ++j) {
         ix.shift[j] = 0.5 * (ix.bmin[j] + ix.bmax[j]);
