@@ -112,6 +112,31 @@ def test_fused_fill_slot_sizes(sj, monkeypatch, slot, kind, d, n, eps):
     assert_same(gpu_pairs(sj, pts, eps, unicomp=False), want, f"slot {slot} {kind}-{d}d")
 
 
+@pytest.mark.parametrize("slot", ["16", "24", "32"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_fused_fill_row_lengths_at_every_boundary(sj, monkeypatch, slot, d):
+    """Groups of k coincident points, far apart, give rows of exactly k
+    entries: k at and around the slot size (kept in the slot / first entries
+    in the slot and the rest spilled), around 64 (sorted by the wave / by the
+    row-sort kernels after the slot entries are copied out) and beyond."""
+    monkeypatch.setenv("SJ_FUSED_NS", slot)
+    ks = [1, 2, 15, 16, 17, 23, 24, 25, 31, 32, 33, 63, 64, 65, 66, 100, 129]
+    rng = np.random.default_rng(77 + d)
+    groups = []
+    for g, k in enumerate(ks):
+        centre = np.zeros(d)
+        centre[0] = 10.0 * g
+        centre[1] = 5.0 * (g % 3)
+        groups.append(np.repeat(centre[None, :], k, axis=0))
+    pts = np.concatenate(groups)
+    pts = pts[rng.permutation(len(pts))]  # rows in random original order
+    _say(f"row-length boundaries slot {slot} d={d} n={len(pts)}")
+    want = ref.pairs(pts, 0.5)
+    lens = np.bincount(want[:, 0], minlength=len(pts))
+    assert sorted(set(lens.tolist())) == sorted(set(ks))
+    assert_same(gpu_pairs(sj, pts, 0.5, unicomp=False), want, f"row boundaries slot {slot} d={d}")
+
+
 @pytest.mark.parametrize("fused", ["0", "1"])
 @pytest.mark.parametrize("kind,d,n,eps", [("uniform", 4, 12007, 14.0), ("clustered", 5, 9001, 3.0),
                                           ("uniform", 2, 20011, 1.5)])
