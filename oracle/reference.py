@@ -23,6 +23,9 @@ Three independent spellings are provided:
   * pairs_numpy:  numpy, vectorised over candidates (small inputs);
   * pairs / count_rows / rows_pairs: the C brute force in sj_oracle.c
     (OpenMP), for anything bigger.
+
+join_rs_numpy is the same predicate between two sets, R x S (the join the
+self-join specialises, Section II), for the two-set join to come.
 """
 from __future__ import annotations
 
@@ -191,3 +194,31 @@ def grid_join(points, eps: float, with_pairs: bool = True):
     if got != total:
         raise RuntimeError("grid join: count and fill disagree")
     return counts, out
+
+
+# --------------------------------------------------------------------------
+# distance join of two sets (the operation the self-join specialises)
+# --------------------------------------------------------------------------
+def join_rs_numpy(r_points, s_points, eps: float) -> np.ndarray:
+    """Sorted (i, j) pairs, i a row of R and j a row of S, with the same
+    predicate as the self-join (d2 in binary64, dimension order 0..d-1, each
+    operation rounded, d2 <= fl(eps * eps)). Section II places the self-join
+    as the special case R = S of this join; Section III gives the predicate.
+    Vectorised over the rows of S (small inputs)."""
+    r = _as_points(r_points)
+    s = _as_points(s_points)
+    if r.shape[0] and s.shape[0] and r.shape[1] != s.shape[1]:
+        raise ValueError("R and S must have the same dimension")
+    eps2 = float(eps) * float(eps)
+    rows = []
+    for i in range(r.shape[0]):
+        acc = np.zeros(s.shape[0], dtype=np.float64)
+        for k in range(r.shape[1]):
+            t = r[i, k] - s[:, k]
+            acc = acc + t * t
+        js = np.nonzero(acc <= eps2)[0]
+        rows.append(np.stack([np.full(js.shape, i, dtype=np.int64), js.astype(np.int64)], axis=1))
+    if not rows:
+        return np.zeros((0, 2), dtype=np.int64)
+    return np.concatenate(rows, axis=0)
+

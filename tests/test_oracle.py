@@ -227,3 +227,38 @@ def test_cpu_grid_join_lattice_boundaries():
         _, got = ref.grid_join(g, 1.0)
         assert np.array_equal(got.astype(np.int64), ref.pairs(g, 1.0))
         assert got.shape[0] == g.shape[0] * (1 + 2 * d) - 2 * d * 6 ** (d - 1)
+
+
+# ------------------------------------------------ distance join of two sets
+def test_join_rs_hand_example():
+    """R = {(0,0), (3,4)}, S = {(0,1), (3,0), (6,8)}, eps = 5: squared
+    distances 1, 9, 100 from the first query and 18, 16, 25 from the second;
+    25 sits exactly on eps^2 and is included."""
+    R = np.array([[0.0, 0.0], [3.0, 4.0]])
+    S = np.array([[0.0, 1.0], [3.0, 0.0], [6.0, 8.0]])
+    got = ref.join_rs_numpy(R, S, 5.0)
+    np.testing.assert_array_equal(got, np.array([[0, 0], [0, 1], [1, 0], [1, 1], [1, 2]]))
+
+
+def test_join_rs_special_cases():
+    pts = datagen.uniform(700, 3, seed=41)
+    # R = S is the self-join (the C brute force, an independent spelling)
+    np.testing.assert_array_equal(ref.join_rs_numpy(pts, pts, 6.0), ref.pairs(pts, 6.0))
+    # swapping the sets transposes every pair
+    R, S = pts[:300], pts[300:]
+    a = ref.join_rs_numpy(R, S, 7.0)
+    b = ref.join_rs_numpy(S, R, 7.0)
+    assert a.shape[0] > 0
+    np.testing.assert_array_equal(sorted_pairs(b[:, ::-1]), a)
+    # empty sides
+    assert ref.join_rs_numpy(R[:0], S, 7.0).shape == (0, 2)
+    assert ref.join_rs_numpy(R, S[:0], 7.0).shape == (0, 2)
+
+
+def test_join_rs_against_scipy_kdtree():
+    scipy_spatial = pytest.importorskip("scipy.spatial")
+    R = datagen.uniform(1500, 2, seed=42)
+    S = datagen.uniform(2500, 2, seed=43)
+    want = scipy_spatial.cKDTree(R).query_ball_tree(scipy_spatial.cKDTree(S), r=1.5, p=2.0)
+    expect = np.array(sorted((i, j) for i, js in enumerate(want) for j in js), dtype=np.int64).reshape(-1, 2)
+    np.testing.assert_array_equal(ref.join_rs_numpy(R, S, 1.5), expect)
