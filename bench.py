@@ -440,7 +440,8 @@ def main():
             byts = sum(kernel_bytes(fk, n, d, i["cells"], i["ranges"], i["pairs"]) for i in info)
             ach = byts / (ms * 1e-3) / 1e9
             band["roofline"] = {"kernel": fk, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_us": round(1e3 * ms / cnt, 3)}
+                                "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_us": round(1e3 * ms / cnt, 3),
+                                "traffic": measured_traffic(fk, args.workload)}
         log(f"[bench] fp32+band: {band['pairs_per_s']:.4g} pairs/s ({band['vs_fp64']:.3f} x fp64)")
 
     serving = None
