@@ -129,6 +129,22 @@ int sj_join_fill(sj_index *idx, uint32_t *pairs_dev, uint64_t capacity_pairs,
                  void *stream);
 
 /*
+ * Distance join of a query set R with the indexed set S (Section II: the
+ * self-join is the case R = S; the pair test is Section III's, as for the
+ * self-join). R is nr x d row-major FP64 with the index's d, in device
+ * memory if r_on_device else host memory, owned by the caller and not
+ * retained. Result: every (i, j) with i a row of R and j a row of S within
+ * eps (the index's), as interleaved uint32 pairs sorted by (i, j).
+ * *total_pairs receives P. If pairs_dev is NULL only P is computed;
+ * otherwise capacity_pairs must be at least P (else SJ_ECAPACITY, with
+ * *total_pairs set and nothing written). Queries outside S's bounding box
+ * are allowed (they probe only the cells that exist). Independent of the
+ * self-join state of the index (count/fill).
+ */
+int sj_join_rs(sj_index *idx, const double *R, uint64_t nr, int r_on_device, uint32_t *pairs_dev,
+               uint64_t capacity_pairs, void *stream, uint64_t *total_pairs);
+
+/*
  * Batched join (Section V-A). The result rows are split into at least
  * opts->min_batches consecutive ranges of i, each holding at most
  * opts->batch_capacity_pairs pairs; every batch is delivered, in order of i,

@@ -96,6 +96,30 @@ class Index:
                                   P, _stream_handle(self._stream)))
         return out[:P] if out.shape[0] != P else out
 
+    def join_rs(self, queries, out=None):
+        """Distance join of the query rows (float64 (nr, d), host or device)
+        with the indexed set: (P, 2) int32 device tensor of (query row,
+        indexed row) pairs sorted by (i, j), at the index's eps."""
+        torch = _torch()
+        L = _lib.load()
+        ptr, nr, d, on_dev, keep = _points_arg(queries)
+        if nr and d != self.d:
+            raise ValueError(f"queries have {d} dimensions, the index {self.d}")
+        total = ctypes.c_uint64(0)
+        _lib.check(L.sj_join_rs(self._h, ptr, nr, on_dev, None, 0, _stream_handle(self._stream),
+                                ctypes.byref(total)))
+        P = int(total.value)
+        if out is None:
+            dev = self._device or torch.device("cuda")
+            out = torch.empty((P, 2), dtype=torch.int32, device=dev)
+        if out.dtype != torch.int32 or not out.is_contiguous() or out.numel() < 2 * P:
+            raise ValueError("out must be a contiguous int32 tensor with room for P pairs")
+        if P:
+            _lib.check(L.sj_join_rs(self._h, ptr, nr, on_dev, ctypes.c_void_p(out.data_ptr()), P,
+                                    _stream_handle(self._stream), ctypes.byref(total)))
+        del keep
+        return out[:P] if out.shape[0] != P else out
+
     def join(self, unicomp: bool = True, precision: str = "fp64"):
         self.count(unicomp, precision)
         return self.fill()

@@ -1,0 +1,156 @@
+// Distance join of a query set R with an indexed set S (the self-join is the
+// case R = S, Section II). Each query row takes its cell in S's grid without
+// clamping -- a query outside S's bounding box probes only the part of its
+// 3^d neighbourhood that lies inside the grid -- and tests the points of
+// those cells with the self-join's predicate (Section III: squared distance
+// in binary64, dimension order 0..d-1, no fused multiply-add, d2 <= eps^2).
+// Dimension 0 varies fastest in the linear cell id, so the cells of one
+// neighbourhood row are consecutive ids: one lower bound in B per row.
+#include "sj_internal.h"
+#include "sj_device.h"
+
+namespace sj {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint32_t rs_lower_bound(const uint64_t *__restrict__ B, uint32_t n, uint64_t key) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (B[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// kMode 0: per-query counts; 1: neighbour ids (S's original rows) into
+// out_j[off[r] ...], in probe order (sorted afterwards).
+template <int D, int kMode>
+__global__ __launch_bounds__(kThreads) void k_join_rs(RsArgs a) {
+    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (r >= a.nr) return;
+    double q[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) q[j] = a.R[r * D + j];
+    // neighbourhood box [lo_j, hi_j] of existing cells
+    int64_t lo[D], hi[D];
+    bool any = a.ncells > 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const double t = floor((q[j] - a.g.gmin[j]) / a.g.w);
+        const double top = static_cast<double>(a.g.dims[j]);
+        if (!(t >= -1.0) || !(t <= top)) {  // NaN, or more than one cell outside
+            any = false;
+            lo[j] = 0;
+            hi[j] = -1;
+            continue;
+        }
+        const int64_t c = static_cast<int64_t>(t);
+        lo[j] = c - 1 > 0 ? c - 1 : 0;
+        hi[j] = c + 1 < static_cast<int64_t>(a.g.dims[j]) - 1 ? c + 1 : static_cast<int64_t>(a.g.dims[j]) - 1;
+        if (lo[j] > hi[j]) any = false;
+    }
+    uint32_t found = 0;
+    uint64_t at = kMode == 1 ? a.off[r] : 0;
+    if (any) {
+        // odometer over dimensions 1..d-1; dimension 0 is the id range
+        int64_t o[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) o[j] = lo[j];
+        while (true) {
+            uint64_t base = 0;
+#pragma unroll
+            for (int j = 1; j < D; ++j) base += static_cast<uint64_t>(o[j]) * a.g.stride[j];
+            const uint64_t k0 = base + static_cast<uint64_t>(lo[0]), k1 = base + static_cast<uint64_t>(hi[0]);
+            uint32_t h = rs_lower_bound(a.B, a.ncells, k0);
+            if (h < a.ncells && a.B[h] <= k1) {
+                uint32_t he = h;
+                while (he + 1 < a.ncells && a.B[he + 1] <= k1) ++he;
+                const uint32_t p0 = a.starts[h], p1 = a.starts[he + 1];
+                for (uint32_t p = p0; p < p1; ++p) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        const double t = __dsub_rn(q[j], a.X[static_cast<size_t>(j) * a.ns + p]);
+                        acc = __dadd_rn(acc, __dmul_rn(t, t));
+                    }
+                    if (acc <= a.eps2) {
+                        if (kMode == 1) {
+                            if (at < a.out_cap)
+                                a.out_j[at] = a.perm[p];
+                            else
+                                atomicOr(a.overflow, 1u);
+                            ++at;
+                        }
+                        ++found;
+                    }
+                }
+            }
+            int j = 1;
+            while (j < D && o[j] == hi[j]) {
+                o[j] = lo[j];
+                ++j;
+            }
+            if (j >= D) break;
+            ++o[j];
+        }
+    }
+    if (kMode == 0) {
+        a.count[r] = found;
+    } else if (at != a.off[r + 1]) {
+        atomicOr(a.overflow, 1u);  // the fill disagrees with the count
+    }
+}
+
+// out[0] = max over counts[0..n); out must be 0 on entry.
+__global__ __launch_bounds__(kThreads) void k_rs_max(const uint32_t *__restrict__ counts, uint64_t n,
+                                                      uint32_t *__restrict__ out) {
+    uint32_t m = 0;
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kThreads)
+        m = counts[i] > m ? counts[i] : m;
+    m = wave_max(m);
+    if (lane_id() == 0 && m) atomicMax(out, m);
+}
+
+template <int D>
+void launch_rs_d(const RsArgs &a, int mode, hipStream_t s) {
+    const unsigned nb = static_cast<unsigned>((a.nr + kThreads - 1) / kThreads);
+    if (mode == 0) {
+        KTimer kt_("rs_count", s);
+        k_join_rs<D, 0><<<nb, kThreads, 0, s>>>(a);
+    } else {
+        KTimer kt_("rs_fill", s);
+        k_join_rs<D, 1><<<nb, kThreads, 0, s>>>(a);
+    }
+    SJ_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void launch_join_rs(const RsArgs &a, int mode, hipStream_t s) {
+    if (a.nr == 0) return;
+    switch (a.g.d) {
+        case 1: launch_rs_d<1>(a, mode, s); break;
+        case 2: launch_rs_d<2>(a, mode, s); break;
+        case 3: launch_rs_d<3>(a, mode, s); break;
+        case 4: launch_rs_d<4>(a, mode, s); break;
+        case 5: launch_rs_d<5>(a, mode, s); break;
+        case 6: launch_rs_d<6>(a, mode, s); break;
+        case 7: launch_rs_d<7>(a, mode, s); break;
+        case 8: launch_rs_d<8>(a, mode, s); break;
+        default: throw Error(SJ_EINVAL, "two-set join: dimension out of range");
+    }
+}
+
+void launch_rs_max(const uint32_t *counts, uint64_t n, uint32_t *out, hipStream_t s) {
+    if (n == 0) return;
+    const unsigned nb = static_cast<unsigned>(std::min<uint64_t>(512, (n + kThreads - 1) / kThreads));
+    k_rs_max<<<nb, kThreads, 0, s>>>(counts, n, out);
+    SJ_LAUNCH_CHECK();
+}
+
+}  // namespace sj

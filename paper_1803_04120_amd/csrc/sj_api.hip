@@ -793,6 +793,69 @@ int sj_join_fill(sj_index *idx, uint32_t *pairs_dev, uint64_t capacity_pairs, vo
     });
 }
 
+int sj_join_rs(sj_index *idx, const double *R, uint64_t nr, int r_on_device, uint32_t *pairs_dev,
+               uint64_t capacity_pairs, void *stream, uint64_t *total_pairs) {
+    hipStream_t s = as_stream(stream);
+    return guarded(s, [&] {
+        if (!idx) throw Error(SJ_EINVAL, "index is NULL");
+        if (nr && !R) throw Error(SJ_EINVAL, "R is NULL");
+        if (nr >= 0x7fffffffULL) throw Error(SJ_EINVAL, "too many query rows");
+        sj_index &ix = *idx;
+        if (total_pairs) *total_pairs = 0;
+        if (nr == 0 || ix.n == 0) return;
+        const uint32_t d = ix.d;
+        DevBuf<double> staged;
+        const double *rp = R;
+        if (!r_on_device) {
+            staged.reset(nr * d);
+            SJ_HIP(hipMemcpyAsync(staged.ptr, R, nr * d * sizeof(double), hipMemcpyHostToDevice, s));
+            rp = staged.ptr;
+        }
+        sj::RsArgs a{};
+        a.R = rp;
+        a.nr = nr;
+        a.X = ix.X.ptr;
+        a.ns = ix.n;
+        a.perm = ix.perm.ptr;
+        a.B = ix.B.ptr;
+        a.starts = ix.starts.ptr;
+        a.ncells = static_cast<uint32_t>(ix.ncells);
+        a.g = ix.grid;
+        a.eps2 = ix.eps * ix.eps;
+        // count pass, row offsets in R's order, longest row and P
+        DevBuf<uint32_t> cnt(nr), words(2);
+        DevBuf<uint64_t> off(nr + 1);
+        a.count = cnt.ptr;
+        sj::launch_join_rs(a, 0, s);
+        sj::scan_exclusive_u32_to_u64(cnt.ptr, off.ptr, nr, s);
+        sj::launch_fill_u32(words.ptr, 2, 0u, s);
+        sj::launch_rs_max(cnt.ptr, nr, words.ptr, s);
+        sj::HostStage hs;
+        SJ_HIP(hipMemcpyAsync(hs.p, off.ptr + nr, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipMemcpyAsync(hs.as<uint32_t>() + 2, words.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipStreamSynchronize(s));
+        const uint64_t P = *hs.as<uint64_t>();
+        const uint32_t max_len = hs.as<uint32_t>()[2];
+        if (total_pairs) *total_pairs = P;
+        if (!pairs_dev || P == 0) return;
+        if (capacity_pairs < P)
+            throw Error(SJ_ECAPACITY, "output buffer holds " + std::to_string(capacity_pairs) +
+                                          " pairs, the result has " + std::to_string(P));
+        // fill pass (neighbour ids per row, unsorted), then each row sorted
+        // and written as (i, j) pairs
+        DevBuf<uint32_t> out_j(P);
+        a.off = off.ptr;
+        a.out_j = out_j.ptr;
+        a.out_cap = P;
+        a.overflow = words.ptr + 1;
+        sj::launch_join_rs(a, 1, s);
+        sj::launch_rowsort(off.ptr, 0, nr, 0, out_j.ptr, pairs_dev, max_len, s);
+        SJ_HIP(hipMemcpyAsync(hs.p, words.ptr + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipStreamSynchronize(s));
+        if (*hs.as<uint32_t>()) throw Error(SJ_EDEVICE, "internal: the two-set fill disagreed with its count");
+    });
+}
+
 int sj_selfjoin_index(sj_index *idx, const sj_join_opts *opts, sj_run_cb cb, void *user,
                       void *stream, uint64_t *total_pairs) {
     hipStream_t s = as_stream(stream);

@@ -88,4 +88,23 @@ struct TileArgs {
     const uint2 *segs;        // [chunk * rows_per_chunk + row] candidate point segment
 };
 
+// Distance join of a query set R with an indexed set S (k_rs.hip).
+struct RsArgs {
+    const double *R;          // nr x d, row-major
+    uint64_t nr;
+    const double *X;          // S: d x ns, cell order
+    uint64_t ns;
+    const uint32_t *perm;     // S's A (cell-ordered position -> row of S)
+    const uint64_t *B;        // S's non-empty cell ids, ascending
+    const uint32_t *starts;   // S's cell starts (ncells + 1)
+    uint32_t ncells;
+    GridParams g;             // S's grid
+    double eps2;
+    uint32_t *count;          // count pass: neighbours of each query row
+    const uint64_t *off;      // fill pass: row offsets (nr + 1)
+    uint32_t *out_j;          // fill pass: S rows, each query row at off[r]
+    uint64_t out_cap;
+    uint32_t *overflow;       // set when a fill write falls outside its row
+};
+
 }  // namespace sj

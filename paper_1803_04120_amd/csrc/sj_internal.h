@@ -235,6 +235,12 @@ uint32_t build_query_list(const uint32_t *perm, uint64_t n, uint64_t i0, uint64_
 void launch_batch_bounds(const uint64_t *off, uint64_t n, uint64_t total, uint32_t nb,
                          uint64_t *rows, hipStream_t s);
 
+// Two-set join (k_rs.hip): mode 0 counts each query row's neighbours into
+// a.count, mode 1 writes them (S rows, unsorted) into a.out_j at a.off.
+void launch_join_rs(const RsArgs &a, int mode, hipStream_t s);
+// *out (0 on entry) = max of counts[0..n).
+void launch_rs_max(const uint32_t *counts, uint64_t n, uint32_t *out, hipStream_t s);
+
 // ---------------------------------------------------------------------
 // Row sort and pair expansion (k_rowsort.hip)
 // ---------------------------------------------------------------------

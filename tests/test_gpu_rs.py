@@ -1,0 +1,90 @@
+"""GPU distance join of a query set R with an indexed set S (sj_join_rs)
+against the oracle's two-set join (oracle.reference.join_rs_numpy), element
+by element."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import reference as ref
+from paper_1803_04120_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sj():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1803_04120_amd as m
+    m._lib.load()
+    return m
+
+
+def _say(msg):
+    print(f"[rs] {msg}", flush=True)
+
+
+def assert_same(got, want, what):
+    assert got.shape == want.shape, f"{what}: {got.shape[0]} pairs vs oracle {want.shape[0]}"
+    if not np.array_equal(got, want):
+        bad = np.nonzero(np.any(got != want, axis=1))[0][:5]
+        raise AssertionError(f"{what}: first differing rows {bad.tolist()}: "
+                             f"got {got[bad].tolist()} want {want[bad].tolist()}")
+
+
+def rs_pairs(sj, S, R, eps, host_queries=False):
+    with sj.Index(torch.from_numpy(S).cuda(), eps) as ix:
+        q = R if host_queries else torch.from_numpy(R).cuda()
+        return ix.join_rs(q).cpu().numpy().astype(np.int64)
+
+
+@pytest.mark.parametrize("kind,d,ns,nr,eps", [("uniform", 1, 3001, 2003, 0.05), ("uniform", 2, 20011, 7001, 0.9),
+                                              ("clustered", 2, 15013, 9001, 0.3), ("uniform", 3, 12007, 5003, 4.0),
+                                              ("clustered", 4, 8009, 4001, 2.5), ("uniform", 6, 4001, 2003, 30.0)])
+def test_join_rs_matches_oracle(sj, kind, d, ns, nr, eps):
+    _say(f"{kind} d={d} ns={ns} nr={nr} eps={eps}")
+    S = datagen.make(kind, ns, d, seed=500 + d)
+    # clustered: the same clusters (same seed, other n); uniform: independent
+    R = datagen.make(kind, nr, d, seed=500 + d if kind == "clustered" else 600 + d)
+    want = ref.join_rs_numpy(R, S, eps)
+    assert want.shape[0] > nr // 4  # real neighbours
+    assert_same(rs_pairs(sj, S, R, eps), want, f"R x S {kind} d={d}")
+
+
+def test_join_rs_queries_outside_the_index_box(sj):
+    """Queries just outside S's bounding box (within eps of its points),
+    one cell out, far away, and non-finite-free extremes."""
+    _say("queries outside the box")
+    S = datagen.uniform(5000, 2, seed=71)
+    lo, hi = S.min(axis=0), S.max(axis=0)
+    R = np.array([[lo[0] - 0.3, lo[1] + 10.0], [hi[0] + 0.2, hi[1] + 0.2], [lo[0] - 1.5, lo[1]],
+                  [1e9, -1e9], [-1e300, 1e300], [50.0, 50.0], [hi[0] + 0.7, 50.0]], dtype=np.float64)
+    want = ref.join_rs_numpy(R, S, 0.75)
+    assert want.shape[0] > 0
+    assert_same(rs_pairs(sj, S, R, 0.75), want, "outside the box")
+
+
+def test_join_rs_self_and_edges(sj):
+    _say("R = S, host queries, empty R, dimension mismatch, capacity")
+    S = datagen.uniform(6007, 3, seed=73)
+    # R = S gives the self-join
+    np.testing.assert_array_equal(rs_pairs(sj, S, S, 3.0), ref.pairs(S, 3.0))
+    # queries from host memory
+    R = datagen.uniform(1003, 3, seed=74)
+    np.testing.assert_array_equal(rs_pairs(sj, S, R, 3.0, host_queries=True), ref.join_rs_numpy(R, S, 3.0))
+    with sj.Index(torch.from_numpy(S).cuda(), 3.0) as ix:
+        assert ix.join_rs(torch.zeros((0, 3), dtype=torch.float64, device="cuda")).shape[0] == 0
+        with pytest.raises(ValueError):
+            ix.join_rs(torch.zeros((5, 2), dtype=torch.float64, device="cuda"))
+        from paper_1803_04120_amd import _lib
+        import ctypes
+        q = torch.from_numpy(R).cuda()
+        total = ctypes.c_uint64(0)
+        buf = torch.empty((4, 2), dtype=torch.int32, device="cuda")
+        rc = _lib.load().sj_join_rs(ix._h, ctypes.c_void_p(q.data_ptr()), R.shape[0], 1,
+                                    ctypes.c_void_p(buf.data_ptr()), 4, None, ctypes.byref(total))
+        assert rc == _lib.SJ_ECAPACITY
+        assert total.value == ref.join_rs_numpy(R, S, 3.0).shape[0]
