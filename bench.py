@@ -24,6 +24,8 @@ Beside `value` (pairs/s of the timed steps) the line carries:
   cpu_grid_baseline  the host-core grid join on the whole workload;
   fp32_band          the same sweep with the FP32 pre-test and FP64 band;
   batched            delivery in 2^24-pair batches;
+  rs_join            the two-set join: n/2 independent queries against the
+                     indexed workload points, per eps;
   serving            a Poisson request stream through the server (p50/p99).
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
@@ -76,6 +78,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--no-band", action="store_true", help="skip the FP32+band leg")
+    ap.add_argument("--no-rs", action="store_true", help="skip the two-set join leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy three times (reference kernel "
                          "of known traffic for hardware byte counters)")
@@ -379,6 +382,32 @@ def main():
     pipeline = {"alg_bytes_per_step": pipe, "achieved_GBs": round(pipe / (ms_per_step * 1e-3) / 1e9, 2),
                 "frac_of_hbm_peak": round(pipe / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
+    # two-set join: n/2 independent queries (the workload distribution) against the
+    # indexed workload points, at each eps (index built outside the timing)
+    rs = None
+    if not args.no_rs:
+        qpts = datagen.make(wl["kind"], n // 2, d, wl["seed"] + 1000)
+        qx = torch.from_numpy(qpts).to("cuda")
+        rs_out = torch.empty((max(i["pairs"] for i in info), 2), dtype=torch.int32, device="cuda")
+        per = []
+        for e in eps_list:
+            with sj.Index(x, e) as ix:
+                ix.join_rs(qx, out=rs_out)  # warm
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                reps = 3
+                for _ in range(reps):
+                    got = ix.join_rs(qx, out=rs_out)
+                torch.cuda.synchronize()
+                per.append((e, int(got.shape[0]), (time.perf_counter() - t0) / reps))
+        tot_p = sum(p for _, p, _ in per)
+        tot_t = sum(t for _, _, t in per)
+        rs = {"queries": int(qpts.shape[0]), "indexed": n, "pairs_per_s": tot_p / tot_t,
+              "ms_per_sweep": 1e3 * tot_t,
+              "per_eps": [{"eps": e, "pairs": p, "ms": round(1e3 * t, 3)} for e, p, t in per],
+              "note": "count + fill + row sort per call (sj_join_rs), index on the workload points"}
+        log(f"[bench] two-set join: {rs['pairs_per_s']:.4g} pairs/s, {rs['ms_per_sweep']:.3f} ms per sweep")
+
     batched = None
     if not args.no_batched:
         cap = args.batch_capacity
@@ -480,6 +509,7 @@ def main():
         "pipeline_hbm": pipeline,
         "per_eps": info,
         "batched": batched,
+        "rs_join": rs,
         "serving": serving,
         "kernels_ms": {k: round(v[1], 4) for k, v in all_prof.items()},
         "call_wall_ms": {k: round(v, 3) for k, v in host_ms.items()},

@@ -106,19 +106,28 @@ class Index:
         if nr and d != self.d:
             raise ValueError(f"queries have {d} dimensions, the index {self.d}")
         total = ctypes.c_uint64(0)
+        if out is not None:
+            # one call when the buffer is large enough
+            if out.dtype != torch.int32 or not out.is_contiguous():
+                raise ValueError("out must be a contiguous int32 tensor")
+            rc = L.sj_join_rs(self._h, ptr, nr, on_dev, ctypes.c_void_p(out.data_ptr()), out.numel() // 2,
+                              _stream_handle(self._stream), ctypes.byref(total))
+            if rc == _lib.SJ_ECAPACITY:
+                raise ValueError(f"out has room for {out.numel() // 2} pairs, the result has {total.value}")
+            _lib.check(rc)
+            P = int(total.value)
+            del keep
+            return out[:P] if out.shape[0] != P else out
         _lib.check(L.sj_join_rs(self._h, ptr, nr, on_dev, None, 0, _stream_handle(self._stream),
                                 ctypes.byref(total)))
         P = int(total.value)
-        if out is None:
-            dev = self._device or torch.device("cuda")
-            out = torch.empty((P, 2), dtype=torch.int32, device=dev)
-        if out.dtype != torch.int32 or not out.is_contiguous() or out.numel() < 2 * P:
-            raise ValueError("out must be a contiguous int32 tensor with room for P pairs")
+        dev = self._device or torch.device("cuda")
+        out = torch.empty((P, 2), dtype=torch.int32, device=dev)
         if P:
             _lib.check(L.sj_join_rs(self._h, ptr, nr, on_dev, ctypes.c_void_p(out.data_ptr()), P,
                                     _stream_handle(self._stream), ctypes.byref(total)))
         del keep
-        return out[:P] if out.shape[0] != P else out
+        return out
 
     def join(self, unicomp: bool = True, precision: str = "fp64"):
         self.count(unicomp, precision)

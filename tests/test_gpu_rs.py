@@ -87,4 +87,11 @@ def test_join_rs_self_and_edges(sj):
         rc = _lib.load().sj_join_rs(ix._h, ctypes.c_void_p(q.data_ptr()), R.shape[0], 1,
                                     ctypes.c_void_p(buf.data_ptr()), 4, None, ctypes.byref(total))
         assert rc == _lib.SJ_ECAPACITY
-        assert total.value == ref.join_rs_numpy(R, S, 3.0).shape[0]
+        want = ref.join_rs_numpy(R, S, 3.0)
+        assert total.value == want.shape[0]
+        # caller buffers: too small raises, large enough is filled in one call
+        with pytest.raises(ValueError):
+            ix.join_rs(q, out=buf)
+        big = torch.empty((want.shape[0] + 100, 2), dtype=torch.int32, device="cuda")
+        got = ix.join_rs(q, out=big).cpu().numpy().astype(np.int64)
+        np.testing.assert_array_equal(got, want)
