@@ -213,9 +213,10 @@ def join_rs_numpy(r_points, s_points, eps: float) -> np.ndarray:
     rows = []
     for i in range(r.shape[0]):
         acc = np.zeros(s.shape[0], dtype=np.float64)
-        for k in range(r.shape[1]):
-            t = r[i, k] - s[:, k]
-            acc = acc + t * t
+        with np.errstate(over="ignore"):  # a far query's d2 is +inf: not within eps
+            for k in range(r.shape[1]):
+                t = r[i, k] - s[:, k]
+                acc = acc + t * t
         js = np.nonzero(acc <= eps2)[0]
         rows.append(np.stack([np.full(js.shape, i, dtype=np.int64), js.astype(np.int64)], axis=1))
     if not rows:
