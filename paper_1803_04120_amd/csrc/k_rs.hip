@@ -5,7 +5,9 @@
 // those cells with the self-join's predicate (Section III: squared distance
 // in binary64, dimension order 0..d-1, no fused multiply-add, d2 <= eps^2).
 // Dimension 0 varies fastest in the linear cell id, so the cells of one
-// neighbourhood row are consecutive ids: one lower bound in B per row.
+// neighbourhood row are consecutive ids: one lower bound in B per row. The
+// queries are taken in S's cell order (sorted by the index's cell key), so
+// the threads of a wave mostly probe the same cells.
 #include "sj_internal.h"
 #include "sj_device.h"
 
@@ -30,8 +32,9 @@ __device__ __forceinline__ uint32_t rs_lower_bound(const uint64_t *__restrict__ 
 // out_j[off[r] ...], in probe order (sorted afterwards).
 template <int D, int kMode>
 __global__ __launch_bounds__(kThreads) void k_join_rs(RsArgs a) {
-    const uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
-    if (r >= a.nr) return;
+    const uint64_t k = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (k >= a.nr) return;
+    const uint64_t r = a.qperm[k];  // neighbouring threads probe neighbouring cells
     double q[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) q[j] = a.R[r * D + j];

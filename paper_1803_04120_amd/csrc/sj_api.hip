@@ -811,9 +811,25 @@ int sj_join_rs(sj_index *idx, const double *R, uint64_t nr, int r_on_device, uin
             SJ_HIP(hipMemcpyAsync(staged.ptr, R, nr * d * sizeof(double), hipMemcpyHostToDevice, s));
             rp = staged.ptr;
         }
+        // queries in S's cell order (the index's cell key and radix sort),
+        // so that a wave's queries share candidate cells
+        DevBuf<uint32_t> qperm(nr), qperm_alt(nr);
+        {
+            DevBuf<uint64_t> k64(nr), k64_alt(nr);
+            if (ix.key_bits <= 32) {
+                uint32_t *k = reinterpret_cast<uint32_t *>(k64.ptr), *k2 = reinterpret_cast<uint32_t *>(k64_alt.ptr);
+                sj::launch_cell_keys_u32(rp, nr, ix.grid, k, qperm.ptr, s);
+                if (sj::radix_sort_u32(k, qperm.ptr, k2, qperm_alt.ptr, nr, ix.key_bits, s)) std::swap(qperm, qperm_alt);
+            } else {
+                sj::launch_cell_keys_u64(rp, nr, ix.grid, k64.ptr, qperm.ptr, s);
+                if (sj::radix_sort_u64(k64.ptr, qperm.ptr, k64_alt.ptr, qperm_alt.ptr, nr, ix.key_bits, s))
+                    std::swap(qperm, qperm_alt);
+            }
+        }
         sj::RsArgs a{};
         a.R = rp;
         a.nr = nr;
+        a.qperm = qperm.ptr;
         a.X = ix.X.ptr;
         a.ns = ix.n;
         a.perm = ix.perm.ptr;

@@ -92,6 +92,7 @@ struct TileArgs {
 struct RsArgs {
     const double *R;          // nr x d, row-major
     uint64_t nr;
+    const uint32_t *qperm;    // query rows in S's cell order (thread k takes row qperm[k])
     const double *X;          // S: d x ns, cell order
     uint64_t ns;
     const uint32_t *perm;     // S's A (cell-ordered position -> row of S)
