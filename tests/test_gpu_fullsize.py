@@ -158,3 +158,42 @@ def test_batched_equals_unbatched_at_scale(sj):
     assert torch.equal(got, out)
     del out, got, x
     torch.cuda.empty_cache()
+
+
+def test_two_set_join_1M_queries_vs_2M_indexed(sj):
+    """The two-set join at the bench's size: 10^6 uniform queries (seed 1002)
+    against the 2,000,000 indexed points (seed 2), eps 0.04 .. 0.2. Sampled
+    query rows are recomputed by the oracle against all of S; every reported
+    pair is checked against the predicate, and the pairs must come sorted by
+    (query, indexed row) with no repeats."""
+    S = datagen.uniform(2_000_000, 2, seed=2)
+    R = datagen.uniform(1_000_000, 2, seed=1002)
+    s_dev, r_dev = torch.from_numpy(S).cuda(), torch.from_numpy(R).cuda()
+    buf = None
+    for e in (0.04, 0.08, 0.12, 0.16, 0.2):
+        _say(f"two-set join 1M queries x 2M indexed eps={e}")
+        with sj.Index(s_dev, e) as ix:
+            got_t = ix.join_rs(r_dev)
+            if buf is None or buf.shape[0] < got_t.shape[0]:
+                buf = torch.empty((got_t.shape[0] + 1024, 2), dtype=torch.int32, device="cuda")
+            # the caller-buffer form (one call, as timed) gives the same pairs
+            assert torch.equal(ix.join_rs(r_dev, out=buf), got_t)
+        got = got_t.cpu().numpy().astype(np.int64)
+        del got_t
+        assert got.shape[0] > R.shape[0]  # several neighbours per query
+        key = got[:, 0] * S.shape[0] + got[:, 1]
+        assert np.all(np.diff(key) > 0), "pairs not sorted or repeated"
+        with np.errstate(over="ignore"):
+            t0 = R[got[:, 0], 0] - S[got[:, 1], 0]
+            t1 = R[got[:, 0], 1] - S[got[:, 1], 1]
+            d2 = (0.0 + t0 * t0) + t1 * t1
+        assert np.all(d2 <= e * e), "a reported pair is farther than eps"
+        rows = np.sort(np.random.default_rng(int(e * 1000) + 7).choice(R.shape[0], 128, replace=False))
+        want = ref.join_rs_numpy(R[rows], S, e)
+        want[:, 0] = rows[want[:, 0]]
+        a = np.searchsorted(got[:, 0], rows, side="left")
+        b = np.searchsorted(got[:, 0], rows, side="right")
+        seg = np.concatenate([got[x:y] for x, y in zip(a, b)], axis=0)
+        np.testing.assert_array_equal(seg, want)
+    del s_dev, r_dev, buf
+    torch.cuda.empty_cache()
