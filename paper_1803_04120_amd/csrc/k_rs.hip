@@ -28,8 +28,10 @@ __device__ __forceinline__ uint32_t rs_lower_bound(const uint64_t *__restrict__ 
     return lo;
 }
 
-// kMode 0: per-query counts; 1: neighbour ids (S's original rows) into
-// out_j[off[r] ...], in probe order (sorted afterwards).
+// kMode 0: per-query counts, by query row and by probe position; 1: neighbour
+// ids (S's original rows) into out_j[off[k] ...], where off is the scan of the
+// counts in probe order: the segments of a wave's queries are adjacent, so its
+// writes land in few lines. The row sort then moves each segment to its row.
 template <int D, int kMode>
 __global__ __launch_bounds__(kThreads) void k_join_rs(RsArgs a) {
     const uint64_t k = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
@@ -57,7 +59,7 @@ __global__ __launch_bounds__(kThreads) void k_join_rs(RsArgs a) {
         if (lo[j] > hi[j]) any = false;
     }
     uint32_t found = 0;
-    uint64_t at = kMode == 1 ? a.off[r] : 0;
+    uint64_t at = kMode == 1 ? a.off[k] : 0;
     if (any) {
         // odometer over dimensions 1..d-1; dimension 0 is the id range
         int64_t o[D];
@@ -103,7 +105,8 @@ __global__ __launch_bounds__(kThreads) void k_join_rs(RsArgs a) {
     }
     if (kMode == 0) {
         a.count[r] = found;
-    } else if (at != a.off[r + 1]) {
+        a.count_k[k] = found;
+    } else if (at != a.off[k + 1]) {
         atomicOr(a.overflow, 1u);  // the fill disagrees with the count
     }
 }

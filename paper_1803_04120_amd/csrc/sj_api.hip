@@ -838,12 +838,15 @@ int sj_join_rs(sj_index *idx, const double *R, uint64_t nr, int r_on_device, uin
         a.ncells = static_cast<uint32_t>(ix.ncells);
         a.g = ix.grid;
         a.eps2 = ix.eps * ix.eps;
-        // count pass, row offsets in R's order, longest row and P
-        DevBuf<uint32_t> cnt(nr), words(2);
-        DevBuf<uint64_t> off(nr + 1);
+        // count pass; row offsets in R's order (output) and in probe order
+        // (fill); longest row and P
+        DevBuf<uint32_t> cnt(nr), cnt_k(nr), words(2);
+        DevBuf<uint64_t> off(nr + 1), off_k(nr + 1);
         a.count = cnt.ptr;
+        a.count_k = cnt_k.ptr;
         sj::launch_join_rs(a, 0, s);
         sj::scan_exclusive_u32_to_u64(cnt.ptr, off.ptr, nr, s);
+        sj::scan_exclusive_u32_to_u64(cnt_k.ptr, off_k.ptr, nr, s);
         sj::launch_fill_u32(words.ptr, 2, 0u, s);
         sj::launch_rs_max(cnt.ptr, nr, words.ptr, s);
         sj::HostStage hs;
@@ -857,15 +860,15 @@ int sj_join_rs(sj_index *idx, const double *R, uint64_t nr, int r_on_device, uin
         if (capacity_pairs < P)
             throw Error(SJ_ECAPACITY, "output buffer holds " + std::to_string(capacity_pairs) +
                                           " pairs, the result has " + std::to_string(P));
-        // fill pass (neighbour ids per row, unsorted), then each row sorted
-        // and written as (i, j) pairs
+        // fill pass (neighbour ids per query in probe order, unsorted), then
+        // each row sorted and written as (i, j) pairs at its offset in R's order
         DevBuf<uint32_t> out_j(P);
-        a.off = off.ptr;
+        a.off = off_k.ptr;
         a.out_j = out_j.ptr;
         a.out_cap = P;
         a.overflow = words.ptr + 1;
         sj::launch_join_rs(a, 1, s);
-        sj::launch_rowsort(off.ptr, 0, nr, 0, out_j.ptr, pairs_dev, max_len, s);
+        sj::launch_rowsort_cells(off_k.ptr, off.ptr, qperm.ptr, nr, out_j.ptr, pairs_dev, max_len, s);
         SJ_HIP(hipMemcpyAsync(hs.p, words.ptr + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         SJ_HIP(hipStreamSynchronize(s));
         if (*hs.as<uint32_t>()) throw Error(SJ_EDEVICE, "internal: the two-set fill disagreed with its count");

@@ -101,9 +101,10 @@ struct RsArgs {
     uint32_t ncells;
     GridParams g;             // S's grid
     double eps2;
-    uint32_t *count;          // count pass: neighbours of each query row
-    const uint64_t *off;      // fill pass: row offsets (nr + 1)
-    uint32_t *out_j;          // fill pass: S rows, each query row at off[r]
+    uint32_t *count;          // count pass: neighbours of each query row (by row)
+    uint32_t *count_k;        // count pass: the same counts in probe order (by k)
+    const uint64_t *off;      // fill pass: offsets in probe order (nr + 1)
+    uint32_t *out_j;          // fill pass: S rows, the k-th probed query at off[k]
     uint64_t out_cap;
     uint32_t *overflow;       // set when a fill write falls outside its row
 };
