@@ -111,15 +111,23 @@ __global__ __launch_bounds__(kThreads) void k_join_rs(RsArgs a) {
     }
 }
 
-// out[0] = max over counts[0..n); out must be 0 on entry.
+// out[0] = max over counts[0..n); out must be 0 on entry. One atomic per
+// block: atomics from every wave on the one address serialise in L2.
 __global__ __launch_bounds__(kThreads) void k_rs_max(const uint32_t *__restrict__ counts, uint64_t n,
                                                       uint32_t *__restrict__ out) {
+    __shared__ uint32_t wmax[kThreads / 64];
     uint32_t m = 0;
     for (uint64_t i = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x; i < n;
          i += static_cast<uint64_t>(gridDim.x) * kThreads)
         m = counts[i] > m ? counts[i] : m;
     m = wave_max(m);
-    if (lane_id() == 0 && m) atomicMax(out, m);
+    if (lane_id() == 0) wmax[threadIdx.x / 64] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 1; w < kThreads / 64; ++w) m = wmax[w] > m ? wmax[w] : m;
+        if (m) atomicMax(out, m);
+    }
 }
 
 template <int D>
@@ -154,7 +162,7 @@ void launch_join_rs(const RsArgs &a, int mode, hipStream_t s) {
 
 void launch_rs_max(const uint32_t *counts, uint64_t n, uint32_t *out, hipStream_t s) {
     if (n == 0) return;
-    const unsigned nb = static_cast<unsigned>(std::min<uint64_t>(512, (n + kThreads - 1) / kThreads));
+    const unsigned nb = static_cast<unsigned>(std::min<uint64_t>(256, (n + kThreads - 1) / kThreads));
     k_rs_max<<<nb, kThreads, 0, s>>>(counts, n, out);
     SJ_LAUNCH_CHECK();
 }
