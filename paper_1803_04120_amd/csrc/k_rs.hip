@@ -60,6 +60,11 @@ __global__ __launch_bounds__(kThreads) void k_join_rs(RsArgs a) {
     }
     uint32_t found = 0;
     uint64_t at = kMode == 1 ? a.off[k] : 0;
+    // fill: a hit at an even position waits for the next one, and the two go
+    // out as one aligned 8-byte store (half the store transactions)
+    uint32_t pend = 0;
+    uint64_t pend_at = 0;
+    bool have = false;
     if (any) {
         // odometer over dimensions 1..d-1; dimension 0 is the id range
         int64_t o[D];
@@ -84,10 +89,19 @@ __global__ __launch_bounds__(kThreads) void k_join_rs(RsArgs a) {
                     }
                     if (acc <= a.eps2) {
                         if (kMode == 1) {
-                            if (at < a.out_cap)
-                                a.out_j[at] = a.perm[p];
-                            else
+                            const uint32_t v = a.perm[p];
+                            if (at >= a.out_cap) {
                                 atomicOr(a.overflow, 1u);
+                            } else if ((at & 1) == 0) {
+                                pend = v;
+                                pend_at = at;
+                                have = true;
+                            } else if (have) {  // pend_at == at - 1, even
+                                *reinterpret_cast<uint2 *>(a.out_j + pend_at) = make_uint2(pend, v);
+                                have = false;
+                            } else {
+                                a.out_j[at] = v;
+                            }
                             ++at;
                         }
                         ++found;
@@ -103,6 +117,7 @@ __global__ __launch_bounds__(kThreads) void k_join_rs(RsArgs a) {
             ++o[j];
         }
     }
+    if (kMode == 1 && have) a.out_j[pend_at] = pend;
     if (kMode == 0) {
         a.count[r] = found;
         a.count_k[k] = found;
