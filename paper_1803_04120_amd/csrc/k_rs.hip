@@ -60,11 +60,30 @@ __global__ __launch_bounds__(kThreads) void k_join_rs(RsArgs a) {
     }
     uint32_t found = 0;
     uint64_t at = kMode == 1 ? a.off[k] : 0;
-    // fill: a hit at an even position waits for the next one, and the two go
-    // out as one aligned 8-byte store (half the store transactions)
-    uint32_t pend = 0;
-    uint64_t pend_at = 0;
-    bool have = false;
+    // fill: hits are held by their place in an aligned group of four output
+    // positions (w0..w3, places [glo, ghi) of the group at gbase); a whole
+    // group goes out as one 16-byte store, a partial one (at the ends of the
+    // query's segment) as aligned pairs and single words
+    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, glo = 4, ghi = 0;
+    uint64_t gbase = 0;
+    auto flush = [&]() {
+        if (glo == 0 && ghi == 4) {
+            *reinterpret_cast<uint4 *>(a.out_j + gbase) = make_uint4(w0, w1, w2, w3);
+            return;
+        }
+        if (glo == 0 && ghi >= 2) {
+            *reinterpret_cast<uint2 *>(a.out_j + gbase) = make_uint2(w0, w1);
+        } else {
+            if (glo == 0 && ghi > 0) a.out_j[gbase] = w0;
+            if (glo <= 1 && ghi > 1) a.out_j[gbase + 1] = w1;
+        }
+        if (glo <= 2 && ghi == 4) {
+            *reinterpret_cast<uint2 *>(a.out_j + gbase + 2) = make_uint2(w2, w3);
+        } else {
+            if (glo <= 2 && ghi > 2) a.out_j[gbase + 2] = w2;
+            if (ghi > 3) a.out_j[gbase + 3] = w3;
+        }
+    };
     if (any) {
         // odometer over dimensions 1..d-1; dimension 0 is the id range
         int64_t o[D];
@@ -92,15 +111,21 @@ __global__ __launch_bounds__(kThreads) void k_join_rs(RsArgs a) {
                             const uint32_t v = a.perm[p];
                             if (at >= a.out_cap) {
                                 atomicOr(a.overflow, 1u);
-                            } else if ((at & 1) == 0) {
-                                pend = v;
-                                pend_at = at;
-                                have = true;
-                            } else if (have) {  // pend_at == at - 1, even
-                                *reinterpret_cast<uint2 *>(a.out_j + pend_at) = make_uint2(pend, v);
-                                have = false;
                             } else {
-                                a.out_j[at] = v;
+                                const uint32_t g = static_cast<uint32_t>(at & 3);
+                                if (glo == 4) {  // first held hit of this group
+                                    gbase = at - g;
+                                    glo = g;
+                                }
+                                w0 = g == 0 ? v : w0;
+                                w1 = g == 1 ? v : w1;
+                                w2 = g == 2 ? v : w2;
+                                w3 = g == 3 ? v : w3;
+                                ghi = g + 1;
+                                if (g == 3) {
+                                    flush();
+                                    glo = 4;
+                                }
                             }
                             ++at;
                         }
@@ -117,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_join_rs(RsArgs a) {
             ++o[j];
         }
     }
-    if (kMode == 1 && have) a.out_j[pend_at] = pend;
+    if (kMode == 1 && glo != 4) flush();
     if (kMode == 0) {
         a.count[r] = found;
         a.count_k[k] = found;
