@@ -1,35 +1,47 @@
 #!/usr/bin/env python3
 """Throughput of the epsilon self-join on one MI355X.
 
-One step = the whole hot path for every eps of the workload: build the grid
+One step = the whole hot path for every join of the workload: build the grid
 index (bounding box, cell ids, sort, cell tables, masks, cell-ordered copy),
 count pass (adjacent-cell search and refine), fill pass and row sorts, with
 the sorted (i, j) pairs written to a device buffer. Inputs are resident in
 HBM before the timed region starts; the output stays in HBM.
 
-Default workload: 2,000,000 points uniform in [0,100]^2 (FP64, seed 2), eps
-in {0.04, 0.08, 0.12, 0.16, 0.2} -- the shape of the paper's 2-D synthetic
-sets (Section VI-A). Prints ONE JSON line on stdout; everything else goes to
-stderr.
+Default workload (the largest single-GPU configuration): 10,000,000 points
+uniform in [0,100]^d for d = 3, 4, 5, 6 (the paper's synthetic sets, Section
+VI-A), each at the eps giving a mean of 32 and of 256 neighbours per point
+(calibrated by the oracle, tests/golden/eps_calibration.json): eight joins
+per step, 2.9e8 .. 2.6e9 pairs each, unicomp on, binary64. Prints ONE JSON
+line on stdout; everything else goes to stderr.
 
 Beside `value` (pairs/s of the timed steps) the line carries:
-  roofline           the modelled kernel with the largest time in one
-                     untimed, fully profiled step; in the timed steps only
-                     its launches carry HIP events: algorithmic bytes per
-                     launch over its event-timed average duration, against
-                     8 TB/s, and the counted HBM traffic from the summary
-                     under profiles/ while its sources are unchanged;
-  kernels_ms         every kernel of that untimed step (ms per step);
-  cpu_baseline       the brute-force oracle on a sample of query rows;
-  cpu_grid_baseline  the host-core grid join on the whole workload;
-  fp32_band          the same sweep with the FP32 pre-test and FP64 band;
-  batched            delivery in 2^24-pair batches;
-  rs_join            the two-set join: n/2 independent queries against the
-                     indexed workload points, per eps;
-  serving            a Poisson request stream through the server (p50/p99).
+  roofline         the modelled kernel with the largest time in one untimed,
+                   fully profiled step; in the timed steps only its launches
+                   carry HIP events. Its bound is the larger of two lower
+                   bounds: HBM (algorithmic bytes at 8 TB/s) and FP64 VALU
+                   (algorithmic operations, (3d - 1) per distance
+                   evaluation, at 3.93e13 non-fused operations/s);
+                   `traffic` is the counted HBM traffic from the summary
+                   under profiles/ while the kernel's sources are unchanged;
+  valu_roofline / hbm_roofline   both fractions for that kernel;
+  legs             the other configurations and modes:
+                     unicomp_off      the same step without unicomp;
+                     batched          the same joins delivered in 2^27-pair
+                                      batches (result larger than one batch);
+                     clustered_5M     5,000,000 clustered points in 2-D and
+                                      3-D, FP32 pre-test + FP64 band vs FP64;
+                     uniform2d_2M     2,000,000 uniform 2-D points, five eps;
+                     uniform2d_10k    10,000 uniform 2-D points, eps 1;
+                     brute_force      the all-pairs kernel vs the grid join;
+                     rs_join          the two-set join;
+                     dbscan           clustering over the CSR neighbour table;
+                     serving          a Poisson request stream (p50/p99);
+  cpu_baseline     the brute-force oracle on a sample of query rows, on all
+                   host threads; cpu_baseline_1core the same on one thread;
+  cpu_grid_baseline  the host-core grid join on whole joins of the workload.
 
-  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
-                  [--no-serve] [--no-band] [--no-batched]
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-legs]
+                  [--no-cpu-baseline] [--no-serve]
 """
 from __future__ import annotations
 
@@ -46,67 +58,207 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-
-WORKLOADS = {
-    # the 2-D sweep the headline metric is quoted on
-    "uniform2d_n2M_eps_sweep": dict(kind="uniform", n=2_000_000, d=2, seed=2,
-                                    eps=[0.04, 0.08, 0.12, 0.16, 0.2]),
-    # small 2-D case
-    "uniform2d_n10k_eps1": dict(kind="uniform", n=10_000, d=2, seed=1, eps=[1.0]),
-}
+# FP64 vector operations that are not fused multiply-adds (the pair test has
+# none): 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz. Unpacked FP32
+# issues at the same rate on gfx950.
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+CALIB = os.path.join(ROOT, "tests", "golden", "eps_calibration.json")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def workloads():
+    with open(CALIB) as f:
+        cal = json.load(f)
+    u, c = cal["uniform_n10M"], cal["clustered_n5M"]
+    return {
+        "uniform_n10M_d3-6_k32-256": [
+            dict(kind="uniform", n=u[k]["n"], d=u[k]["d"], seed=u[k]["seed"], eps=u[k]["eps"], tag=k)
+            for k in ("d3_k32", "d3_k256", "d4_k32", "d4_k256", "d5_k32", "d5_k256", "d6_k32", "d6_k256")],
+        "clustered_n5M_d2-3_median50": [
+            dict(kind="clustered", n=c[k]["n"], d=c[k]["d"], seed=c[k]["seed"], eps=c[k]["eps"], tag=k)
+            for k in ("d2", "d3")],
+        "uniform2d_n2M_eps_sweep": [dict(kind="uniform", n=2_000_000, d=2, seed=2, eps=e, tag=f"eps{e}")
+                                    for e in (0.04, 0.08, 0.12, 0.16, 0.2)],
+        "uniform2d_n10k_eps1": [dict(kind="uniform", n=10_000, d=2, seed=1, eps=1.0, tag="eps1")],
+    }
+
+
+DEFAULT_WORKLOAD = "uniform_n10M_d3-6_k32-256"
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="uniform2d_n2M_eps_sweep", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(workloads()))
     ap.add_argument("--unicomp", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_band"])
+    ap.add_argument("--no-legs", action="store_true", help="only the headline workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="target CPU time of the oracle baseline sample")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batch-capacity", type=int, default=1 << 24,
-                    help="pairs per batch for the batched-delivery figure")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of each host baseline sample")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
-    ap.add_argument("--serve-requests", type=int, default=128)
+    ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-slots", type=int, default=4)
-    ap.add_argument("--no-band", action="store_true", help="skip the FP32+band leg")
-    ap.add_argument("--no-rs", action="store_true", help="skip the two-set join leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy three times (reference kernel "
                          "of known traffic for hardware byte counters)")
     return ap.parse_args()
 
 
-def kernel_bytes(name, n, d, cells, ranges, pairs):
-    """Algorithmic HBM bytes of one launch of a kernel (each array the
-    kernel must touch, read or written once). Neighbour re-reads, atomics and
-    scratch are overhead, not counted."""
-    if name.startswith("join_count") or name.startswith("tiled_count"):
-        # X (d doubles) + cell of each point + its row length; cell range table
-        return n * (8 * d + 4 + 4) + 8 * (cells + 1) + 8 * ranges
-    if name.startswith("tiled_fill_sort") and name.endswith("fp32band"):
-        # as below, plus the FP32 copy of every point (4d bytes)
-        return n * (8 * d + 4 * d + 4 + 8 + 4 + 8) + 8 * pairs
+# ------------------------------------------------------------ workloads
+class Workload:
+    """Device-resident points of every join of a workload and the joins'
+    sizes (from an untimed count pass)."""
+
+    def __init__(self, name, joins, torch):
+        from paper_1803_04120_amd import datagen
+        self.name, self.joins, self.torch = name, joins, torch
+        self.points = {}
+        for j in joins:
+            key = (j["kind"], j["n"], j["d"], j["seed"])
+            if key not in self.points:
+                pts = datagen.make(j["kind"], j["n"], j["d"], j["seed"])
+                self.points[key] = (pts, torch.from_numpy(pts).to("cuda"))
+        self.info = None
+
+    def x(self, j):
+        return self.points[(j["kind"], j["n"], j["d"], j["seed"])][1]
+
+    def host(self, j):
+        return self.points[(j["kind"], j["n"], j["d"], j["seed"])][0]
+
+    def size(self, sj, unicomp=True, precision="fp64"):
+        info = []
+        for j in self.joins:
+            with sj.Index(self.x(j), j["eps"]) as ix:
+                P = ix.count(unicomp=unicomp, precision=precision)
+                st = ix.stats()
+                off = ix.export(sj._lib.SJ_EXPORT_ROW_OFFSETS)
+            lens = np.diff(off.astype(np.int64))
+            info.append(dict(tag=j["tag"], n=j["n"], d=j["d"], eps=j["eps"], pairs=P, cells=st["cells"],
+                             evals=st["evals"], band_rechecks=st["band_rechecks"],
+                             max_cell=st["max_cell_points"], max_row=st["max_row_pairs"],
+                             unicomp=unicomp, row_classes=row_classes(lens)))
+        self.info = info
+        return info
+
+    def max_pairs(self):
+        return max(i["pairs"] for i in self.info)
+
+    def step(self, sj, out, unicomp=True, precision="fp64"):
+        total, flags = 0, []
+        for j in self.joins:
+            with sj.Index(self.x(j), j["eps"]) as ix:
+                total += ix.count(unicomp=unicomp, precision=precision)
+                ix.fill(out)
+                flags.append(ix.stats()["fill_unicomp"])
+        self._last_fill_unicomp = flags  # which fill kernel each join ran
+        return total
+
+
+def row_classes(lens):
+    """Pairs in rows of each row-sort size class."""
+    out = {}
+    for name, lo, hi in (("le32", 0, 32), ("33_64", 33, 64), ("65_1024", 65, 1024), ("1025_8192", 1025, 8192),
+                         ("gt8192", 8193, 1 << 62)):
+        m = (lens >= lo) & (lens <= hi)
+        out[name] = int(lens[m].sum())
+    return out
+
+
+# ------------------------------------------------------------ kernel models
+def kernel_model(name, i):
+    """(algorithmic HBM bytes, algorithmic FP64 operations) of one launch of
+    kernel `name` in join i (sizes from the count pass), or None when the
+    kernel is not modelled. Bytes count each array the kernel must touch
+    once; operations count (3d - 1) per distance evaluation (d subtractions,
+    d multiplications, d - 1 additions)."""
+    n, d, P, cells = i["n"], i["d"], i["pairs"], i["cells"]
+    U = i["evals"] if i["unicomp"] else (i["evals"] + n) // 2  # unicomp evaluations (U = (T + n) / 2)
+    T = 2 * U - n
+    ops_per_eval = 3 * d - 1
+    if name.startswith("tiled_count"):
+        ev = U if "unicomp" in name else T
+        return n * (8 * d + 4 + 4) + 8 * (cells + 1), ev * ops_per_eval
     if name.startswith("tiled_fill_sort"):
-        # X + cell + cell-order row offset + permutation entry + the row's
-        # final offset per point, one (i, j) pair (8 bytes) per result pair
-        return n * (8 * d + 4 + 8 + 4 + 8) + 8 * pairs
-    if name.startswith("join_fill") or name.startswith("tiled_fill"):
-        # X + cell + row offset + permutation entry per point, range table,
-        # one 4-byte neighbour id per pair
-        return n * (8 * d + 4 + 8 + 4) + 8 * (cells + 1) + 8 * ranges + 4 * pairs
-    if name in ("rowsort_small", "rowsort_lane", "rowsort_group16"):
-        # row offsets, neighbour ids in, (i, j) pairs out
-        return 8 * (n + 1) + 4 * pairs + 8 * pairs
+        # coordinates, cell coordinate, cell-order and final row offsets,
+        # permutation entry per point; one 8-byte (i, j) pair per result pair
+        extra = 4 * d * n if name.endswith("fp32band") else 0
+        return n * (8 * d + 4 + 8 + 4 + 8) + extra + 8 * P, T * ops_per_eval
+    if name.startswith("tiled_fill"):
+        ev = U if "unicomp" in name else T
+        extra = 4 * d * n if name.endswith("fp32band") else 0
+        return n * (8 * d + 4 + 8 + 4) + extra + 4 * P, ev * ops_per_eval
+    rc = i["row_classes"]
+    if name == "rowsort_wave":
+        p = rc["65_1024"]
+        return 8 * n + 12 * p, 0
+    if name == "rowsort_block":
+        return 12 * rc["1025_8192"], 0
+    if name == "rowsort_group16":
+        return 12 * rc["33_64"], 0
+    if name == "rowsort_lane":
+        return 8 * (n + 1) + 12 * rc["le32"], 0
     return None
+
+
+def modelled(prof, info, fill_unicomp_flags):
+    """{kernel: (launches, ms, bytes, ops)} summed over the joins of a step."""
+    out = {}
+    for name, (cnt, ms) in prof.items():
+        b = o = 0
+        ok = False
+        for k, i in enumerate(info):
+            m = kernel_model(name, i)
+            if m is None:
+                break
+            ok = True
+            # a join contributes only if it launched this kernel
+            if launched_in(name, i, fill_unicomp_flags[k] if k < len(fill_unicomp_flags) else 0):
+                b += m[0]
+                o += m[1]
+        if ok and (b or o):
+            out[name] = (cnt, ms, b, o)
+    return out
+
+
+def launched_in(name, i, fill_unicomp):
+    """Whether join i launches kernel `name` (which fill and row sorts run)."""
+    d = i["d"]
+    fused = d <= 3 and not fill_unicomp
+    if name.startswith("tiled_count"):
+        return ("unicomp" in name) == bool(i["unicomp"])
+    if name.startswith("tiled_fill_sort"):
+        return fused
+    if name.startswith("tiled_fill"):
+        return (not fused) and (("unicomp" in name) == bool(fill_unicomp))
+    rc = i["row_classes"]
+    if name == "rowsort_wave":
+        return rc["65_1024"] > 0
+    if name == "rowsort_block":
+        return rc["1025_8192"] > 0
+    if name in ("rowsort_group16", "rowsort_lane"):
+        return not fused
+    return False
+
+
+def roofline_of(name, cnt, ms, byts, ops):
+    t = ms * 1e-3
+    gbs = byts / t / 1e9
+    opss = ops / t
+    hbm = {"achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    valu = {"achieved": round(opss / 1e12, 3), "peak": round(VALU_PEAK_OPS / 1e12, 3), "unit": "TFLOP/s",
+            "frac": round(opss / VALU_PEAK_OPS, 4)}
+    bound = "alu" if ops / VALU_PEAK_OPS > byts / (HBM_PEAK_GBS * 1e9) else "hbm"
+    main = valu if bound == "alu" else hbm
+    return dict(bound=bound, kernel=name, achieved=main["achieved"], peak=main["peak"], unit=main["unit"],
+                frac=main["frac"], avg_launch_us=round(1e3 * ms / cnt, 3), launches=cnt,
+                bytes_per_launch=int(byts / cnt), ops_per_launch=int(ops / cnt)), hbm, valu
 
 
 # Sources compiled into each family of modelled kernels: a traffic figure
@@ -115,6 +267,8 @@ KERNEL_SOURCES = {
     "tiled_": ["k_tile.hip", "sj_device.h", "sj_args.h"],
     "join_": ["k_join.hip", "sj_device.h", "sj_args.h"],
     "rowsort_": ["k_rowsort.hip", "sj_device.h", "sj_args.h"],
+    "brute_": ["k_brute.hip", "sj_device.h", "sj_args.h"],
+    "rs_": ["k_rs.hip", "sj_device.h", "sj_args.h"],
 }
 
 
@@ -152,55 +306,219 @@ def measured_traffic(name, workload):
 
 
 def pipeline_bytes(n, d, cells, pairs):
-    """Algorithmic bytes of the whole path for one eps: read the input,
+    """Algorithmic bytes of the whole path for one join: read the input,
     write and read the cell-ordered copy (24 n d), the point map (4 n), the
     cell tables written and read (32 |G|) and each pair written once (8 P)."""
     return 24 * n * d + 4 * n + 32 * cells + 8 * pairs
 
 
-def cpu_baseline(pts, eps_list, target_s):
-    """The brute-force oracle on a bounded sample of query rows (all n
-    candidates each), on the host's cores, scaled to pairs/s."""
-    from oracle import reference
-    n = pts.shape[0]
-    g = np.random.default_rng(12345)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    pilot_rows = g.choice(n, size=min(n, 256), replace=False)
+# ------------------------------------------------------------ timing helpers
+def timed_steps(fn, steps, torch):
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    reference.count_rows(pts, max(eps_list), pilot_rows)
-    per_row = (time.perf_counter() - t0) / len(pilot_rows)
-    rows_per_eps = int(max(64, min(n, target_s / (per_row * len(eps_list)))))
-    rows = g.choice(n, size=rows_per_eps, replace=False)
+    tot = 0
+    for _ in range(steps):
+        tot += fn()
+    torch.cuda.synchronize()
+    return tot, time.perf_counter() - t0
+
+
+def profiled_step(fn, _lib, torch, select=""):
+    _lib.profile_select(select)
+    _lib.profile_enable(True)
+    fn()
+    torch.cuda.synchronize()
+    _lib.profile_enable(False)
+    _lib.profile_select("")
+    return _lib.profile_read()
+
+
+def sweep_leg(sj, _lib, torch, wl, steps, unicomp=True, precision="fp64", label=""):
+    """Timed steps of a workload plus the roofline of its dominant kernel
+    (events on that kernel's launches of a final step)."""
+    info = wl.size(sj, unicomp, precision)
+    out = torch.empty((wl.max_pairs(), 2), dtype=torch.int32, device="cuda")
+    fn = lambda: wl.step(sj, out, unicomp, precision)  # noqa: E731
+    fn()
+    tot, dt = timed_steps(fn, steps, torch)
+    prof = profiled_step(fn, _lib, torch)
+    mod = modelled(prof, info, wl._last_fill_unicomp)
+    res = {"pairs_per_s": tot / dt, "ms_per_step": 1e3 * dt / steps, "steps": steps,
+           "pairs_per_step": tot // steps, "unicomp": unicomp, "precision": precision,
+           "per_join": [{k: v for k, v in i.items() if k != "row_classes"} for i in info],
+           "kernels_ms": {k: round(v[1], 4) for k, v in prof.items()}}
+    if mod:
+        dom = max(mod, key=lambda k: mod[k][1])
+        r, hbm, valu = roofline_of(dom, *mod[dom])
+        r["traffic"] = measured_traffic(dom, wl.name)
+        res["roofline"] = r
+        res["hbm_roofline"], res["valu_roofline"] = hbm, valu
+    log(f"[bench] {label or wl.name} {precision} unicomp={unicomp}: {res['pairs_per_s']:.4g} pairs/s, "
+        f"{res['ms_per_step']:.3f} ms/step" + (f", {res['roofline']['kernel']} {res['roofline']['bound']} "
+                                                f"frac {res['roofline']['frac']}" if mod else ""))
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
+# ------------------------------------------------------------ host baselines
+def host_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "omp_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
+
+
+def _set_omp_threads(k):
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(k))
+        return True
+    except OSError:
+        return False
+
+
+def cpu_baseline(wl, target_s, threads):
+    """The brute-force oracle on a bounded sample of query rows (all n
+    candidates each) of every join of the workload, on `threads` host
+    threads, scaled to pairs/s."""
+    from oracle import reference
+    _set_omp_threads(threads)
+    g = np.random.default_rng(12345)
+    # pilot: cost per query row of each join
+    per_row = []
+    for j in wl.joins:
+        pts = wl.host(j)
+        rows = g.choice(pts.shape[0], size=16, replace=False)
+        t0 = time.perf_counter()
+        reference.count_rows(pts, j["eps"], rows)
+        per_row.append((time.perf_counter() - t0) / 16)
+    rows_per = max(16, int(target_s / sum(per_row)))
     pairs = 0
     t0 = time.perf_counter()
-    for e in eps_list:
-        pairs += int(reference.count_rows(pts, e, rows).sum())
+    for j in wl.joins:
+        pts = wl.host(j)
+        rows = g.choice(pts.shape[0], size=min(rows_per, pts.shape[0]), replace=False)
+        pairs += int(reference.count_rows(pts, j["eps"], rows).sum())
     dt = time.perf_counter() - t0
+    _set_omp_threads(host_info()["omp_threads"])
     return {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"{rows_per_eps} random query rows x all {n} candidates for each of "
-                      f"{len(eps_list)} eps ({pairs} pairs in {dt:.1f} s); "
-                      f"rate = sample pairs / sample time"}
+            "sample": f"{rows_per} random query rows x all n candidates for each of the {len(wl.joins)} joins "
+                      f"of {wl.name} ({pairs} pairs in {dt:.1f} s); rate = sample pairs / sample time"}
 
 
-def cpu_grid_baseline(pts, eps_list, target_s):
+def cpu_grid_baseline(wl, target_s, threads):
     """The host-core grid join (oracle/cpu_grid_join.c: the same grid method,
-    count then sorted fill) on the whole workload, one eps after another in
-    sweep order until about target_s seconds have passed."""
+    count then sorted fill) on whole joins of the workload, in order, until
+    about target_s seconds have passed."""
     from oracle import reference
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     pairs, done = 0, []
     t0 = time.perf_counter()
-    for e in eps_list:
-        counts, out = reference.grid_join(pts, e)
+    for j in wl.joins:
+        counts, out = reference.grid_join(wl.host(j), j["eps"])
         pairs += out.shape[0]
-        done.append(e)
+        done.append(j["tag"])
         del out
         if time.perf_counter() - t0 > target_s:
             break
     dt = time.perf_counter() - t0
     return {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "cpu_grid_join",
-            "sample": f"whole {pts.shape[0]}-point join with sorted (i,j) output for eps {done} "
-                      f"({pairs} pairs in {dt:.1f} s)"}
+            "sample": f"whole joins {done} of {wl.name} with sorted (i,j) output ({pairs} pairs in {dt:.1f} s)"}
+
+
+# ------------------------------------------------------------ other legs
+def batched_leg(sj, torch, wl, cap):
+    t0 = time.perf_counter()
+    nb, tot = [], 0
+    for j in wl.joins:
+        with sj.Index(wl.x(j), j["eps"]) as ix:
+            bl = []
+            tot += ix.batches(lambda p, np_, b, r0, r1: bl.append(np_), unicomp=True, precision="fp64",
+                              batch_capacity_pairs=cap, min_batches=3)
+            nb.append(len(bl))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"[bench] batched ({cap} pairs): {tot / dt:.4g} pairs/s, batches {nb}")
+    return {"capacity_pairs": cap, "min_batches": 3, "batches_per_join": nb, "pairs_per_s": tot / dt,
+            "ms_per_step": 1e3 * dt, "note": "one pass; every batch delivered in device memory to a callback"}
+
+
+def brute_leg(sj, _lib, torch):
+    """The all-pairs kernel beside the grid join on the same inputs: the
+    10,000-point 2-D workload and a 6-D set whose grid degenerates."""
+    from paper_1803_04120_amd import datagen
+    res = []
+    for (n, d, eps, seed) in ((10_000, 2, 1.0, 1), (200_000, 6, 100.0 / 3.0, 61)):
+        x = torch.from_numpy(datagen.uniform(n, d, seed)).cuda()
+        P = sj.bruteforce(x, eps).shape[0]
+        out = torch.empty((P, 2), dtype=torch.int32, device="cuda")
+        sj.bruteforce(x, eps, out=out)
+        reps = 3 if n > 50_000 else 20
+        _, dt = timed_steps(lambda: sj.bruteforce(x, eps, out=out).shape[0], reps, torch)
+        prof = profiled_step(lambda: sj.bruteforce(x, eps, out=out), _lib, torch)
+        ms_k = sum(v[1] for k, v in prof.items() if k.startswith("brute_"))
+        ops = 2 * n * n * (3 * d - 1)  # count and fill passes
+        _, gdt = timed_steps(lambda: sj.selfjoin(x, eps).shape[0], reps, torch)
+        res.append({"n": n, "d": d, "eps": eps, "pairs": P, "brute_ms": 1e3 * dt / reps,
+                    "brute_pairs_per_s": P * reps / dt, "grid_ms": 1e3 * gdt / reps,
+                    "grid_pairs_per_s": P * reps / gdt,
+                    "roofline": {"bound": "alu", "kernel": "brute_count+brute_fill",
+                                 "achieved": round(ops / (ms_k * 1e-3) / 1e12, 3),
+                                 "peak": round(VALU_PEAK_OPS / 1e12, 3), "unit": "TFLOP/s",
+                                 "frac": round(ops / (ms_k * 1e-3) / VALU_PEAK_OPS, 4)}})
+        log(f"[bench] brute force n={n} d={d}: {1e3 * dt / reps:.3f} ms vs grid {1e3 * gdt / reps:.3f} ms")
+        del out, x
+    torch.cuda.empty_cache()
+    return res
+
+
+def rs_leg(sj, torch):
+    from paper_1803_04120_amd import datagen
+    S = torch.from_numpy(datagen.uniform(2_000_000, 2, 2)).cuda()
+    R = torch.from_numpy(datagen.uniform(1_000_000, 2, 1002)).cuda()
+    out = torch.empty((26_000_000, 2), dtype=torch.int32, device="cuda")
+    per = []
+    for e in (0.04, 0.08, 0.12, 0.16, 0.2):
+        with sj.Index(S, e) as ix:
+            ix.join_rs(R, out=out)
+            reps = 3
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                got = ix.join_rs(R, out=out)
+            torch.cuda.synchronize()
+            per.append((e, int(got.shape[0]), (time.perf_counter() - t0) / reps))
+    tp, tt = sum(p for _, p, _ in per), sum(t for _, _, t in per)
+    log(f"[bench] two-set join: {tp / tt:.4g} pairs/s")
+    return {"queries": 1_000_000, "indexed": 2_000_000, "pairs_per_s": tp / tt, "ms_per_sweep": 1e3 * tt,
+            "per_eps": [{"eps": e, "pairs": p, "ms": round(1e3 * t, 3)} for e, p, t in per],
+            "note": "count + fill + row sort per call (sj_join_rs), index on the 2M uniform 2-D points"}
+
+
+def dbscan_leg(sj, torch, wl):
+    res = []
+    for j in wl.joins:
+        x = wl.x(j)
+        sj.dbscan(x, j["eps"], 50)
+        reps = 3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            labels, nc = sj.dbscan(x, j["eps"], 50)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        noise = int((labels == -1).sum().item())
+        res.append({"join": j["tag"], "n": j["n"], "eps": j["eps"], "min_pts": 50, "ms": round(1e3 * dt, 3),
+                    "clusters": nc, "noise_points": noise, "points_per_s": j["n"] / dt})
+        log(f"[bench] dbscan {j['tag']}: {1e3 * dt:.2f} ms, {nc} clusters")
+    return res
 
 
 def calibrate_eps_gpu(sj, x, k, eps0):
@@ -226,11 +544,14 @@ def serving_leg(args, sj, torch):
     server: n log-uniform in [1e3, 2e6], d uniform in 2..6, uniform or
     clustered points, eps for a target mean neighbour count log-uniform in
     [4, 128], FP32 pre-test path. A closed-loop pass (all requests at once)
-    gives the saturation rate; the open-loop pass runs at 0.7 of it."""
+    gives the saturation rate; open-loop passes run at 0.7 and 0.5 of it.
+    The same requests run one at a time on the plain FP64 path give the
+    reference rate."""
     from paper_1803_04120_amd import datagen
     from paper_1803_04120_amd.serve import Server, run_stream, uniform_eps_for_k
     descs = datagen.serving_requests(args.serve_requests, seed=5)
     reqs = []
+    t0 = time.perf_counter()
     for q in descs:
         pts = datagen.make(q["kind"], q["n"], q["d"], q["seed"])
         x = torch.from_numpy(pts).cuda()
@@ -240,28 +561,54 @@ def serving_leg(args, sj, torch):
         reqs.append({"points": x, "eps": eps, "precision": "fp32_band", "unicomp": True,
                      "expected_pairs": int(q["n"] * (q["k"] + 1)), "n": q["n"], "d": q["d"]})
     torch.cuda.synchronize()
+    log(f"[bench] serving: {len(reqs)} requests prepared in {time.perf_counter() - t0:.1f} s")
+    # the same requests alone, plain FP64 path (and their algorithmic bytes)
+    solo_pairs, alg = 0, 0
+    t0 = time.perf_counter()
+    for r in reqs:
+        with sj.Index(r["points"], r["eps"]) as ix:
+            P = ix.count(unicomp=True, precision="fp64")
+            st = ix.stats()
+            out = torch.empty((max(P, 1), 2), dtype=torch.int32, device="cuda")
+            ix.fill(out)
+            del out
+        solo_pairs += P
+        alg += pipeline_bytes(r["n"], r["d"], st["cells"], P)
+    torch.cuda.synchronize()
+    solo_dt = time.perf_counter() - t0
     budget = 64 << 30
+    res = {"requests": len(reqs), "slots": args.serve_slots, "mem_budget_bytes": budget,
+           "precision": "fp32_band",
+           "n_range": [int(min(r["n"] for r in reqs)), int(max(r["n"] for r in reqs))],
+           "solo_fp64": {"pairs_per_s": solo_pairs / solo_dt, "s": round(solo_dt, 3),
+                         "hbm_frac": round(alg / solo_dt / 1e9 / HBM_PEAK_GBS, 5)}}
     with Server(slots=args.serve_slots, mem_budget_bytes=budget) as srv:
-        # closed loop: everything arrives at t = 0
         done, span = run_stream(srv, reqs, np.zeros(len(reqs)))
         sat = len(reqs) / span
-        rate = 0.7 * sat
-        arr = datagen.poisson_arrivals(len(reqs), rate, seed=6)
-        done, span2 = run_stream(srv, reqs, arr)
-        info = srv.info()
-    lat = np.array([c["latency_ms"] for c in done])
-    pairs = sum(c["npairs"] for c in done)
-    return {"requests": len(reqs), "slots": args.serve_slots, "mem_budget_bytes": budget,
-            "precision": "fp32_band", "saturation_req_per_s": round(sat, 2),
-            "rate_req_per_s": round(rate, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "mean_queue_ms": round(float(np.mean([c["queue_ms"] for c in done])), 3),
-            "pairs_per_s": pairs / span2, "closed_loop_pairs_per_s": pairs / span,
-            "errors": int(sum(c["status"] != 0 for c in done)),
-            "over_estimate": info["over_estimate"],
-            "n_range": [int(min(r["n"] for r in reqs)), int(max(r["n"] for r in reqs))]}
+        res["saturation_req_per_s"] = round(sat, 2)
+        res["closed_loop_pairs_per_s"] = sum(c["npairs"] for c in done) / span
+        for frac in (0.7, 0.5):
+            arr = datagen.poisson_arrivals(len(reqs), frac * sat, seed=6)
+            done, span2 = run_stream(srv, reqs, arr)
+            lat = np.array([c["latency_ms"] for c in done])
+            pairs = sum(c["npairs"] for c in done)
+            res[f"at_{frac}"] = {
+                "rate_req_per_s": round(frac * sat, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "p99_over_p50": round(float(np.percentile(lat, 99) / np.percentile(lat, 50)), 2),
+                "mean_queue_ms": round(float(np.mean([c["queue_ms"] for c in done])), 3),
+                "pairs_per_s": pairs / span2, "vs_solo_fp64": round((pairs / span2) / (solo_pairs / solo_dt), 3),
+                "hbm_frac": round(alg / span2 / 1e9 / HBM_PEAK_GBS, 5),
+                "errors": int(sum(c["status"] != 0 for c in done))}
+            log(f"[bench] serving at {frac} x saturation: p50 {res[f'at_{frac}']['p50_ms']} ms, "
+                f"p99 {res[f'at_{frac}']['p99_ms']} ms, {pairs / span2:.4g} pairs/s")
+        res["over_estimate"] = srv.info()["over_estimate"]
+    del reqs
+    torch.cuda.empty_cache()
+    return res
 
 
+# ------------------------------------------------------------ main
 def main():
     args = parse()
     if args.gpus != 1:
@@ -273,76 +620,32 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     import paper_1803_04120_amd as sj
-    from paper_1803_04120_amd import _lib, datagen
+    from paper_1803_04120_amd import _lib
 
-    wl = WORKLOADS[args.workload]
-    n, d = wl["n"], wl["d"]
-    eps_list = list(wl["eps"])
-    pts = datagen.make(wl["kind"], n, d, wl["seed"])
-    x = torch.from_numpy(pts).to("cuda")
-    stream = torch.cuda.current_stream()
-
-    # sizes per eps (also warms the library's memory pool)
-    info = []
-    for e in eps_list:
-        with sj.Index(x, e) as ix:
-            P = ix.count(unicomp=bool(args.unicomp), precision=args.precision)
-            st = ix.stats()
-            info.append(dict(eps=e, pairs=P, cells=st["cells"], ranges=st["ranges"],
-                             evals=st["evals"], band_rechecks=st["band_rechecks"],
-                             max_cell=st["max_cell_points"], key_bits=st["key_bits"]))
-    maxP = max(i["pairs"] for i in info)
-    out = torch.empty((maxP, 2), dtype=torch.int32, device="cuda")
+    W = workloads()
+    t_start = time.perf_counter()
+    wl = Workload(args.workload, W[args.workload], torch)
+    log(f"[bench] workload {args.workload}: {len(wl.joins)} joins, points generated")
+    uni, prec = bool(args.unicomp), args.precision
+    info = wl.size(sj, uni, prec)
+    for i in info:
+        log(f"[bench]   {i['tag']}: n={i['n']} d={i['d']} eps={i['eps']} pairs={i['pairs']} evals={i['evals']}")
+    out = torch.empty((wl.max_pairs(), 2), dtype=torch.int32, device="cuda")
 
     def step():
-        total = 0
-        for e in eps_list:
-            with sj.Index(x, e) as ix:
-                P = ix.count(unicomp=bool(args.unicomp), precision=args.precision)
-                ix.fill(out)
-                total += P
-        return total
+        return wl.step(sj, out, uni, prec)
 
     for _ in range(args.warmup):
         step()
-    # wall time of each ABI call for one step (calls return after their device work)
-    host_ms = {"build": 0.0, "count": 0.0, "fill": 0.0, "destroy": 0.0}
-    for e in eps_list:
-        t_a = time.perf_counter()
-        ix = sj.Index(x, e)
-        t_b = time.perf_counter()
-        ix.count(unicomp=bool(args.unicomp), precision=args.precision)
-        t_c = time.perf_counter()
-        ix.fill(out)
-        t_d = time.perf_counter()
-        ix.close()
-        t_e = time.perf_counter()
-        for k, v in zip(host_ms, (t_b - t_a, t_c - t_b, t_d - t_c, t_e - t_d)):
-            host_ms[k] += 1e3 * v
-    log("[bench] per-step call wall times (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in host_ms.items()))
     torch.cuda.synchronize()
     # every kernel of one untimed step (for the log), which also names the
     # dominant modelled kernel: the one the timed region times with events
-    _lib.profile_select("")
-    _lib.profile_enable(True)
-    step()
-    torch.cuda.synchronize()
-    _lib.profile_enable(False)
-    all_prof = _lib.profile_read()
+    all_prof = profiled_step(step, _lib, torch)
     log("[bench] all kernels of one step:")
     for k, (cnt, ms) in sorted(all_prof.items(), key=lambda kv: -kv[1][1]):
-        log(f"[bench]   {k:28s} launches={cnt:6d} total={ms:9.3f} ms avg={1e3 * ms / cnt:9.2f} us")
-
-    def modelled_of(prof, steps):
-        out = {}
-        for name, (cnt, ms) in prof.items():
-            per_step = [kernel_bytes(name, n, d, i["cells"], i["ranges"], i["pairs"]) for i in info]
-            if None in per_step:
-                continue
-            out[name] = (cnt, ms, sum(per_step) * steps)
-        return out
-
-    first = modelled_of(all_prof, 1)
+        log(f"[bench]   {k:30s} launches={cnt:6d} total={ms:9.3f} ms avg={1e3 * ms / cnt:9.2f} us")
+    fill_flags = list(wl._last_fill_unicomp)
+    first = modelled(all_prof, info, fill_flags)
     if not first:
         raise RuntimeError(f"no modelled kernel among {sorted(all_prof)}")
     dom = max(first, key=lambda k: first[k][1])
@@ -366,65 +669,53 @@ def main():
     ms_per_step = 1e3 * dt / args.steps
     value = pairs_total / dt
     log(f"[bench] {args.steps} steps in {dt:.3f}s, {ms_per_step:.3f} ms/step, {value:.4g} pairs/s")
-
-    # roofline of the dominant kernel, from the timed region's events
-    modelled = modelled_of(prof, 1)
-    if dom not in modelled:
+    mod = modelled(prof, info, fill_flags)
+    if dom not in mod:
         raise RuntimeError(f"the timed region recorded no launch of {dom}")
-    cnt, ms, byts = modelled[dom]
-    achieved = byts / (ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom, args.workload),
-                "avg_launch_us": round(1e3 * ms / cnt, 3),
-                "bytes_per_launch": int(byts / cnt)}
-    pipe = sum(pipeline_bytes(n, d, i["cells"], i["pairs"]) for i in info)
+    roofline, hbm_r, valu_r = roofline_of(dom, *mod[dom])
+    roofline["traffic"] = measured_traffic(dom, args.workload)
+    pipe = sum(pipeline_bytes(i["n"], i["d"], i["cells"], i["pairs"]) for i in info)
+    ops_step = sum(mod_i[3] for mod_i in first.values())
     pipeline = {"alg_bytes_per_step": pipe, "achieved_GBs": round(pipe / (ms_per_step * 1e-3) / 1e9, 2),
-                "frac_of_hbm_peak": round(pipe / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                "frac_of_hbm_peak": round(pipe / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "alg_fp64_ops_per_step": ops_step,
+                "frac_of_valu_peak": round(ops_step / (ms_per_step * 1e-3) / VALU_PEAK_OPS, 4)}
+    del out
+    torch.cuda.empty_cache()
 
-    # two-set join: n/2 independent queries (the workload distribution) against the
-    # indexed workload points, at each eps (index built outside the timing)
-    rs = None
-    if not args.no_rs:
-        qpts = datagen.make(wl["kind"], n // 2, d, wl["seed"] + 1000)
-        qx = torch.from_numpy(qpts).to("cuda")
-        rs_out = torch.empty((max(i["pairs"] for i in info), 2), dtype=torch.int32, device="cuda")
-        per = []
-        for e in eps_list:
-            with sj.Index(x, e) as ix:
-                ix.join_rs(qx, out=rs_out)  # warm
-                torch.cuda.synchronize()
+    legs = {}
+    if not args.no_legs:
+        if args.workload == DEFAULT_WORKLOAD:
+            legs["unicomp_off"] = sweep_leg(sj, _lib, torch, wl, 2, unicomp=False, label="unicomp off")
+            legs["unicomp_off"]["vs_unicomp_on"] = round(legs["unicomp_off"]["pairs_per_s"] / value, 4)
+            legs["batched"] = batched_leg(sj, torch, wl, 1 << 27)
+            legs["batched"]["vs_unbatched"] = round(legs["batched"]["pairs_per_s"] / value, 4)
+        for name, key, steps in (("clustered_5M", "clustered_n5M_d2-3_median50", 3),
+                                 ("uniform2d_2M", "uniform2d_n2M_eps_sweep", 20),
+                                 ("uniform2d_10k", "uniform2d_n10k_eps1", 50)):
+            if key == args.workload:
+                continue
+            w2 = Workload(key, W[key], torch)
+            legs[name] = {"workload": key, "fp64": sweep_leg(sj, _lib, torch, w2, steps, label=key)}
+            if name == "clustered_5M":
+                b = sweep_leg(sj, _lib, torch, w2, steps, precision="fp32_band", label=key)
+                b["vs_fp64"] = round(b["pairs_per_s"] / legs[name]["fp64"]["pairs_per_s"], 4)
+                legs[name]["fp32_band"] = b
+                legs["dbscan"] = dbscan_leg(sj, torch, w2)
+            if name == "uniform2d_10k" and not args.no_cpu_baseline:
+                from oracle import reference
+                j = w2.joins[0]
                 t0 = time.perf_counter()
-                reps = 3
-                for _ in range(reps):
-                    got = ix.join_rs(qx, out=rs_out)
-                torch.cuda.synchronize()
-                per.append((e, int(got.shape[0]), (time.perf_counter() - t0) / reps))
-        tot_p = sum(p for _, p, _ in per)
-        tot_t = sum(t for _, _, t in per)
-        rs = {"queries": int(qpts.shape[0]), "indexed": n, "pairs_per_s": tot_p / tot_t,
-              "ms_per_sweep": 1e3 * tot_t,
-              "per_eps": [{"eps": e, "pairs": p, "ms": round(1e3 * t, 3)} for e, p, t in per],
-              "note": "count + fill + row sort per call (sj_join_rs), index on the workload points"}
-        log(f"[bench] two-set join: {rs['pairs_per_s']:.4g} pairs/s, {rs['ms_per_sweep']:.3f} ms per sweep")
-
-    batched = None
-    if not args.no_batched:
-        cap = args.batch_capacity
-        t0 = time.perf_counter()
-        nb = []
-        tot = 0
-        for e in eps_list:
-            with sj.Index(x, e) as ix:
-                batches = []
-                tot += ix.batches(lambda p, np_, b, r0, r1: batches.append(np_),
-                                  unicomp=bool(args.unicomp), precision=args.precision,
-                                  batch_capacity_pairs=cap, min_batches=1)
-                nb.append(len(batches))
-        torch.cuda.synchronize()
-        bdt = time.perf_counter() - t0
-        batched = {"capacity_pairs": cap, "batches_per_eps": nb, "pairs_per_s": tot / bdt,
-                   "note": "one untimed-by-events pass, batches delivered in device memory"}
+                P = reference.pairs(w2.host(j), j["eps"]).shape[0]
+                legs[name]["cpu_oracle_full"] = {"value": P / (time.perf_counter() - t0), "unit": "pairs/s",
+                                                 "cores": host_info()["omp_threads"], "kind": "oracle",
+                                                 "sample": "the whole 10,000-point join"}
+            del w2
+            torch.cuda.empty_cache()
+        legs["brute_force"] = brute_leg(sj, _lib, torch)
+        legs["rs_join"] = rs_leg(sj, torch)
+        if not args.no_serve:
+            legs["serving"] = serving_leg(args, sj, torch)
 
     if args.calib_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -435,55 +726,14 @@ def main():
         log("[bench] calibration copy: 3 x 1 GiB read + 1 GiB written")
         del src, dst
 
-    # the same sweep with the FP32 pre-test and FP64 band re-decision
-    band = None
-    if not args.no_band and args.precision == "fp64":
-        def step_band():
-            total = 0
-            for e in eps_list:
-                with sj.Index(x, e) as ix:
-                    P = ix.count(unicomp=bool(args.unicomp), precision="fp32_band")
-                    ix.fill(out)
-                    total += P
-            return total
-        step_band()
-        torch.cuda.synchronize()
-        _lib.profile_select("tiled_fill")  # events on the last step's fill launches only
-        t0 = time.perf_counter()
-        bp = 0
-        for k in range(args.steps):
-            if k == args.steps - 1:
-                _lib.profile_enable(True)
-            bp += step_band()
-        torch.cuda.synchronize()
-        bdt = time.perf_counter() - t0
-        _lib.profile_enable(False)
-        _lib.profile_select("")
-        bprof = _lib.profile_read()
-        fills = {k: v for k, v in bprof.items() if k.startswith("tiled_fill")}
-        band = {"pairs_per_s": bp / bdt, "ms_per_step": 1e3 * bdt / args.steps,
-                "vs_fp64": (bp / bdt) / value, "kernels_ms": {k: round(v[1], 4) for k, v in bprof.items()}}
-        if fills:
-            fk = max(fills, key=lambda k: fills[k][1])
-            cnt, ms = fills[fk]
-            byts = sum(kernel_bytes(fk, n, d, i["cells"], i["ranges"], i["pairs"]) for i in info)
-            ach = byts / (ms * 1e-3) / 1e9
-            band["roofline"] = {"kernel": fk, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_us": round(1e3 * ms / cnt, 3),
-                                "traffic": measured_traffic(fk, args.workload)}
-        log(f"[bench] fp32+band: {band['pairs_per_s']:.4g} pairs/s ({band['vs_fp64']:.3f} x fp64)")
-
-    serving = None
-    if not args.no_serve:
-        serving = serving_leg(args, sj, torch)
-        log(f"[bench] serving: p50 {serving['p50_ms']} ms p99 {serving['p99_ms']} ms at "
-            f"{serving['rate_req_per_s']} req/s, {serving['pairs_per_s']:.4g} pairs/s")
-
-    cpu = cpu_grid = None
+    cpu = cpu1 = cpu_grid = None
+    hi = host_info()
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(pts, eps_list, args.cpu_seconds)
+        cpu = cpu_baseline(wl, args.cpu_seconds, hi["omp_threads"])
         log(f"[bench] cpu oracle baseline {cpu['value']:.4g} pairs/s on {cpu['cores']} threads")
-        cpu_grid = cpu_grid_baseline(pts, eps_list, args.cpu_seconds)
+        cpu1 = cpu_baseline(wl, args.cpu_seconds / 2, 1)
+        log(f"[bench] cpu oracle baseline {cpu1['value']:.4g} pairs/s on 1 thread")
+        cpu_grid = cpu_grid_baseline(wl, args.cpu_seconds, hi["omp_threads"])
         log(f"[bench] cpu grid-join baseline {cpu_grid['value']:.4g} pairs/s on {cpu_grid['cores']} threads")
 
     rec = {
@@ -497,24 +747,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64" if prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "distribution": wl["kind"], "n": n, "d": d,
-                   "eps": eps_list, "unicomp": bool(args.unicomp), "precision": args.precision,
-                   "output": "sorted (i,j) pairs in HBM"},
+        "config": {"workload": args.workload, "joins": [f"{i['tag']} (n={i['n']}, d={i['d']}, eps={i['eps']})"
+                                                        for i in info],
+                   "unicomp": uni, "precision": prec, "output": "sorted (i,j) pairs in HBM"},
         "roofline": roofline,
+        "hbm_roofline": hbm_r,
+        "valu_roofline": valu_r,
+        "pipeline": pipeline,
         "cpu_baseline": cpu,
+        "cpu_baseline_1core": cpu1,
         "cpu_grid_baseline": cpu_grid,
-        "fp32_band": band,
-        "pipeline_hbm": pipeline,
-        "per_eps": info,
-        "batched": batched,
-        "rs_join": rs,
-        "serving": serving,
+        "host": hi,
+        "per_join": [{k: v for k, v in i.items() if k != "row_classes"} for i in info],
         "kernels_ms": {k: round(v[1], 4) for k, v in all_prof.items()},
-        "call_wall_ms": {k: round(v, 3) for k, v in host_ms.items()},
+        "legs": legs,
+        "bench_wall_s": round(time.perf_counter() - t_start, 1),
     }
-    del stream
     print(json.dumps(rec), flush=True)
 
 

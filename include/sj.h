@@ -59,10 +59,16 @@ typedef struct sj_join_opts {
     int32_t  precision;            /* SJ_FP64 or SJ_FP32_BAND */
     uint64_t batch_capacity_pairs; /* max pairs per delivered batch; 0 = no limit */
     uint32_t min_batches;          /* at least this many batches (Section V-A uses 3) */
-    int32_t  reserved;             /* must be 0 */
+    int32_t  sort_output;          /* 1: every row's j ascending, so the pairs are sorted
+                                      by (i, j) (the key/value sort of Section IV-E);
+                                      0: rows still in ascending i with the row offsets
+                                      of the sorted form, but the j of a row in an
+                                      unspecified order (the separate row-sort kernels
+                                      are replaced by a plain row move) */
 } sj_join_opts;
 
-/* Fills *o with unicomp=1, precision=SJ_FP64, no capacity limit, 1 batch. */
+/* Fills *o with unicomp=1, precision=SJ_FP64, no capacity limit, 1 batch,
+ * sort_output=1. */
 void sj_default_opts(sj_join_opts *o);
 
 /* ---- statistics --------------------------------------------------------- */
@@ -108,7 +114,9 @@ typedef struct sj_index sj_index;
 int sj_build_index(const double *pts, uint64_t n, uint32_t d, double eps,
                    int pts_on_device, void *stream, sj_index **out);
 
-/* Releases the index and its device memory (NULL is ignored). */
+/* Releases the index of Section IV-C (B, G, A, M and the cell-ordered
+ * points) and all its device memory. NULL is ignored. The caller must not
+ * use the index afterwards, and no call on it may still be running. */
 void sj_destroy_index(sj_index *idx);
 
 /*
@@ -129,6 +137,46 @@ int sj_join_fill(sj_index *idx, uint32_t *pairs_dev, uint64_t capacity_pairs,
                  void *stream);
 
 /*
+ * Fill pass into a compressed sparse row (CSR) neighbour table instead of
+ * pairs: row_off_dev receives n + 1 uint64 row offsets (row i holds
+ * cols_dev[row_off[i] .. row_off[i+1]), row_off[n] = P) and cols_dev the P
+ * neighbour ids j, 4 bytes per entry instead of the 8 of an (i, j) pair --
+ * the neighbour table that the DBSCAN use of the self-join consumes
+ * (Section I; the batching of Section V-A comes from that use). Rows hold
+ * the same j as the pair form: ascending if the count pass's
+ * opts->sort_output was 1, else in an unspecified order. Both buffers are
+ * device memory owned by the caller; capacity is the entries cols_dev holds
+ * (SJ_ECAPACITY if below P, nothing written). Needs a preceding
+ * sj_join_count, like sj_join_fill.
+ */
+int sj_join_fill_csr(sj_index *idx, uint64_t *row_off_dev, uint32_t *cols_dev, uint64_t capacity,
+                     void *stream);
+
+/*
+ * DBSCAN (Ester et al.; the clustering Section I names as a user of the
+ * self-join) over a CSR neighbour table as sj_join_fill_csr writes it: row i
+ * lists every point within eps of point i, i itself included, so i is a
+ * core point when its row holds at least min_pts entries. labels_dev (n
+ * int32, device, caller-owned) receives for a core point the smallest index
+ * of the core points of its cluster (clusters are the connected components
+ * of core points joined by table entries), for a border point (not core,
+ * with a core point in its row) the label of the smallest-index core point
+ * in its row, and -1 for noise. *nclusters receives the number of clusters.
+ * The order of j within a row does not matter. n < 2^31, min_pts >= 1.
+ */
+int sj_dbscan_csr(const uint64_t *row_off_dev, const uint32_t *cols_dev, uint64_t n, uint32_t min_pts,
+                  int32_t *labels_dev, void *stream, uint64_t *nclusters);
+
+/*
+ * DBSCAN of n points in one call: the grid index and count pass (unicomp),
+ * the CSR fill with unsorted rows into library scratch (4 bytes per pair),
+ * then sj_dbscan_csr's labelling into labels_dev. Arguments as for
+ * sj_build_index and sj_dbscan_csr.
+ */
+int sj_dbscan(const double *pts, uint64_t n, uint32_t d, double eps, uint32_t min_pts, int pts_on_device,
+              int32_t *labels_dev, void *stream, uint64_t *nclusters);
+
+/*
  * Distance join of a query set R with the indexed set S (Section II: the
  * self-join is the case R = S; the pair test is Section III's, as for the
  * self-join). R is nr x d row-major FP64 with the index's d, in device
@@ -145,15 +193,19 @@ int sj_join_rs(sj_index *idx, const double *R, uint64_t nr, int r_on_device, uin
                uint64_t capacity_pairs, void *stream, uint64_t *total_pairs);
 
 /*
- * Batched join (Section V-A). The result rows are split into at least
- * opts->min_batches consecutive ranges of i, each holding at most
- * opts->batch_capacity_pairs pairs; every batch is delivered, in order of i,
- * to cb(user, pairs_dev, npairs, batch_id, row_begin, row_end) as a device
- * buffer of npairs sorted pairs that stays valid until cb returns. The
- * batches partition the result and their concatenation is sorted by (i, j).
- * While cb runs, the next batch is already being computed. A non-zero return
- * from cb stops the join and is returned. The library owns the buffers.
- * SJ_ECAPACITY if one result row alone exceeds the batch capacity.
+ * Batched join (Section V-A): the result is delivered in at least
+ * opts->min_batches runs of at most opts->batch_capacity_pairs pairs each,
+ * sized from the exact row lengths of the count pass. Run b holds every
+ * result row of the points at positions [row_begin, row_end) of the index's
+ * cell order (SJ_EXPORT_PERM maps a position to its point id), sorted by
+ * (i, j) within the run; the runs partition the result, and merging them
+ * gives the sorted result. A run is passed to cb(user, pairs_dev, npairs,
+ * batch_id, row_begin, row_end) as a device buffer that stays valid until
+ * cb returns; while cb runs, the next run is already being computed. A
+ * non-zero return from cb stops the join and is returned. The library owns
+ * the buffers. SJ_ECAPACITY if one result row alone exceeds the capacity.
+ * Runs are whole grid-row chunks of the tiled join when the capacity holds
+ * 128 times the longest row, else ranges of single points.
  */
 typedef int (*sj_run_cb)(void *user, const uint32_t *pairs_dev, uint64_t npairs,
                          uint32_t batch_id, uint64_t row_begin, uint64_t row_end);
@@ -162,20 +214,61 @@ int sj_selfjoin_index(sj_index *idx, const sj_join_opts *opts, sj_run_cb cb,
                       void *user, void *stream, uint64_t *total_pairs);
 
 /*
- * Convenience: build, join and return all pairs sorted by (i, j) in a buffer
- * allocated by the library -- device memory if out_on_device, else pinned
- * host memory filled batch by batch while later batches compute. Release it
+ * Convenience: the whole self-join of Section III in one call -- the index
+ * of Section IV-B/IV-C, the count and fill passes of Algorithm 1 (unicomp of
+ * Section V-B per opts) -- returning all pairs sorted by (i, j) in a buffer
+ * allocated by the library: device memory if out_on_device, else pinned
+ * host memory filled batch by batch while later batches compute (the
+ * result transfer overlapped with computation, Section V-A). Release it
  * with sj_free. *pairs_out is NULL when *npairs is 0.
+ *   pts, n, d, eps   as for sj_build_index (pts_on_device selects device or
+ *                    host memory); opts as for sj_join_count (NULL:
+ *                    sj_default_opts).
+ * Statistics of the run: sj_last_run_stats on the same thread.
  */
 int sj_selfjoin(const double *pts, uint64_t n, uint32_t d, double eps,
                 const sj_join_opts *opts, int pts_on_device, int out_on_device,
                 void *stream, uint32_t **pairs_out, uint64_t *npairs);
 
-/* Frees a buffer returned by sj_selfjoin (device or pinned host; NULL ignored). */
+/* Frees a result buffer that sj_selfjoin allocated (device or pinned host
+ * memory, the two placements of a Section V-A result). NULL and pointers the
+ * library did not hand out are ignored. */
 void sj_free(void *ptr);
 
-/* Statistics of the index and of its last join. */
+/*
+ * Statistics of the index (|G| of Section IV-C, the grid |g_j| of Section
+ * IV-B, the largest cell) and of the last join run on it (evaluations, band
+ * re-decisions, pairs, batches, times). Host-side state only: no device
+ * work, and it may be called while no call on the index runs.
+ */
 int sj_index_stats(const sj_index *idx, sj_stats *out);
+
+/*
+ * Statistics of the last join run on the calling thread, whatever produced
+ * it: a count or fill pass, the batched join (Section V-A), the convenience
+ * sj_selfjoin (whose index is gone when it returns), the two-set join or the
+ * brute force (whose evals is n^2). Fields a run does not produce are 0.
+ * SJ_ESTATE if no join has run on this thread.
+ */
+int sj_last_run_stats(sj_stats *out);
+
+/*
+ * All-pairs join, the GPU brute-force comparison of Section VI-B: every
+ * point is compared with every point (n^2 evaluations of the Section III
+ * pair test, with no index), giving the same result as the grid join: every
+ * ordered pair (i, j) with d2 <= fl(eps * eps), sorted by (i, j).
+ *   pts             n x d row-major binary64, device memory if pts_on_device,
+ *                   else host memory (copied to the device); not retained.
+ *   pairs_dev       device buffer for the pairs (2 * capacity_pairs uint32),
+ *                   owned by the caller, or NULL to compute only P.
+ *   *total_pairs    receives P (also when SJ_ECAPACITY is returned, in which
+ *                   case nothing is written to pairs_dev).
+ * Non-finite coordinates are not rejected: a point with a NaN or infinite
+ * coordinate has a NaN or infinite distance to every point, itself included,
+ * so it takes part in no pair. The cost is n^2 evaluations whatever eps is.
+ */
+int sj_bruteforce(const double *pts, uint64_t n, uint32_t d, double eps, int pts_on_device,
+                  uint32_t *pairs_dev, uint64_t capacity_pairs, void *stream, uint64_t *total_pairs);
 
 /*
  * Copies an internal array of the index to host memory (tests, debugging).

@@ -17,7 +17,8 @@ import numpy as np
 from . import _lib
 from ._lib import SjError  # noqa: F401
 
-__all__ = ["Index", "selfjoin", "band_thresholds", "SjError", "version"]
+__all__ = ["Index", "selfjoin", "bruteforce", "dbscan", "dbscan_csr", "band_thresholds", "last_run_stats",
+           "SjError", "version"]
 
 
 def _torch():
@@ -70,10 +71,11 @@ class Index:
         self._counted = None
 
     # ---------------------------------------------------------------- join
-    def count(self, unicomp: bool = True, precision: str = "fp64") -> int:
-        """Count pass: result size P (rows and offsets stay on the device)."""
+    def count(self, unicomp: bool = True, precision: str = "fp64", sort_output: bool = True) -> int:
+        """Count pass: result size P (rows and offsets stay on the device).
+        sort_output=False lets the fill leave each row's j unsorted."""
         L = _lib.load()
-        o = _lib.opts(unicomp, precision)
+        o = _lib.opts(unicomp, precision, sort_output=sort_output)
         total = ctypes.c_uint64(0)
         _lib.check(L.sj_join_count(self._h, ctypes.byref(o), _stream_handle(self._stream),
                                    ctypes.byref(total)))
@@ -95,6 +97,22 @@ class Index:
         _lib.check(L.sj_join_fill(self._h, ctypes.c_void_p(out.data_ptr() if P else 0),
                                   P, _stream_handle(self._stream)))
         return out[:P] if out.shape[0] != P else out
+
+    def fill_csr(self):
+        """Fill pass after count() into a CSR neighbour table: (row_off int64
+        (n + 1,), cols int32 (P,)) device tensors; row i's neighbours are
+        cols[row_off[i]:row_off[i + 1]]."""
+        torch = _torch()
+        if self._counted is None:
+            raise RuntimeError("fill_csr() needs count() first")
+        P = self._counted
+        dev = self._device or torch.device("cuda")
+        row_off = torch.empty((self.n + 1,), dtype=torch.int64, device=dev)
+        cols = torch.empty((max(P, 1),), dtype=torch.int32, device=dev)
+        _lib.check(_lib.load().sj_join_fill_csr(self._h, ctypes.c_void_p(row_off.data_ptr()),
+                                                ctypes.c_void_p(cols.data_ptr()), P,
+                                                _stream_handle(self._stream)))
+        return row_off, cols[:P]
 
     def join_rs(self, queries, out=None):
         """Distance join of the query rows (float64 (nr, d), host or device)
@@ -136,7 +154,9 @@ class Index:
     def batches(self, callback, unicomp: bool = True, precision: str = "fp64",
                 batch_capacity_pairs: int = 0, min_batches: int = 1) -> int:
         """Batched join: callback(pairs_ptr, npairs, batch_id, row_begin, row_end)
-        is called per batch with a device pointer valid during the call.
+        is called per run with a device pointer valid during the call. A run
+        holds the rows of the cell-ordered positions [row_begin, row_end),
+        sorted by (i, j) within the run; the runs partition the result.
         Returns the total number of pairs."""
         L = _lib.load()
         o = _lib.opts(unicomp, precision, batch_capacity_pairs, min_batches)
@@ -160,8 +180,9 @@ class Index:
 
     def join_batched(self, unicomp: bool = True, precision: str = "fp64",
                      batch_capacity_pairs: int = 0, min_batches: int = 1):
-        """Batched join gathered into one (P, 2) int32 device tensor; also
-        returns the list of (batch_id, row_begin, row_end, npairs)."""
+        """Batched join gathered into one (P, 2) int32 device tensor, the runs
+        one after another (each sorted by (i, j) within itself); also returns
+        the list of (batch_id, row_begin, row_end, npairs)."""
         torch = _torch()
         chunks, info = [], []
 
@@ -245,6 +266,73 @@ def selfjoin(points, eps: float, *, unicomp: bool = True, precision: str = "fp64
     tensor sorted by (i, j). points: (n, d) float64 CUDA tensor."""
     with Index(points, eps, stream=stream) as ix:
         return ix.join(unicomp=unicomp, precision=precision)
+
+
+def bruteforce(points, eps: float, *, out=None, stream=None):
+    """All-pairs join (no index, n^2 evaluations of the same pair test):
+    (P, 2) int32 device tensor sorted by (i, j). points: (n, d) float64,
+    host or device. With `out` (a contiguous int32 device tensor) the pairs
+    go there in one call when it has room; without it the count pass runs
+    twice (once to size the result)."""
+    torch = _torch()
+    L = _lib.load()
+    ptr, n, d, on_dev, keep = _points_arg(points)
+    total = ctypes.c_uint64(0)
+    sh = _stream_handle(stream)
+    if out is not None:
+        if out.dtype != torch.int32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 tensor")
+        rc = L.sj_bruteforce(ptr, n, d, float(eps), on_dev, ctypes.c_void_p(out.data_ptr()),
+                             out.numel() // 2, sh, ctypes.byref(total))
+        if rc == _lib.SJ_ECAPACITY:
+            raise ValueError(f"out has room for {out.numel() // 2} pairs, the result has {total.value}")
+        _lib.check(rc)
+        P = int(total.value)
+        del keep
+        return out[:P] if out.shape[0] != P else out
+    _lib.check(L.sj_bruteforce(ptr, n, d, float(eps), on_dev, None, 0, sh, ctypes.byref(total)))
+    P = int(total.value)
+    dev = points.device if getattr(points, "is_cuda", False) else torch.device("cuda")
+    res = torch.empty((P, 2), dtype=torch.int32, device=dev)
+    if P:
+        _lib.check(L.sj_bruteforce(ptr, n, d, float(eps), on_dev, ctypes.c_void_p(res.data_ptr()), P, sh,
+                                   ctypes.byref(total)))
+    del keep
+    return res
+
+
+def dbscan_csr(row_off, cols, min_pts: int, stream=None):
+    """DBSCAN labels (int32 device tensor, -1 = noise; a cluster is labelled
+    by its smallest core index) and the cluster count, from a CSR neighbour
+    table (row_off int64 (n + 1,), cols int32, device tensors)."""
+    torch = _torch()
+    n = int(row_off.shape[0]) - 1
+    labels = torch.empty((max(n, 0),), dtype=torch.int32, device=row_off.device)
+    nc = ctypes.c_uint64(0)
+    _lib.check(_lib.load().sj_dbscan_csr(ctypes.c_void_p(row_off.data_ptr()), ctypes.c_void_p(cols.data_ptr()),
+                                         n, int(min_pts), ctypes.c_void_p(labels.data_ptr()),
+                                         _stream_handle(stream), ctypes.byref(nc)))
+    return labels, int(nc.value)
+
+
+def dbscan(points, eps: float, min_pts: int, stream=None):
+    """DBSCAN of (n, d) float64 points (host or device) at radius eps:
+    (labels int32 device tensor, number of clusters)."""
+    torch = _torch()
+    ptr, n, d, on_dev, keep = _points_arg(points)
+    dev = points.device if getattr(points, "is_cuda", False) else torch.device("cuda")
+    labels = torch.empty((n,), dtype=torch.int32, device=dev)
+    nc = ctypes.c_uint64(0)
+    _lib.check(_lib.load().sj_dbscan(ptr, n, d, float(eps), int(min_pts), on_dev,
+                                     ctypes.c_void_p(labels.data_ptr()), _stream_handle(stream),
+                                     ctypes.byref(nc)))
+    del keep
+    return labels, int(nc.value)
+
+
+def last_run_stats() -> dict:
+    """Statistics of the last join run on the calling thread."""
+    return _lib.last_run_stats()
 
 
 def band_thresholds(d: int, eps: float, extent: float):

@@ -41,7 +41,7 @@ class SjJoinOpts(ctypes.Structure):
                 ("precision", ctypes.c_int32),
                 ("batch_capacity_pairs", ctypes.c_uint64),
                 ("min_batches", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32)]
+                ("sort_output", ctypes.c_int32)]
 
 
 class SjStats(ctypes.Structure):
@@ -106,6 +106,9 @@ def load():
         "sj_join_count": (ctypes.c_int, [vp, ctypes.POINTER(SjJoinOpts), vp,
                                          ctypes.POINTER(ctypes.c_uint64)]),
         "sj_join_fill": (ctypes.c_int, [vp, vp, u64, vp]),
+        "sj_join_fill_csr": (ctypes.c_int, [vp, vp, vp, u64, vp]),
+        "sj_dbscan_csr": (ctypes.c_int, [vp, vp, u64, u32, vp, vp, ctypes.POINTER(u64)]),
+        "sj_dbscan": (ctypes.c_int, [vp, u64, u32, dbl, u32, ctypes.c_int, vp, vp, ctypes.POINTER(u64)]),
         "sj_join_rs": (ctypes.c_int, [vp, vp, u64, ctypes.c_int, vp, u64, vp, ctypes.POINTER(u64)]),
         "sj_selfjoin_index": (ctypes.c_int, [vp, ctypes.POINTER(SjJoinOpts), RUN_CB, vp, vp,
                                              ctypes.POINTER(ctypes.c_uint64)]),
@@ -114,6 +117,8 @@ def load():
                                        ctypes.POINTER(ctypes.c_uint64)]),
         "sj_free": (None, [vp]),
         "sj_index_stats": (ctypes.c_int, [vp, ctypes.POINTER(SjStats)]),
+        "sj_last_run_stats": (ctypes.c_int, [ctypes.POINTER(SjStats)]),
+        "sj_bruteforce": (ctypes.c_int, [vp, u64, u32, dbl, ctypes.c_int, vp, u64, vp, ctypes.POINTER(u64)]),
         "sj_index_export_size": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]),
         "sj_index_export": (ctypes.c_int, [vp, ctypes.c_int, vp, u64]),
         "sj_index_search": (ctypes.c_int, [vp, ctypes.c_int, vp]),
@@ -142,7 +147,7 @@ def check(rc: int):
 
 
 def opts(unicomp: bool = True, precision: str = "fp64", batch_capacity_pairs: int = 0,
-         min_batches: int = 1) -> SjJoinOpts:
+         min_batches: int = 1, sort_output: bool = True) -> SjJoinOpts:
     o = SjJoinOpts()
     load().sj_default_opts(ctypes.byref(o))
     o.unicomp = 1 if unicomp else 0
@@ -154,7 +159,7 @@ def opts(unicomp: bool = True, precision: str = "fp64", batch_capacity_pairs: in
         raise ValueError(f"unknown precision {precision!r}")
     o.batch_capacity_pairs = int(batch_capacity_pairs or 0)
     o.min_batches = int(max(1, min_batches))
-    o.reserved = 0
+    o.sort_output = 1 if sort_output else 0
     return o
 
 
@@ -166,6 +171,13 @@ def stats_dict(st: SjStats) -> dict:
             v = [int(x) for x in v][: st.d]
         out[name] = v
     return out
+
+
+def last_run_stats() -> dict:
+    """Statistics of the last join run on this thread (sj_last_run_stats)."""
+    st = SjStats()
+    check(load().sj_last_run_stats(ctypes.byref(st)))
+    return stats_dict(st)
 
 
 def profile_enable(on: bool = True):

@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kThreads) void k_join_guarded(JoinArgs a) {
     const bool active = t < a.nq;
     uint32_t own = 0, evals = 0, rechecks = 0;
     if (active) {
-        const uint32_t p = a.qlist ? a.qlist[t] : t;
+        const uint32_t p = a.qlist ? a.qlist[t] : a.qbase + t;
         const uint32_t h = a.cell_of[p];
         Point<D, kBand> pt;
 #pragma unroll
@@ -395,6 +395,47 @@ __global__ void k_batch_bounds(const uint64_t *__restrict__ off, uint64_t n, uin
     rows[b] = lo;
 }
 
+// Batch b of a cell-ordered run plan starts at the first work unit u (a
+// chunk, or a single point when chunks is null) whose first point's
+// cell-order row offset is at least b * total / nb: unit[b], its first
+// point pos[b] and that offset off[b]; entry nb is the end (units, n, total).
+__global__ void k_batch_units(const uint2 *__restrict__ chunks, const uint64_t *__restrict__ off_cell,
+                              uint64_t n, uint32_t units, uint64_t total, uint32_t nb,
+                              uint32_t *__restrict__ unit, uint64_t *__restrict__ pos,
+                              uint64_t *__restrict__ off) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nb) return;
+    auto start = [&](uint32_t u) -> uint64_t { return u >= units ? n : (chunks ? chunks[u].x : u); };
+    if (b == nb) {
+        unit[b] = units;
+        pos[b] = n;
+        off[b] = total;
+        return;
+    }
+    const unsigned __int128 t128 = static_cast<unsigned __int128>(b) * total / nb;
+    const uint64_t target = static_cast<uint64_t>(t128);
+    uint32_t lo = 0, hi = units;  // first u in [0, units] with off_cell[start(u)] >= target
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (off_cell[start(mid)] < target)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    unit[b] = lo;
+    pos[b] = start(lo);
+    off[b] = off_cell[start(lo)];
+}
+
+// len_b[perm[r]] = len_cell[r] for the batch's points r in [r0, r1) (len_b
+// cleared before): the batch's row lengths in order of i.
+__global__ __launch_bounds__(kThreads) void k_batch_lengths(const uint32_t *__restrict__ len_cell,
+                                                             const uint32_t *__restrict__ perm, uint64_t r0,
+                                                             uint64_t r1, uint32_t *__restrict__ len_b) {
+    const uint64_t r = r0 + blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    if (r < r1) len_b[perm[r]] = len_cell[r];
+}
+
 inline unsigned blocks_for(uint64_t n) {
     return static_cast<unsigned>((n + kThreads - 1) / kThreads);
 }
@@ -533,6 +574,19 @@ void launch_gather_offsets(const uint64_t *off_orig, const uint32_t *perm, uint6
                            uint64_t *offc, hipStream_t s) {
     KTimer kt_("row_offsets_gather", s);
     k_gather_offsets<<<blocks_for(n), kThreads, 0, s>>>(off_orig, perm, n, offc);
+    SJ_LAUNCH_CHECK();
+}
+
+void launch_batch_units(const uint2 *chunks, const uint64_t *off_cell, uint64_t n, uint32_t units,
+                        uint64_t total, uint32_t nb, uint32_t *unit, uint64_t *pos, uint64_t *off, hipStream_t s) {
+    k_batch_units<<<(nb + 1 + 255) / 256, 256, 0, s>>>(chunks, off_cell, n, units, total, nb, unit, pos, off);
+    SJ_LAUNCH_CHECK();
+}
+
+void launch_batch_lengths(const uint32_t *len_cell, const uint32_t *perm, uint64_t r0, uint64_t r1,
+                          uint32_t *len_b, hipStream_t s) {
+    if (r1 <= r0) return;
+    k_batch_lengths<<<blocks_for(r1 - r0), kThreads, 0, s>>>(len_cell, perm, r0, r1, len_b);
     SJ_LAUNCH_CHECK();
 }
 

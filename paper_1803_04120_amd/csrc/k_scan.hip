@@ -186,7 +186,8 @@ __global__ void k_set_values(T *p, T *q, T v) {
 
 // nscans = 1 or 2 (ops.in[1] etc. unused for one).
 template <typename Tout, bool kInclusive, typename Load>
-void scan_impl(const ScanOps<Tout, Load> &ops, unsigned nscans, size_t n, hipStream_t s) {
+void scan_impl(const ScanOps<Tout, Load> &ops, unsigned nscans, size_t n, hipStream_t s,
+               Tout *part_ws = nullptr) {
     if (n == 0) {
         if (ops.total[0] || (nscans > 1 && ops.total[1])) {
             k_set_values<Tout><<<1, 64, 0, s>>>(ops.total[0], nscans > 1 ? ops.total[1] : nullptr, Tout(0));
@@ -196,17 +197,22 @@ void scan_impl(const ScanOps<Tout, Load> &ops, unsigned nscans, size_t n, hipStr
     }
     const size_t nb = (n + kTile - 1) / kTile;
     if (nb > 0x7fffffffULL) throw Error(SJ_EINVAL, "scan: input too large");
-    DevBuf<Tout> part(nscans * (nb + 1));
-    k_tile_sum<Tout, Load><<<dim3(static_cast<unsigned>(nb), nscans), kThreads, 0, s>>>(ops, n, part.ptr);
+    DevBuf<Tout> part_own;
+    Tout *part = part_ws;
+    if (!part) {
+        part_own.reset(nscans * (nb + 1));
+        part = part_own.ptr;
+    }
+    k_tile_sum<Tout, Load><<<dim3(static_cast<unsigned>(nb), nscans), kThreads, 0, s>>>(ops, n, part);
     SJ_LAUNCH_CHECK();
     const int inline_prefix = nb <= kInlineTiles ? 1 : 0;
     if (!inline_prefix) {
-        k_scan_partials<Tout><<<nscans, kThreads, 0, s>>>(part.ptr, nb);
+        k_scan_partials<Tout><<<nscans, kThreads, 0, s>>>(part, nb);
         SJ_LAUNCH_CHECK();
     }
     KTimer kt_("scan", s);
     k_tile_scan<Tout, kInclusive, Load><<<dim3(static_cast<unsigned>(nb), nscans), kThreads, 0, s>>>(
-        ops, n, part.ptr, inline_prefix);
+        ops, n, part, inline_prefix);
     SJ_LAUNCH_CHECK();
 }
 
@@ -220,6 +226,13 @@ void scan_one(Load in, Tout *out, size_t n, Tout *total, hipStream_t s) {
 
 void scan_exclusive_u32_to_u64(const uint32_t *in, uint64_t *out, size_t n, hipStream_t s) {
     scan_one<uint64_t, false>(ArrayLoad<uint32_t>{in}, out, n, out + n, s);
+}
+
+size_t scan_partials(size_t n) { return (n + kTile - 1) / kTile + 1; }
+
+void scan_exclusive_u32_to_u64_ws(const uint32_t *in, uint64_t *out, size_t n, uint64_t *part, hipStream_t s) {
+    ScanOps<uint64_t, ArrayLoad<uint32_t>> ops{{{in}, {in}}, {out, out}, {out + n, nullptr}};
+    scan_impl<uint64_t, false>(ops, 1, n, s, part);
 }
 
 void scan_exclusive_u32_to_u64_x2(const uint32_t *in0, uint64_t *out0, const uint32_t *in1,

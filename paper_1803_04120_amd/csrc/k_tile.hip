@@ -82,8 +82,9 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     // chunks go to workgroups in launch order, which the hardware deals out
     // to the XCDs round robin: a dense cluster's many heavy chunks, adjacent
     // in cell order, spread over all XCDs
-    const uint32_t chunk = blockIdx.x * kWaves + wave;
-    if (chunk < *t.nchunks_dev) {  // uniform across the wave
+    const uint32_t chunk = t.chunk0 + blockIdx.x * kWaves + wave;
+    const uint32_t nch = *t.nchunks_dev;
+    if (chunk < (t.chunk_end < nch ? t.chunk_end : nch)) {  // uniform across the wave
         // segment table of the chunk, 64 rows per register load; the first
         // load is issued before anything else (it needs only the chunk index)
         const uint2 *segs = t.segs + static_cast<size_t>(chunk) * t.rows_per_chunk;
@@ -479,7 +480,8 @@ const char *const kTiledNames[8] = {"tiled_count_full_fp64", "tiled_count_full_f
 
 template <int D, bool U, int M, bool BD, int NS>
 void launch_tiled_one(const JoinArgs &a, const TileArgs &t, hipStream_t s) {
-    const unsigned nb = (t.nchunks + kWaves - 1) / kWaves;
+    const uint32_t span = t.chunk_end < t.nchunks ? t.chunk_end - t.chunk0 : t.nchunks - t.chunk0;
+    const unsigned nb = (span + kWaves - 1) / kWaves;
     if (nb == 0) return;
     KTimer kt_(NS ? (BD ? "tiled_fill_sort_full_fp32band" : "tiled_fill_sort_full_fp64")
                   : kTiledNames[M * 4 + (U ? 2 : 0) + (BD ? 1 : 0)],

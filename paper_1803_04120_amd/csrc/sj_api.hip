@@ -23,8 +23,17 @@ using sj::Error;
 namespace {
 
 thread_local std::string t_error;
+// Statistics of the last join run on this thread (any index, the two-set
+// join, the convenience call or the brute force).
+thread_local sj_stats t_last_run{};
+thread_local bool t_have_last_run = false;
 
 void set_error(const std::string &m) { t_error = m; }
+
+void note_run(const sj_stats &st) {
+    t_last_run = st;
+    t_have_last_run = true;
+}
 
 double now_ms() {
     using namespace std::chrono;
@@ -171,6 +180,20 @@ struct sj_index {
 
 namespace {
 
+// Index and last-join statistics, from host-side state only.
+sj_stats stats_of(const sj_index &ix) {
+    sj_stats st = ix.stats;
+    st.n = ix.n;
+    st.d = ix.d;
+    st.key_bits = static_cast<uint32_t>(ix.key_bits);
+    st.cells = ix.ncells;
+    for (int j = 0; j < sj::kMaxDim; ++j) st.grid_dims[j] = j < static_cast<int>(ix.d) ? ix.grid.dims[j] : 0;
+    st.eps = ix.eps;
+    st.cell_width = ix.grid.w;
+    st.max_cell_points = ix.max_cell;
+    return st;
+}
+
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 void compute_grid(sj_index &ix) {
@@ -223,7 +246,7 @@ void validate_opts(const sj_join_opts *o) {
     if (!o) return;
     if (o->precision != SJ_FP64 && o->precision != SJ_FP32_BAND)
         throw Error(SJ_EINVAL, "precision must be SJ_FP64 or SJ_FP32_BAND");
-    if (o->reserved != 0) throw Error(SJ_EINVAL, "opts.reserved must be 0");
+    if (o->sort_output != 0 && o->sort_output != 1) throw Error(SJ_EINVAL, "opts.sort_output must be 0 or 1");
 }
 
 sj_join_opts resolve_opts(const sj_join_opts *o) {
@@ -317,8 +340,10 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
                                                  std::fabs(ix.bmin[j] - ix.shift[j])));
     }
     SJ_HIP(hipMemcpyAsync(hs.p, ix.cell_of.ptr + (n - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(hs.as<uint32_t>() + 1, ix.max_cell_dev.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
     ix.ncells = static_cast<uint64_t>(*hs.as<uint32_t>()) + 1;
+    ix.max_cell = hs.as<uint32_t>()[1];
     ix.stats.ms_build = now_ms() - t0;
 }
 
@@ -365,6 +390,8 @@ sj::TileArgs tile_args(sj_index &ix) {
     t.chunks = ix.chunks;
     t.nchunks = ix.nchunks;
     t.nchunks_dev = ix.nchunks_dev.ptr;
+    t.chunk0 = 0;
+    t.chunk_end = 0xffffffffu;
     t.rows_per_chunk = ix.rows_per_chunk;
     t.segs = ix.segs.ptr;
     return t;
@@ -466,6 +493,7 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     if (ix.n == 0) {
         ix.counted = true;
         ix.stats.ms_count = now_ms() - t0;
+        note_run(stats_of(ix));
         return;
     }
     const int uni = o.unicomp ? 1 : 0;
@@ -518,6 +546,7 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     ix.overflow_clear = true;
     ix.counted = true;
     ix.stats.ms_count = now_ms() - t0;
+    note_run(stats_of(ix));
 }
 
 void check_overflow(sj_index &ix, hipStream_t s) {
@@ -537,7 +566,8 @@ struct Scratch {
 };
 
 void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t cap,
-               bool unicomp_fill, uint32_t *out_j, uint32_t *pairs, Scratch &sc, hipStream_t s) {
+               bool unicomp_fill, uint32_t *out_j, uint32_t *pairs, Scratch &sc, hipStream_t s,
+               uint32_t *cols = nullptr) {
     const uint64_t n = ix.n;
     const int mode = unicomp_fill ? 1 : 0;
     const bool whole = (i0 == 0 && i1 == n);
@@ -571,7 +601,7 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
     }
     // whole result, full fill: each point's row is complete when its own
     // evaluation ends, so the row sort runs inside the fill kernel
-    const bool fused = tiled && !unicomp_fill && whole && use_fused_sort(ix.d);
+    const bool fused = tiled && !unicomp_fill && whole && !cols && use_fused_sort(ix.d);
     if (tiled) {
         uint32_t ns = 0;
         if (fused) {
@@ -585,7 +615,7 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
         if (fused) {
             // the fused fill sorts rows of up to 64 itself
             sj::launch_rowsort_long(ix.off_cell.ptr, ix.off_orig.ptr, ix.perm.ptr, n, out_j, pairs,
-                                    ix.max_row, 64, s);
+                                    ix.max_row, 64, s, nullptr, ix.opts.sort_output != 0);
             return;
         }
     } else if (unicomp_fill) {
@@ -608,9 +638,10 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
     }
     if (whole)
         sj::launch_rowsort_cells(ix.off_cell.ptr, ix.off_orig.ptr, ix.perm.ptr, n, out_j, pairs,
-                                 ix.max_row, s);
+                                 ix.max_row, s, cols, ix.opts.sort_output != 0);
     else
-        sj::launch_rowsort(ix.off_orig.ptr, i0, i1, base, out_j, pairs, ix.max_row, s);
+        sj::launch_rowsort(ix.off_orig.ptr, i0, i1, base, out_j, pairs, ix.max_row, s, cols,
+                           ix.opts.sort_output != 0);
 }
 
 // The fill pass may evaluate the unicomp subset (every mirrored pair then
@@ -627,7 +658,7 @@ bool choose_unicomp_fill(const sj_index &ix) {
     return static_cast<double>(ix.pairs) < 0.05 * static_cast<double>(ix.stats.evals);
 }
 
-void join_fill_all(sj_index &ix, uint32_t *pairs_dev, hipStream_t s) {
+void join_fill_all(sj_index &ix, uint32_t *pairs_dev, hipStream_t s, uint32_t *cols_dev = nullptr) {
     const double t0 = now_ms();
     if (ix.n == 0 || ix.pairs == 0) return;
     DevBuf<uint32_t> out_j(ix.pairs);
@@ -636,15 +667,146 @@ void join_fill_all(sj_index &ix, uint32_t *pairs_dev, hipStream_t s) {
     const bool uni_fill = choose_unicomp_fill(ix);
     ix.stats.fill_unicomp = uni_fill ? 1u : 0u;
     // (a whole-result fill clears the overflow flag itself)
-    fill_rows(ix, 0, ix.n, 0, ix.pairs, uni_fill, out_j.ptr, pairs_dev, sc, s);
+    fill_rows(ix, 0, ix.n, 0, ix.pairs, uni_fill, out_j.ptr, pairs_dev, sc, s, cols_dev);
     check_overflow(ix, s);
     ix.stats.batches = 1;
     ix.stats.ms_fill = now_ms() - t0;
+    note_run(stats_of(ix));
 }
 
-// Batched delivery (Section V-A): consecutive row ranges, double-buffered so
-// batch b+1 computes while the callback consumes batch b.
-int join_batched(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
+// Batched delivery (Section V-A) in runs of cell order: batch b holds the
+// rows of the cell-ordered points [pos[b], pos[b+1]), a range of whole
+// grid-row chunks (so the fill is the tiled kernel, with its row sort fused
+// in 1..3-D) or, when the capacity is below what one chunk can hold, of
+// single points (the per-point kernel). Batches are sized from the exact
+// row lengths of the count pass, at least min_batches, and each is sorted
+// by (i, j) within itself: its row lengths are scattered to order of i and
+// scanned, and the fill writes every row at that batch-local offset.
+// Double-buffered, so batch b+1 computes while the callback consumes b.
+int join_batched_cells(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
+    const double t0 = now_ms();
+    const uint64_t n = ix.n, P = ix.pairs;
+    if (n == 0 || P == 0) {
+        ix.stats.batches = 0;
+        note_run(stats_of(ix));
+        return 0;
+    }
+    const uint64_t cap = ix.opts.batch_capacity_pairs ? ix.opts.batch_capacity_pairs : P;
+    if (ix.max_row > cap)
+        throw Error(SJ_ECAPACITY, "batch capacity is smaller than the longest result row (" +
+                                      std::to_string(ix.max_row) + " pairs)");
+    // work units: grid-row chunks (at most 64 rows each) when the capacity
+    // leaves room for one, else single points
+    const bool tiled = use_tiled() && static_cast<double>(cap) >= 128.0 * ix.max_row;
+    if (tiled) ensure_chunks(ix, s);
+    const uint32_t units = tiled ? static_cast<uint32_t>(ix.stats.chunks) : static_cast<uint32_t>(n);
+    const uint64_t gran = tiled ? 64ull * ix.max_row : ix.max_row;
+    const uint64_t per = cap > gran ? cap - gran : 1;
+    uint64_t nb64 = std::max<uint64_t>(ix.opts.min_batches, (P + per - 1) / per);
+    if (cap >= P && ix.opts.min_batches <= 1) nb64 = 1;
+    nb64 = std::min<uint64_t>(nb64, units);
+    const uint32_t nb = static_cast<uint32_t>(std::max<uint64_t>(nb64, 1));
+    std::vector<uint32_t> unit(nb + 1);
+    std::vector<uint64_t> pos(nb + 1), boff(nb + 1);
+    {
+        DevBuf<uint32_t> du(nb + 1);
+        DevBuf<uint64_t> dp(nb + 1), dof(nb + 1);
+        sj::launch_batch_units(tiled ? ix.chunks : nullptr, ix.off_cell.ptr, n, units, P, nb, du.ptr, dp.ptr,
+                               dof.ptr, s);
+        SJ_HIP(hipMemcpyAsync(unit.data(), du.ptr, (nb + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipMemcpyAsync(pos.data(), dp.ptr, (nb + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipMemcpyAsync(boff.data(), dof.ptr, (nb + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipStreamSynchronize(s));
+    }
+    uint64_t maxbatch = 0;
+    for (uint32_t b = 0; b < nb; ++b) maxbatch = std::max(maxbatch, boff[b + 1] - boff[b]);
+    if (maxbatch > cap) throw Error(SJ_EDEVICE, "internal: a planned batch exceeds the capacity");
+    ix.stats.fill_unicomp = 0;  // every point writes its own row
+    const bool fused = tiled && use_fused_sort(ix.d);
+    const uint32_t ns = fused ? fused_slot(ix) : 0;
+    const int nsets = nb > 1 ? 2 : 1;
+    DevBuf<uint32_t> out_j[2], pairs[2];
+    for (int k = 0; k < nsets; ++k) {
+        out_j[k].reset(std::max<uint64_t>(1, maxbatch));
+        pairs[k].reset(2 * std::max<uint64_t>(1, maxbatch));
+    }
+    DevBuf<uint32_t> len_b(n);
+    DevBuf<uint64_t> off_b(n + 1);
+    hipEvent_t ev[2];
+    SJ_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    SJ_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } evg{ev};
+    int rc = 0;
+    auto deliver = [&](uint32_t b) {
+        const int k = b & 1;
+        SJ_HIP(hipEventSynchronize(ev[k]));
+        if (rc == 0 && cb) rc = cb(user, pairs[k].ptr, boff[b + 1] - boff[b], b, pos[b], pos[b + 1]);
+    };
+    ix.overflow.ensure(1);
+    sj::launch_fill_u32(ix.overflow.ptr, 1, 0u, s);
+    ix.overflow_clear = false;
+    for (uint32_t b = 0; b < nb && rc == 0; ++b) {
+        const int k = b & 1;
+        const uint64_t r0 = pos[b], r1 = pos[b + 1], bp = boff[b + 1] - boff[b];
+        if (bp > 0) {
+            // the batch's row offsets in order of i
+            sj::launch_fill_u32(len_b.ptr, n, 0u, s);
+            sj::launch_batch_lengths(ix.len_cell.ptr, ix.perm.ptr, r0, r1, len_b.ptr, s);
+            sj::scan_exclusive_u32_to_u64(len_b.ptr, off_b.ptr, n, s);
+            sj::JoinArgs a = base_args(ix, 0);
+            a.out_j = out_j[k].ptr;
+            a.offc = ix.off_cell.ptr;
+            a.out_base = boff[b];
+            a.out_cap = bp;
+            a.overflow = ix.overflow.ptr;
+            if (tiled) {
+                sj::TileArgs t = tile_args(ix);
+                t.chunk0 = unit[b];
+                t.chunk_end = unit[b + 1];
+                if (fused) {
+                    a.off_orig = off_b.ptr;
+                    a.pairs = reinterpret_cast<uint2 *>(pairs[k].ptr);
+                }
+                sj::launch_join_tiled(a, t, ix.d, 0, sj::kFill, ix.band_used, s, ns);
+            } else {
+                ensure_ranges(ix, 0, s);
+                a = base_args(ix, 0);
+                a.out_j = out_j[k].ptr;
+                a.offc = ix.off_cell.ptr;
+                a.out_base = boff[b];
+                a.out_cap = bp;
+                a.overflow = ix.overflow.ptr;
+                a.qlist = nullptr;
+                a.qbase = static_cast<uint32_t>(r0);
+                a.nq = static_cast<uint32_t>(r1 - r0);
+                sj::launch_join(a, ix.d, 0, sj::kFill, ix.band_used, s);
+            }
+            sj::launch_rowsort_range(ix.off_cell.ptr, r0, r1, boff[b], off_b.ptr, ix.perm.ptr, out_j[k].ptr,
+                                     pairs[k].ptr, ix.max_row, fused ? 64u : 0u, s, nullptr,
+                                     ix.opts.sort_output != 0);
+        }
+        SJ_HIP(hipEventRecord(ev[k], s));
+        if (b >= 1) deliver(b - 1);
+    }
+    if (rc == 0) deliver(nb - 1);
+    check_overflow(ix, s);
+    ix.stats.batches = nb;
+    ix.stats.ms_fill = now_ms() - t0;
+    note_run(stats_of(ix));
+    return rc;
+}
+
+// Batched delivery in consecutive ranges of i (the convenience call's
+// pinned-host result, whose batches are concatenated in place): each batch's
+// query points scan all adjacent cells with the per-point kernel and write
+// only their own rows; double-buffered like the cell-ordered runs.
+int join_batched_rows(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
     const double t0 = now_ms();
     const uint64_t n = ix.n, P = ix.pairs;
     if (n == 0 || P == 0) {
@@ -718,7 +880,89 @@ int join_batched(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
     check_overflow(ix, s);
     ix.stats.batches = nb;
     ix.stats.ms_fill = now_ms() - t0;
+    note_run(stats_of(ix));
     return rc;
+}
+
+// ---------------------------------------------------------------- brute force
+// Candidate ranges per query row: enough workgroups (query blocks x ranges)
+// to fill the chip, each range a whole number of LDS tiles.
+struct BrutePlan {
+    uint32_t splits;
+    uint64_t span;
+};
+
+BrutePlan brute_plan(uint64_t n, uint32_t d) {
+    constexpr uint64_t kTargetBlocks = 1024;
+    const uint64_t rows_blk = sj::brute_rows_per_block(d);
+    const uint64_t tile = sj::brute_tile();
+    const uint64_t qblocks = (n + rows_blk - 1) / rows_blk;
+    const uint64_t tiles = (n + tile - 1) / tile;
+    uint64_t S = qblocks ? (kTargetBlocks + qblocks - 1) / qblocks : 1;
+    S = std::max<uint64_t>(1, std::min<uint64_t>(S, tiles));
+    const uint64_t span = ((n + S - 1) / S + tile - 1) / tile * tile;
+    BrutePlan p;
+    p.span = std::max<uint64_t>(span, tile);
+    p.splits = static_cast<uint32_t>(n ? (n + p.span - 1) / p.span : 1);
+    return p;
+}
+
+// Count pass, offsets and (when pairs_dev is set and holds the result) fill
+// pass of the all-pairs join over device points dp. count, off and part
+// hold n * splits, n * splits + 1 and scan_partials(n * splits) entries;
+// flag is one word; readback is a host word for P (page-locked or not).
+// Allocates nothing.
+void brute_join(const double *dp, uint64_t n, uint32_t d, double eps, const BrutePlan &pl, uint32_t *count,
+                uint64_t *off, uint64_t *part, uint32_t *flag, uint64_t *readback, uint32_t *pairs_dev,
+                uint64_t cap, hipStream_t s, uint64_t *P_out) {
+    sj::BruteArgs a{};
+    a.pts = dp;
+    a.n = n;
+    a.splits = pl.splits;
+    a.span = pl.span;
+    a.eps2 = eps * eps;
+    a.count = count;
+    const double t0 = now_ms();
+    sj::launch_brute(a, d, sj::kCount, s);
+    const size_t cells = static_cast<size_t>(n) * pl.splits;
+    sj::scan_exclusive_u32_to_u64_ws(count, off, cells, part, s);
+    sj::launch_fill_u32(flag, 1, 0u, s);
+    SJ_HIP(hipMemcpyAsync(readback, off + cells, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    const uint64_t P = *readback;
+    if (P_out) *P_out = P;
+    sj_stats st{};
+    st.n = n;
+    st.d = d;
+    st.eps = eps;
+    st.precision_used = SJ_FP64;
+    st.evals = n * n;
+    st.pairs = P;
+    st.ms_count = now_ms() - t0;
+    note_run(st);
+    if (!pairs_dev || P == 0) return;
+    if (cap < P)
+        throw Error(SJ_ECAPACITY, "output buffer holds " + std::to_string(cap) + " pairs, the result has " +
+                                      std::to_string(P));
+    const double t1 = now_ms();
+    a.off = off;
+    a.pairs = reinterpret_cast<uint2 *>(pairs_dev);
+    a.overflow = flag;
+    sj::launch_brute(a, d, sj::kFill, s);
+    uint32_t *fw = reinterpret_cast<uint32_t *>(readback);
+    SJ_HIP(hipMemcpyAsync(fw, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    if (*fw) throw Error(SJ_EDEVICE, "internal: the brute-force fill disagreed with its count");
+    st.ms_fill = now_ms() - t1;
+    st.batches = 1;
+    note_run(st);
+}
+
+void validate_brute_args(const double *pts, uint64_t n, uint32_t d, double eps) {
+    if (d < 1 || d > static_cast<uint32_t>(sj::kMaxDim)) throw Error(SJ_EINVAL, "d must be in [1, 8]");
+    if (!(eps > 0.0) || !std::isfinite(eps)) throw Error(SJ_EINVAL, "eps must be finite and > 0");
+    if (n >= 0xffffffffULL) throw Error(SJ_EINVAL, "n must be below 2^32 - 1");
+    if (n > 0 && !pts) throw Error(SJ_EINVAL, "pts is NULL");
 }
 
 }  // namespace
@@ -732,7 +976,7 @@ void sj_default_opts(sj_join_opts *o) {
     o->precision = SJ_FP64;
     o->batch_capacity_pairs = 0;
     o->min_batches = 1;
-    o->reserved = 0;
+    o->sort_output = 1;
 }
 
 const char *sj_last_error(void) { return t_error.c_str(); }
@@ -790,6 +1034,27 @@ int sj_join_fill(sj_index *idx, uint32_t *pairs_dev, uint64_t capacity_pairs, vo
                                           " pairs, the result has " + std::to_string(idx->pairs));
         if (idx->pairs && !pairs_dev) throw Error(SJ_EINVAL, "pairs_dev is NULL");
         join_fill_all(*idx, pairs_dev, s);
+    });
+}
+
+int sj_join_fill_csr(sj_index *idx, uint64_t *row_off_dev, uint32_t *cols_dev, uint64_t capacity,
+                     void *stream) {
+    hipStream_t s = as_stream(stream);
+    return guarded(s, [&] {
+        if (!idx) throw Error(SJ_EINVAL, "index is NULL");
+        if (!idx->counted) throw Error(SJ_ESTATE, "sj_join_fill_csr needs a preceding sj_join_count");
+        if (capacity < idx->pairs)
+            throw Error(SJ_ECAPACITY, "column buffer holds " + std::to_string(capacity) +
+                                          " entries, the result has " + std::to_string(idx->pairs));
+        if (!row_off_dev) throw Error(SJ_EINVAL, "row_off_dev is NULL");
+        if (idx->pairs && !cols_dev) throw Error(SJ_EINVAL, "cols_dev is NULL");
+        if (idx->n == 0) {
+            sj::launch_fill_u64(row_off_dev, 1, 0, s);
+            return;
+        }
+        SJ_HIP(hipMemcpyAsync(row_off_dev, idx->off_orig.ptr, (idx->n + 1) * sizeof(uint64_t),
+                              hipMemcpyDeviceToDevice, s));
+        join_fill_all(*idx, nullptr, s, cols_dev);
     });
 }
 
@@ -875,6 +1140,90 @@ int sj_join_rs(sj_index *idx, const double *R, uint64_t nr, int r_on_device, uin
     });
 }
 
+int sj_bruteforce(const double *pts, uint64_t n, uint32_t d, double eps, int pts_on_device,
+                  uint32_t *pairs_dev, uint64_t capacity_pairs, void *stream, uint64_t *total_pairs) {
+    hipStream_t s = as_stream(stream);
+    return guarded(s, [&] {
+        validate_brute_args(pts, n, d, eps);
+        if (total_pairs) *total_pairs = 0;
+        if (n == 0) return;
+        DevBuf<double> staged;
+        const double *dp = pts;
+        if (!pts_on_device) {
+            staged.reset(n * d);
+            SJ_HIP(hipMemcpyAsync(staged.ptr, pts, n * d * sizeof(double), hipMemcpyHostToDevice, s));
+            dp = staged.ptr;
+        }
+        const BrutePlan pl = brute_plan(n, d);
+        const size_t cells = static_cast<size_t>(n) * pl.splits;
+        DevBuf<uint32_t> count(cells), flag(1);
+        DevBuf<uint64_t> off(cells + 1), part(sj::scan_partials(cells));
+        sj::HostStage hs;
+        brute_join(dp, n, d, eps, pl, count.ptr, off.ptr, part.ptr, flag.ptr, hs.as<uint64_t>(), pairs_dev,
+                   capacity_pairs, s, total_pairs);
+    });
+}
+
+int sj_dbscan_csr(const uint64_t *row_off_dev, const uint32_t *cols_dev, uint64_t n, uint32_t min_pts,
+                  int32_t *labels_dev, void *stream, uint64_t *nclusters) {
+    hipStream_t s = as_stream(stream);
+    return guarded(s, [&] {
+        if (nclusters) *nclusters = 0;
+        if (n == 0) return;
+        if (!row_off_dev || !cols_dev || !labels_dev) throw Error(SJ_EINVAL, "NULL argument");
+        if (min_pts == 0) throw Error(SJ_EINVAL, "min_pts must be at least 1");
+        if (n > 0x7fffffffULL) throw Error(SJ_EINVAL, "n must be below 2^31");
+        DevBuf<unsigned long long> cnt(1);
+        sj::launch_fill_u64(reinterpret_cast<uint64_t *>(cnt.ptr), 1, 0, s);
+        sj::launch_dbscan(row_off_dev, cols_dev, n, min_pts, labels_dev, cnt.ptr, s);
+        sj::HostStage hs;
+        SJ_HIP(hipMemcpyAsync(hs.p, cnt.ptr, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipStreamSynchronize(s));
+        if (nclusters) *nclusters = *hs.as<uint64_t>();
+    });
+}
+
+int sj_dbscan(const double *pts, uint64_t n, uint32_t d, double eps, uint32_t min_pts, int pts_on_device,
+              int32_t *labels_dev, void *stream, uint64_t *nclusters) {
+    hipStream_t s = as_stream(stream);
+    if (nclusters) *nclusters = 0;
+    if (n >= 0x7fffffffULL) {
+        set_error("n must be below 2^31 - 1");
+        return SJ_EINVAL;
+    }
+    if (min_pts == 0) {
+        set_error("min_pts must be at least 1");
+        return SJ_EINVAL;
+    }
+    if (n > 0 && !labels_dev) {
+        set_error("labels_dev is NULL");
+        return SJ_EINVAL;
+    }
+    sj_index *ix = nullptr;
+    int rc = sj_build_index(pts, n, d, eps, pts_on_device, stream, &ix);
+    if (rc != SJ_OK) return rc;
+    rc = guarded(s, [&] {
+        if (n == 0) return;
+        sj_join_opts o;
+        sj_default_opts(&o);
+        o.sort_output = 0;  // the clustering needs each row's members, not their order
+        join_count(*ix, o, s);
+        DevBuf<uint64_t> off(n + 1);
+        DevBuf<uint32_t> cols(std::max<uint64_t>(1, ix->pairs));
+        SJ_HIP(hipMemcpyAsync(off.ptr, ix->off_orig.ptr, (n + 1) * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+        join_fill_all(*ix, nullptr, s, cols.ptr);
+        DevBuf<unsigned long long> cnt(1);
+        sj::launch_fill_u64(reinterpret_cast<uint64_t *>(cnt.ptr), 1, 0, s);
+        sj::launch_dbscan(off.ptr, cols.ptr, n, min_pts, labels_dev, cnt.ptr, s);
+        sj::HostStage hs;
+        SJ_HIP(hipMemcpyAsync(hs.p, cnt.ptr, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipStreamSynchronize(s));
+        if (nclusters) *nclusters = *hs.as<uint64_t>();
+    });
+    sj_destroy_index(ix);
+    return rc;
+}
+
 int sj_selfjoin_index(sj_index *idx, const sj_join_opts *opts, sj_run_cb cb, void *user,
                       void *stream, uint64_t *total_pairs) {
     hipStream_t s = as_stream(stream);
@@ -884,7 +1233,7 @@ int sj_selfjoin_index(sj_index *idx, const sj_join_opts *opts, sj_run_cb cb, voi
         validate_opts(opts);
         join_count(*idx, resolve_opts(opts), s);
         if (total_pairs) *total_pairs = idx->pairs;
-        cb_rc = join_batched(*idx, cb, user, s);
+        cb_rc = join_batched_cells(*idx, cb, user, s);
     });
     if (rc != SJ_OK) return rc;
     if (cb_rc != 0) set_error("the batch callback stopped the join");
@@ -917,21 +1266,8 @@ int sj_selfjoin(const double *pts, uint64_t n, uint32_t d, double eps, const sj_
                 std::lock_guard<std::mutex> lk(g_out_mu);
                 g_out_bufs[buf] = true;
             }
-            if (o.batch_capacity_pairs == 0 && o.min_batches <= 1) {
-                join_fill_all(*ix, buf, s);
-            } else {
-                struct Ctx { uint32_t *dst; hipStream_t s; uint64_t at; } ctx{buf, s, 0};
-                auto cb = [](void *u, const uint32_t *p, uint64_t np, uint32_t, uint64_t, uint64_t) -> int {
-                    auto *c = static_cast<Ctx *>(u);
-                    if (hipMemcpyAsync(c->dst + 2 * c->at, p, np * 8, hipMemcpyDeviceToDevice, c->s) != hipSuccess)
-                        return SJ_EDEVICE;
-                    if (hipStreamSynchronize(c->s) != hipSuccess) return SJ_EDEVICE;
-                    c->at += np;
-                    return 0;
-                };
-                const int r = join_batched(*ix, cb, &ctx, s);
-                if (r) throw Error(r, "batched device copy failed");
-            }
+            // the whole result is in device memory anyway: one fill into it
+            join_fill_all(*ix, buf, s);
         } else {
             SJ_HIP(hipHostMalloc(reinterpret_cast<void **>(&buf), P * 2 * sizeof(uint32_t),
                                  hipHostMallocDefault));
@@ -952,7 +1288,7 @@ int sj_selfjoin(const double *pts, uint64_t n, uint32_t d, double eps, const sj_
             };
             int r = 0;
             try {
-                r = join_batched(*ix, cb, &ctx, s);
+                r = join_batched_rows(*ix, cb, &ctx, s);
             } catch (...) {
                 (void)hipStreamSynchronize(cs);
                 (void)hipStreamDestroy(cs);
@@ -995,19 +1331,20 @@ int sj_index_stats(const sj_index *idx, sj_stats *out) {
         set_error("NULL argument");
         return SJ_EINVAL;
     }
-    sj_stats st = idx->stats;
-    st.n = idx->n;
-    st.d = idx->d;
-    st.key_bits = static_cast<uint32_t>(idx->key_bits);
-    st.cells = idx->ncells;
-    for (int j = 0; j < sj::kMaxDim; ++j) st.grid_dims[j] = j < static_cast<int>(idx->d) ? idx->grid.dims[j] : 0;
-    st.eps = idx->eps;
-    st.cell_width = idx->grid.w;
-    uint32_t mc = idx->max_cell;
-    if (idx->max_cell_dev.ptr && hipMemcpy(&mc, idx->max_cell_dev.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost) == hipSuccess)
-        const_cast<sj_index *>(idx)->max_cell = mc;
-    st.max_cell_points = mc;
-    *out = st;
+    *out = stats_of(*idx);
+    return SJ_OK;
+}
+
+int sj_last_run_stats(sj_stats *out) {
+    if (!out) {
+        set_error("NULL argument");
+        return SJ_EINVAL;
+    }
+    if (!t_have_last_run) {
+        set_error("no join has run on this thread");
+        return SJ_ESTATE;
+    }
+    *out = t_last_run;
     return SJ_OK;
 }
 

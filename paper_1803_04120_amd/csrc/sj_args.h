@@ -43,8 +43,9 @@ struct JoinArgs {
     const uint32_t *starts;
     const uint64_t *roff;
     const uint2 *rng;
-    const uint32_t *qlist;    // query points (cell order) or null for all
+    const uint32_t *qlist;    // query points (cell order) or null for qbase + [0, nq)
     uint32_t nq;
+    uint32_t qbase;           // first query position when qlist is null
     double eps2;
     float lo, hi;
     // count outputs
@@ -84,6 +85,8 @@ struct TileArgs {
     const uint2 *chunks;      // [first, end) point range of each chunk
     uint32_t nchunks;         // upper bound on the chunk count (launch size)
     const uint32_t *nchunks_dev;  // the chunk count (device)
+    uint32_t chunk0;          // first chunk of the launch (a batch's range; 0 for all)
+    uint32_t chunk_end;       // end of the launch's chunk range (~0u: up to the count)
     uint32_t rows_per_chunk;  // 3^(d-1)
     const uint2 *segs;        // [chunk * rows_per_chunk + row] candidate point segment
 };
@@ -107,6 +110,21 @@ struct RsArgs {
     uint32_t *out_j;          // fill pass: S rows, the k-th probed query at off[k]
     uint64_t out_cap;
     uint32_t *overflow;       // set when a fill write falls outside its row
+};
+
+// All-pairs join (k_brute.hip): every query row against every point, the
+// candidates split into `splits` consecutive ranges of `span` points so that
+// small inputs still fill the chip.
+struct BruteArgs {
+    const double *pts;        // n x d, row-major (the caller's layout)
+    uint64_t n;
+    uint32_t splits;          // candidate ranges per query row
+    uint64_t span;            // points per range (a multiple of the tile)
+    double eps2;
+    uint32_t *count;          // count pass: hits of row i in range s at [i * splits + s]
+    const uint64_t *off;      // fill pass: exclusive scan of count (n * splits + 1 entries)
+    uint2 *pairs;             // fill pass: (i, j) pairs, row i range s at off[i * splits + s]
+    uint32_t *overflow;       // set if a fill write would leave its range
 };
 
 }  // namespace sj

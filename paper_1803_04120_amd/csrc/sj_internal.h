@@ -107,6 +107,10 @@ void scan_exclusive_u32_to_u64(const uint32_t *in, uint64_t *out, size_t n, hipS
 // Two such scans of equal length in one pair of launches.
 void scan_exclusive_u32_to_u64_x2(const uint32_t *in0, uint64_t *out0, const uint32_t *in1,
                                   uint64_t *out1, size_t n, hipStream_t s);
+// The same with the tile sums in a caller buffer of scan_partials(n) u64
+// (allocates nothing).
+size_t scan_partials(size_t n);
+void scan_exclusive_u32_to_u64_ws(const uint32_t *in, uint64_t *out, size_t n, uint64_t *part, hipStream_t s);
 // in place inclusive scan of u32.
 void scan_inclusive_u32(uint32_t *data, size_t n, hipStream_t s);
 // exclusive scan of u32 into u32 (no total), in place allowed.
@@ -230,6 +234,14 @@ void launch_gather_offsets(const uint64_t *off_orig, const uint32_t *perm, uint6
 // Returns the count (host sync).
 uint32_t build_query_list(const uint32_t *perm, uint64_t n, uint64_t i0, uint64_t i1,
                           uint32_t *flags_scratch, uint32_t *qlist, hipStream_t s);
+// Cell-ordered batch plan: batch b starts at work unit unit[b] (a chunk, or
+// a point when chunks is null), point pos[b], cell-order row offset off[b];
+// entry nb holds (units, n, total).
+void launch_batch_units(const uint2 *chunks, const uint64_t *off_cell, uint64_t n, uint32_t units,
+                        uint64_t total, uint32_t nb, uint32_t *unit, uint64_t *pos, uint64_t *off, hipStream_t s);
+// len_b[perm[r]] = len_cell[r] for r in [r0, r1).
+void launch_batch_lengths(const uint32_t *len_cell, const uint32_t *perm, uint64_t r0, uint64_t r1,
+                          uint32_t *len_b, hipStream_t s);
 // rows[b] = first row i with off[i] >= floor(b * total / nb), b in [0, nb];
 // rows[nb] = n.
 void launch_batch_bounds(const uint64_t *off, uint64_t n, uint64_t total, uint32_t nb,
@@ -241,23 +253,44 @@ void launch_join_rs(const RsArgs &a, int mode, hipStream_t s);
 // *out (0 on entry) = max of counts[0..n).
 void launch_rs_max(const uint32_t *counts, uint64_t n, uint32_t *out, hipStream_t s);
 
+// All-pairs join (k_brute.hip): mode kCount writes a.count, kFill a.pairs.
+void launch_brute(const BruteArgs &a, uint32_t d, int mode, hipStream_t s);
+uint32_t brute_rows_per_block(uint32_t d);  // query rows per workgroup
+uint32_t brute_tile();                      // candidates per LDS tile
+
+// DBSCAN over a CSR neighbour table (k_dbscan.hip): label[i] = smallest core
+// index of i's cluster, -1 for noise; *nclusters (0 on entry) += clusters.
+void launch_dbscan(const uint64_t *off, const uint32_t *cols, uint64_t n, uint32_t min_pts, int32_t *label,
+                   unsigned long long *nclusters, hipStream_t s);
+
 // ---------------------------------------------------------------------
 // Row sort and pair expansion (k_rowsort.hip)
 // ---------------------------------------------------------------------
-// Sorts each row's neighbour ids and writes interleaved (i, j) pairs.
+// Sorts each row's neighbour ids and writes interleaved (i, j) pairs -- or,
+// with cols set, only the j of each entry (compressed sparse row columns);
+// with sorted false the rows are moved unsorted.
 // Rows [i0, i1); row i occupies [off[i] - base, off[i+1] - base) of out_j
-// and of pairs. max_len is the longest row.
+// and of the output. max_len is the longest row.
 void launch_rowsort(const uint64_t *off, uint64_t i0, uint64_t i1, uint64_t base,
-                    uint32_t *out_j, uint32_t *pairs, uint32_t max_len, hipStream_t s);
+                    uint32_t *out_j, uint32_t *pairs, uint32_t max_len, hipStream_t s,
+                    uint32_t *cols = nullptr, bool sorted = true);
 // Whole result filled in cell order: row r (cell-ordered point r) occupies
-// out_j[off_cell[r], off_cell[r+1]) and goes to pairs[off_orig[perm[r]], ...)
+// out_j[off_cell[r], off_cell[r+1]) and goes to output [off_orig[perm[r]], ...)
 // with i = perm[r].
 void launch_rowsort_cells(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,
-                          uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t max_len, hipStream_t s);
-// Same layout; sorts only the rows longer than sorted_len (a fused fill has
-// written the others).
+                          uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t max_len, hipStream_t s,
+                          uint32_t *cols = nullptr, bool sorted = true);
+// Rows of the cell-ordered points [r0, r1): row r occupies
+// out_j[off_cell[r] - in_base, +len) and goes to off_out[perm[r]]; only the
+// rows longer than sorted_len (0: all rows).
+void launch_rowsort_range(const uint64_t *off_cell, uint64_t r0, uint64_t r1, uint64_t in_base,
+                          const uint64_t *off_out, const uint32_t *perm, uint32_t *out_j, uint32_t *pairs,
+                          uint32_t max_len, uint32_t sorted_len, hipStream_t s, uint32_t *cols = nullptr,
+                          bool sorted = true);
+// Same layout; handles only the rows longer than sorted_len (a fused fill
+// has written the others).
 void launch_rowsort_long(const uint64_t *off_cell, const uint64_t *off_orig, const uint32_t *perm,
                          uint64_t n, uint32_t *out_j, uint32_t *pairs, uint32_t max_len, uint32_t sorted_len,
-                         hipStream_t s);
+                         hipStream_t s, uint32_t *cols = nullptr, bool sorted = true);
 
 }  // namespace sj

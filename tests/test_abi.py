@@ -41,7 +41,7 @@ def test_default_opts(lib):
     from paper_1803_04120_amd import _lib
     o = _lib.SjJoinOpts()
     lib.sj_default_opts(ctypes.byref(o))
-    assert (o.unicomp, o.precision, o.batch_capacity_pairs, o.min_batches, o.reserved) == (1, 0, 0, 1, 0)
+    assert (o.unicomp, o.precision, o.batch_capacity_pairs, o.min_batches, o.sort_output) == (1, 0, 0, 1, 1)
 
 
 @pytest.mark.parametrize("d,eps,extent", [(2, 0.04, 50.0), (2, 0.2, 50.0), (3, 0.9142, 50.0),

@@ -379,8 +379,19 @@ def test_batches_partition_the_result(sj, cap, minb, uni):
         assert P == want.shape[0]
         assert len(info) >= minb
         assert all(npairs <= (cap or P) for _, _, _, npairs in info)
-        assert [r for _, r, _, _ in info][0] == 0 and info[-1][2] == 12000
-        assert_same(got.cpu().numpy().astype(np.int64), want, f"batched cap={cap}")
+        # the runs cover the cell-ordered positions [0, n) in order
+        assert info[0][1] == 0 and info[-1][2] == 12000
+        assert all(info[k][2] == info[k + 1][1] for k in range(len(info) - 1))
+        g = got.cpu().numpy().astype(np.int64)
+        perm = ix.export(sj._lib.SJ_EXPORT_PERM).astype(np.int64)
+        at = 0
+        for _, r0, r1, npairs in info:
+            run = g[at:at + npairs]
+            at += npairs
+            key = run[:, 0] * 12000 + run[:, 1]
+            assert np.all(np.diff(key) > 0), "a run is not sorted by (i, j)"
+            assert set(np.unique(run[:, 0])) <= set(perm[r0:r1].tolist())
+        assert_same(g[np.lexsort((g[:, 1], g[:, 0]))], want, f"batched cap={cap}")
 
 
 def test_convenience_host_and_device_output(sj):
