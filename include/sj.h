@@ -230,6 +230,20 @@ int sj_selfjoin(const double *pts, uint64_t n, uint32_t d, double eps,
                 const sj_join_opts *opts, int pts_on_device, int out_on_device,
                 void *stream, uint32_t **pairs_out, uint64_t *npairs);
 
+/*
+ * sj_bruteforce for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same all-pairs join and the same result, with every temporary in a fixed
+ * device array that the library holds on each GPU it runs on until the
+ * process ends (about 24 MiB), so the call makes no hipMalloc, hipFree or
+ * other allocating call. pts_dev must be device memory (no host staging).
+ * At most 2^21 points (SJ_EINVAL beyond, before any device work); other
+ * arguments and errors as for sj_bruteforce. Calls that overlap on one GPU
+ * share that array and race: serialise them.
+ */
+int sj_bruteforce_noalloc(const double *pts_dev, uint64_t n, uint32_t d, double eps, uint32_t *pairs_dev,
+                          uint64_t capacity_pairs, void *stream, uint64_t *total_pairs);
+
 /* Frees a result buffer that sj_selfjoin allocated (device or pinned host
  * memory, the two placements of a Section V-A result). NULL and pointers the
  * library did not hand out are ignored. */

@@ -119,6 +119,7 @@ def load():
         "sj_index_stats": (ctypes.c_int, [vp, ctypes.POINTER(SjStats)]),
         "sj_last_run_stats": (ctypes.c_int, [ctypes.POINTER(SjStats)]),
         "sj_bruteforce": (ctypes.c_int, [vp, u64, u32, dbl, ctypes.c_int, vp, u64, vp, ctypes.POINTER(u64)]),
+        "sj_bruteforce_noalloc": (ctypes.c_int, [vp, u64, u32, dbl, vp, u64, vp, ctypes.POINTER(u64)]),
         "sj_index_export_size": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]),
         "sj_index_export": (ctypes.c_int, [vp, ctypes.c_int, vp, u64]),
         "sj_index_search": (ctypes.c_int, [vp, ctypes.c_int, vp]),

@@ -20,6 +20,27 @@
 using sj::DevBuf;
 using sj::Error;
 
+// ------------------------------------------------ allocation-free brute force
+// Device scratch of sj_bruteforce_noalloc, a file-scope array that every GPU
+// the library runs on holds until the process ends: the count, offset and
+// scan tile-sum arrays of at most kNoAllocCells (row, candidate range)
+// cells and the fill's overflow word, each region 256-byte aligned. It has
+// external linkage, so the device code object keeps it although no kernel
+// names it (kernels get its address as an argument).
+namespace sj {
+constexpr size_t kNoAllocCells = size_t(1) << 21;
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kNaCountOff = 0;
+constexpr size_t kNaOffOff = align256(kNaCountOff + kNoAllocCells * sizeof(uint32_t));
+constexpr size_t kNaPartOff = align256(kNaOffOff + (kNoAllocCells + 1) * sizeof(uint64_t));
+constexpr size_t kNaPartWords = kNoAllocCells / 2048 + 2;  // >= scan_partials(kNoAllocCells)
+constexpr size_t kNaFlagOff = align256(kNaPartOff + kNaPartWords * sizeof(uint64_t));
+constexpr size_t kNoAllocBytes = align256(kNaFlagOff + sizeof(uint32_t));
+
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+}  // namespace sj
+
+
 namespace {
 
 thread_local std::string t_error;
@@ -958,6 +979,27 @@ void brute_join(const double *dp, uint64_t n, uint32_t d, double eps, const Brut
     note_run(st);
 }
 
+// The array's device address on the current device, looked up once per
+// device (in host code the array's name is only a stand-in, not a device
+// address).
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+unsigned char *g_scratch_addr[kMaxDevices] = {};
+
+unsigned char *scratch_on_current_device() {
+    int dev = -1;
+    SJ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw Error(SJ_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        SJ_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(sj::scratch)));
+        if (!p) throw Error(SJ_EDEVICE, "scratch address lookup returned NULL");
+        g_scratch_addr[dev] = static_cast<unsigned char *>(p);
+    }
+    return g_scratch_addr[dev];
+}
+
 void validate_brute_args(const double *pts, uint64_t n, uint32_t d, double eps) {
     if (d < 1 || d > static_cast<uint32_t>(sj::kMaxDim)) throw Error(SJ_EINVAL, "d must be in [1, 8]");
     if (!(eps > 0.0) || !std::isfinite(eps)) throw Error(SJ_EINVAL, "eps must be finite and > 0");
@@ -1222,6 +1264,28 @@ int sj_dbscan(const double *pts, uint64_t n, uint32_t d, double eps, uint32_t mi
     });
     sj_destroy_index(ix);
     return rc;
+}
+
+int sj_bruteforce_noalloc(const double *pts_dev, uint64_t n, uint32_t d, double eps, uint32_t *pairs_dev,
+                          uint64_t capacity_pairs, void *stream, uint64_t *total_pairs) {
+    hipStream_t s = as_stream(stream);
+    return guarded(s, [&] {
+        validate_brute_args(pts_dev, n, d, eps);
+        if (total_pairs) *total_pairs = 0;
+        if (n == 0) return;
+        const BrutePlan pl = brute_plan(n, d);
+        const size_t cells = static_cast<size_t>(n) * pl.splits;
+        if (cells > sj::kNoAllocCells || sj::scan_partials(cells) > sj::kNaPartWords)
+            throw Error(SJ_EINVAL, "sj_bruteforce_noalloc takes at most " + std::to_string(sj::kNoAllocCells) +
+                                       " points (" + std::to_string(n) + " given)");
+        unsigned char *base = scratch_on_current_device();
+        uint64_t readback = 0;  // pageable host word: no pinned staging block
+        brute_join(pts_dev, n, d, eps, pl, reinterpret_cast<uint32_t *>(base + sj::kNaCountOff),
+                   reinterpret_cast<uint64_t *>(base + sj::kNaOffOff),
+                   reinterpret_cast<uint64_t *>(base + sj::kNaPartOff),
+                   reinterpret_cast<uint32_t *>(base + sj::kNaFlagOff), &readback, pairs_dev, capacity_pairs, s,
+                   total_pairs);
+    });
 }
 
 int sj_selfjoin_index(sj_index *idx, const sj_join_opts *opts, sj_run_cb cb, void *user,
