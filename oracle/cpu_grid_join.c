@@ -9,15 +9,18 @@
  * The method of Section IV on the host, written plainly: cells of width
  * w >= eps (Section IV-B), points sorted by linearised cell id so each
  * non-empty cell is one run of the sorted order (Section IV-C), and for each
- * point the 3^d adjacent cells looked up by binary search among the non-empty
- * cell ids and scanned (Algorithm 1). The pair test is the oracle's: squared
+ * non-empty cell the 3^d adjacent cells looked up by binary search among the
+ * non-empty cell ids (Algorithm 1's lookup; every point of a cell has the
+ * same adjacent cells) and their points scanned for each point of the cell.
+ * The coordinates are read from a copy in the sorted order, so a cell's
+ * points are contiguous in memory; the pair test is the oracle's: squared
  * distance in binary64, dimension order 0..d-1, no fused multiply-add
  * (-ffp-contract=off), accepted iff d2 <= fl(eps * eps). Every row's
  * neighbours are sorted ascending, so the pairs come out sorted by (i, j),
  * the same result as sjo_fill_rows.
  *
- * Query points are processed in parallel with OpenMP; the result does not
- * depend on the thread count.
+ * Cells are processed in parallel with OpenMP; the result does not depend
+ * on the thread count.
  */
 #include <math.h>
 #include <stdint.h>
@@ -64,6 +67,7 @@ typedef struct {
     uint64_t *cell_start;/* ncells + 1 */
     uint32_t *order;     /* point ids in cell order */
     uint32_t *coord;     /* n x d cell coordinates of each point */
+    double *xs;          /* n x d coordinates in cell order: xs[r] = x[order[r]] */
 } sjg_grid;
 
 static uint64_t sjg_coord(double v, double lo, double w, uint64_t dim)
@@ -142,6 +146,11 @@ static int sjg_build(const double *x, int64_t n, int d, double eps, sjg_grid *g)
     g->cell_start[nc] = (uint64_t)n;
     g->ncells = nc;
     free(items);
+    g->xs = (double *)malloc((size_t)n * (size_t)d * sizeof(double));
+    if (!g->xs) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n; ++r)
+        for (int k = 0; k < d; ++k) g->xs[r * d + k] = x[(int64_t)g->order[r] * d + k];
     return 0;
 }
 
@@ -151,6 +160,7 @@ static void sjg_free(sjg_grid *g)
     free(g->cell_start);
     free(g->order);
     free(g->coord);
+    free(g->xs);
 }
 
 /* position of key among the non-empty cells, or -1 */
@@ -168,24 +178,22 @@ static int64_t sjg_find(const sjg_grid *g, uint64_t key)
 }
 
 /*
- * Neighbours of point i into buf (capacity cap); returns the row length
- * (which may exceed cap: then only the count is valid). Candidates are the
- * points of the 3^d cells around i's cell.
+ * Point ranges [lo, hi) of the sorted order covering the non-empty cells
+ * among the 3^d cells adjacent to cell h (h itself included); returns their
+ * number (at most 3^d, the capacity of rng).
  */
-static uint64_t sjg_row(const double *x, const sjg_grid *g, int64_t i, double eps2, uint32_t *buf,
-                        uint64_t cap)
+static int sjg_adjacent(const sjg_grid *g, uint64_t h, uint64_t *rng)
 {
     const int d = g->d;
-    int64_t c[SJG_MAX_DIM];
-    for (int k = 0; k < d; ++k) c[k] = (int64_t)g->coord[i * d + k];
+    const uint32_t *c0 = g->coord + (int64_t)g->order[g->cell_start[h]] * d;
     int off[SJG_MAX_DIM];
     for (int k = 0; k < d; ++k) off[k] = -1;
-    uint64_t len = 0;
+    int m = 0;
     for (;;) {
         int inside = 1;
         uint64_t key = 0;
         for (int k = 0; k < d; ++k) {
-            int64_t v = c[k] + off[k];
+            int64_t v = (int64_t)c0[k] + off[k];
             if (v < 0 || v >= (int64_t)g->dims[k]) {
                 inside = 0;
                 break;
@@ -193,21 +201,38 @@ static uint64_t sjg_row(const double *x, const sjg_grid *g, int64_t i, double ep
             key += (uint64_t)v * g->stride[k];
         }
         if (inside) {
-            int64_t h = sjg_find(g, key);
-            if (h >= 0)
-                for (uint64_t r = g->cell_start[h]; r < g->cell_start[h + 1]; ++r) {
-                    uint32_t j = g->order[r];
-                    if (sjg_within(x + i * d, x + (int64_t)j * d, d, eps2)) {
-                        if (len < cap) buf[len] = j;
-                        ++len;
-                    }
-                }
+            int64_t a = sjg_find(g, key);
+            if (a >= 0) {
+                rng[2 * m] = g->cell_start[a];
+                rng[2 * m + 1] = g->cell_start[a + 1];
+                ++m;
+            }
         }
         int k = 0;
         while (k < d && off[k] == 1) off[k++] = -1;
         if (k == d) break;
         ++off[k];
     }
+    return m;
+}
+
+/*
+ * Neighbours of the point at sorted position p into buf (capacity cap),
+ * scanning the ranges of its cell's adjacent cells; returns the row length
+ * (which may exceed cap: then only the count is valid).
+ */
+static uint64_t sjg_row(const sjg_grid *g, uint64_t p, const uint64_t *rng, int m, double eps2, uint32_t *buf,
+                        uint64_t cap)
+{
+    const int d = g->d;
+    const double *a = g->xs + (int64_t)p * d;
+    uint64_t len = 0;
+    for (int e = 0; e < m; ++e)
+        for (uint64_t r = rng[2 * e]; r < rng[2 * e + 1]; ++r)
+            if (sjg_within(a, g->xs + (int64_t)r * d, d, eps2)) {
+                if (len < cap) buf[len] = g->order[r];
+                ++len;
+            }
     return len;
 }
 
@@ -225,12 +250,33 @@ int64_t sjg_grid_join(const double *x, int64_t n, int64_t d, double eps, int64_t
         sjg_free(&g);
         return -1;
     }
+    int adj = 1;
+    for (int k = 0; k < d; ++k) adj *= 3;
     const double eps2 = eps * eps;
     int64_t total = 0;
-#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : total)
-    for (int64_t i = 0; i < n; ++i) {
-        counts[i] = (int64_t)sjg_row(x, &g, i, eps2, NULL, 0);
-        total += counts[i];
+    int fail = 0;
+#pragma omp parallel reduction(+ : total)
+    {
+        uint64_t *rng = (uint64_t *)malloc((size_t)adj * 2 * sizeof(uint64_t));
+        if (!rng) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t h = 0; h < (int64_t)g.ncells; ++h) {
+            if (!rng) continue;
+            const int m = sjg_adjacent(&g, (uint64_t)h, rng);
+            for (uint64_t p = g.cell_start[h]; p < g.cell_start[h + 1]; ++p) {
+                const int64_t c = (int64_t)sjg_row(&g, p, rng, m, eps2, NULL, 0);
+                counts[g.order[p]] = c;
+                total += c;
+            }
+        }
+        free(rng);
+    }
+    if (fail) {
+        sjg_free(&g);
+        return -1;
     }
     if (pairs) {
         int64_t *off = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
@@ -244,21 +290,27 @@ int64_t sjg_grid_join(const double *x, int64_t n, int64_t d, double eps, int64_t
         {
             uint64_t cap = 1024;
             uint32_t *buf = (uint32_t *)malloc(cap * sizeof(uint32_t));
-#pragma omp for schedule(dynamic, 1024)
-            for (int64_t i = 0; i < n; ++i) {
-                if ((uint64_t)counts[i] > cap) {
-                    cap = (uint64_t)counts[i];
-                    free(buf);
-                    buf = (uint32_t *)malloc(cap * sizeof(uint32_t));
-                }
-                uint64_t len = sjg_row(x, &g, i, eps2, buf, cap);
-                qsort(buf, (size_t)len, sizeof(uint32_t), sjg_cmp_u32);
-                for (uint64_t k = 0; k < len; ++k) {
-                    pairs[2 * (off[i] + (int64_t)k)] = (int32_t)i;
-                    pairs[2 * (off[i] + (int64_t)k) + 1] = (int32_t)buf[k];
+            uint64_t *rng = (uint64_t *)malloc((size_t)adj * 2 * sizeof(uint64_t));
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t h = 0; h < (int64_t)g.ncells; ++h) {
+                const int m = sjg_adjacent(&g, (uint64_t)h, rng);
+                for (uint64_t p = g.cell_start[h]; p < g.cell_start[h + 1]; ++p) {
+                    const uint32_t i = g.order[p];
+                    if ((uint64_t)counts[i] > cap) {
+                        cap = (uint64_t)counts[i];
+                        free(buf);
+                        buf = (uint32_t *)malloc(cap * sizeof(uint32_t));
+                    }
+                    const uint64_t len = sjg_row(&g, p, rng, m, eps2, buf, cap);
+                    qsort(buf, (size_t)len, sizeof(uint32_t), sjg_cmp_u32);
+                    for (uint64_t k = 0; k < len; ++k) {
+                        pairs[2 * (off[i] + (int64_t)k)] = (int32_t)i;
+                        pairs[2 * (off[i] + (int64_t)k) + 1] = (int32_t)buf[k];
+                    }
                 }
             }
             free(buf);
+            free(rng);
         }
         free(off);
     }
