@@ -26,6 +26,8 @@ Beside `value` (pairs/s of the timed steps) the line carries:
   valu_roofline / hbm_roofline   both fractions for that kernel;
   legs             the other configurations and modes:
                      unicomp_off      the same step without unicomp;
+                     fp32_band        the same step with the FP32 pre-test
+                                      and FP64 band re-decision;
                      batched          the same joins delivered in 2^27-pair
                                       batches (result larger than one batch);
                      clustered_5M     5,000,000 clustered points in 2-D and
@@ -688,6 +690,8 @@ def main():
         if args.workload == DEFAULT_WORKLOAD:
             legs["unicomp_off"] = sweep_leg(sj, _lib, torch, wl, 2, unicomp=False, label="unicomp off")
             legs["unicomp_off"]["vs_unicomp_on"] = round(legs["unicomp_off"]["pairs_per_s"] / value, 4)
+            legs["fp32_band"] = sweep_leg(sj, _lib, torch, wl, 2, precision="fp32_band", label="fp32+band")
+            legs["fp32_band"]["vs_fp64"] = round(legs["fp32_band"]["pairs_per_s"] / value, 4)
             legs["batched"] = batched_leg(sj, torch, wl, 1 << 27)
             legs["batched"]["vs_unbatched"] = round(legs["batched"]["pairs_per_s"] / value, 4)
         for name, key, steps in (("clustered_5M", "clustered_n5M_d2-3_median50", 3),

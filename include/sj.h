@@ -193,6 +193,19 @@ int sj_join_rs(sj_index *idx, const double *R, uint64_t nr, int r_on_device, uin
                uint64_t capacity_pairs, void *stream, uint64_t *total_pairs);
 
 /*
+ * The same two-set join in two calls, for callers that size the output
+ * from P: sj_join_rs_count runs the query sort and the count pass and
+ * returns P; sj_join_rs_fill then writes the pairs (capacity_pairs >= P, else
+ * SJ_ECAPACITY and nothing written) without repeating either. Between the
+ * two calls device queries must stay valid and unchanged (host queries are
+ * copied to the device by the count call). A later count replaces the
+ * state; the self-join's count/fill state is separate.
+ */
+int sj_join_rs_count(sj_index *idx, const double *R, uint64_t nr, int r_on_device, void *stream,
+                     uint64_t *total_pairs);
+int sj_join_rs_fill(sj_index *idx, uint32_t *pairs_dev, uint64_t capacity_pairs, void *stream);
+
+/*
  * Batched join (Section V-A): the result is delivered in at least
  * opts->min_batches runs of at most opts->batch_capacity_pairs pairs each,
  * sized from the exact row lengths of the count pass. Run b holds every
@@ -333,7 +346,11 @@ int sj_band_thresholds(uint32_t d, double eps, double extent, float *lo, float *
  * counted against the budget, until sj_server_release.
  *
  * Points passed to sj_server_submit must stay valid (and unchanged) until
- * the request completes; they may be device or host memory.
+ * the request completes; they may be device or host memory. The request is
+ * read on the server's own worker stream, which is not ordered after any of
+ * the caller's streams: device points must be complete when sj_server_submit
+ * is called (the stream that wrote them synchronised, or an event on it
+ * waited for).
  */
 typedef struct sj_server sj_server;
 
@@ -370,8 +387,10 @@ typedef struct sj_server_info_t {
 } sj_server_info_t;
 
 int  sj_server_create(const sj_server_opts *opts, sj_server **out);
-/* Queues a request; *req_id identifies it. opts may be NULL (defaults);
- * expected_pairs 0 means "about n". Never blocks on device work. */
+/* Queues a self-join request (the join of Section III with the method of
+ * Sections IV-V; opts as for sj_join_count); *req_id identifies it. opts may
+ * be NULL (defaults); expected_pairs 0 means "about n". Never blocks on
+ * device work; see above for the ordering of device points. */
 int  sj_server_submit(sj_server *srv, const double *pts, uint64_t n, uint32_t d, double eps,
                       int pts_on_device, const sj_join_opts *opts, uint64_t expected_pairs,
                       uint64_t *req_id);

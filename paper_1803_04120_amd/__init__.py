@@ -136,14 +136,15 @@ class Index:
             P = int(total.value)
             del keep
             return out[:P] if out.shape[0] != P else out
-        _lib.check(L.sj_join_rs(self._h, ptr, nr, on_dev, None, 0, _stream_handle(self._stream),
-                                ctypes.byref(total)))
+        # count once, allocate the exact result, fill from the count's state
+        _lib.check(L.sj_join_rs_count(self._h, ptr, nr, on_dev, _stream_handle(self._stream),
+                                      ctypes.byref(total)))
         P = int(total.value)
         dev = self._device or torch.device("cuda")
         out = torch.empty((P, 2), dtype=torch.int32, device=dev)
         if P:
-            _lib.check(L.sj_join_rs(self._h, ptr, nr, on_dev, ctypes.c_void_p(out.data_ptr()), P,
-                                    _stream_handle(self._stream), ctypes.byref(total)))
+            _lib.check(L.sj_join_rs_fill(self._h, ctypes.c_void_p(out.data_ptr()), P,
+                                         _stream_handle(self._stream)))
         del keep
         return out
 

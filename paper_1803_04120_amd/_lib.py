@@ -110,6 +110,8 @@ def load():
         "sj_dbscan_csr": (ctypes.c_int, [vp, vp, u64, u32, vp, vp, ctypes.POINTER(u64)]),
         "sj_dbscan": (ctypes.c_int, [vp, u64, u32, dbl, u32, ctypes.c_int, vp, vp, ctypes.POINTER(u64)]),
         "sj_join_rs": (ctypes.c_int, [vp, vp, u64, ctypes.c_int, vp, u64, vp, ctypes.POINTER(u64)]),
+        "sj_join_rs_count": (ctypes.c_int, [vp, vp, u64, ctypes.c_int, vp, ctypes.POINTER(u64)]),
+        "sj_join_rs_fill": (ctypes.c_int, [vp, vp, u64, vp]),
         "sj_selfjoin_index": (ctypes.c_int, [vp, ctypes.POINTER(SjJoinOpts), RUN_CB, vp, vp,
                                              ctypes.POINTER(ctypes.c_uint64)]),
         "sj_selfjoin": (ctypes.c_int, [vp, u64, u32, dbl, ctypes.POINTER(SjJoinOpts), ctypes.c_int,

@@ -193,6 +193,9 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         };
         // candidates [i0, i1) of the staged tile, kUnroll of them loaded and
         // tested before any is emitted
+        // (two from 4-D on: four candidates' coordinates would take the
+        // registers of two waves per SIMD; the count takes one branch per
+        // step for the rare mirrored hits)
         constexpr int kUnroll = D <= 3 ? 4 : 2;
         auto run = [&](uint32_t T0, uint32_t i0, uint32_t i1) {
             if (i0 >= i1) return;
@@ -205,8 +208,22 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 for (int u = 0; u < kUnroll; ++u) id[u] = kPerm ? saux[i + u] : 0u;
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) h[u] = test(i + u, T0 + i + u);
+                if (kMode == kCount) {
+                    bool any = false;
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) emit(h[u], i + u, T0 + i + u, id[u], kUni && T0 + i + u != p);
+                    for (int u = 0; u < kUnroll; ++u) {
+                        own += h[u] ? 1u : 0u;
+                        any = any || h[u];
+                    }
+                    if (kUni && any) {
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u)
+                            if (h[u] && T0 + i + u != p) atomicAdd(&saux[i + u], 1u);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u) emit(h[u], i + u, T0 + i + u, id[u], kUni && T0 + i + u != p);
+                }
             }
             for (; i < i1; ++i) {
                 const uint32_t id = kPerm ? saux[i] : 0u;

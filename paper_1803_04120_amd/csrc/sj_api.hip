@@ -191,6 +191,18 @@ struct sj_index {
     uint32_t max_row = 0;
     uint64_t rows_longer[3] = {0, 0, 0};  // rows longer than 16, 24, 32
     sj_stats stats{};
+    // two-set join state between its count and fill (sj_join_rs_count /
+    // sj_join_rs_fill): the queries (staged copy if they came from the host),
+    // their order, row offsets by query row and by probe position
+    struct RsState {
+        bool counted = false;
+        const double *R = nullptr;
+        DevBuf<double> staged;
+        uint64_t nr = 0, P = 0;
+        uint32_t max_len = 0;
+        DevBuf<uint32_t> qperm, cnt, cnt_k, words;
+        DevBuf<uint64_t> off, off_k;
+    } rs;
 
     ~sj_index() {
         for (auto &r : ranges)
@@ -669,14 +681,18 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
 // takes a global slot with an atomic) or all adjacent cells (each point
 // writes only its own row, no atomics, twice the distance evaluations).
 // Both fill the same rows. When pairs are a large fraction of the unicomp
-// evaluations the atomics cost more than the extra evaluations.
+// evaluations the atomics cost more than the extra evaluations: the unicomp
+// fill is taken below 8%.
 // SJ_FILL_MODE=full|unicomp overrides the choice.
 bool choose_unicomp_fill(const sj_index &ix) {
     if (!ix.opts.unicomp) return false;
     const char *e = std::getenv("SJ_FILL_MODE");
     if (e && std::strcmp(e, "full") == 0) return false;
     if (e && std::strcmp(e, "unicomp") == 0) return true;
-    return static_cast<double>(ix.pairs) < 0.05 * static_cast<double>(ix.stats.evals);
+    // measured on the 10M-point joins: unicomp fill faster at 5.0% (5-D, 32
+    // neighbours: 12.1 against 16.1 ms), even at 5.3% (5-D, 256), slower at
+    // about 12% (4-D: 6.7 against 5.0 ms, and 92 against 27 ms)
+    return static_cast<double>(ix.pairs) < 0.08 * static_cast<double>(ix.stats.evals);
 }
 
 void join_fill_all(sj_index &ix, uint32_t *pairs_dev, hipStream_t s, uint32_t *cols_dev = nullptr) {
@@ -1007,6 +1023,106 @@ void validate_brute_args(const double *pts, uint64_t n, uint32_t d, double eps) 
     if (n > 0 && !pts) throw Error(SJ_EINVAL, "pts is NULL");
 }
 
+// ---------------------------------------------------------------- two-set join
+sj::RsArgs rs_args(sj_index &ix) {
+    sj::RsArgs a{};
+    a.R = ix.rs.R;
+    a.nr = ix.rs.nr;
+    a.qperm = ix.rs.qperm.ptr;
+    a.X = ix.X.ptr;
+    a.ns = ix.n;
+    a.perm = ix.perm.ptr;
+    a.B = ix.B.ptr;
+    a.starts = ix.starts.ptr;
+    a.ncells = static_cast<uint32_t>(ix.ncells);
+    a.g = ix.grid;
+    a.eps2 = ix.eps * ix.eps;
+    return a;
+}
+
+// Count pass of R x S: queries in S's cell order (the index's cell key and
+// radix sort), so that a wave's queries share candidate cells; row offsets
+// by query row (output) and by probe position (fill layout); P and the
+// longest row. State kept in ix.rs for rs_fill.
+void rs_count(sj_index &ix, const double *R, uint64_t nr, int r_on_device, hipStream_t s) {
+    auto &st = ix.rs;
+    st.counted = false;
+    st.P = 0;
+    st.nr = nr;
+    if (nr && !R) throw Error(SJ_EINVAL, "R is NULL");
+    if (nr >= 0x7fffffffULL) throw Error(SJ_EINVAL, "too many query rows");
+    if (nr == 0 || ix.n == 0) {
+        st.counted = true;
+        return;
+    }
+    const uint32_t d = ix.d;
+    const double *rp = R;
+    if (!r_on_device) {
+        st.staged.ensure(nr * d);
+        SJ_HIP(hipMemcpyAsync(st.staged.ptr, R, nr * d * sizeof(double), hipMemcpyHostToDevice, s));
+        rp = st.staged.ptr;
+    }
+    st.R = rp;
+    st.qperm.ensure(nr);
+    {
+        DevBuf<uint32_t> qperm_alt(nr);
+        DevBuf<uint64_t> k64(nr), k64_alt(nr);
+        if (ix.key_bits <= 32) {
+            uint32_t *k = reinterpret_cast<uint32_t *>(k64.ptr), *k2 = reinterpret_cast<uint32_t *>(k64_alt.ptr);
+            sj::launch_cell_keys_u32(rp, nr, ix.grid, k, st.qperm.ptr, s);
+            if (sj::radix_sort_u32(k, st.qperm.ptr, k2, qperm_alt.ptr, nr, ix.key_bits, s))
+                std::swap(st.qperm, qperm_alt);
+        } else {
+            sj::launch_cell_keys_u64(rp, nr, ix.grid, k64.ptr, st.qperm.ptr, s);
+            if (sj::radix_sort_u64(k64.ptr, st.qperm.ptr, k64_alt.ptr, qperm_alt.ptr, nr, ix.key_bits, s))
+                std::swap(st.qperm, qperm_alt);
+        }
+    }
+    sj::RsArgs a = rs_args(ix);
+    st.cnt.ensure(nr);
+    st.cnt_k.ensure(nr);
+    st.words.ensure(2);
+    st.off.ensure(nr + 1);
+    st.off_k.ensure(nr + 1);
+    a.count = st.cnt.ptr;
+    a.count_k = st.cnt_k.ptr;
+    sj::launch_join_rs(a, 0, s);
+    sj::scan_exclusive_u32_to_u64_x2(st.cnt.ptr, st.off.ptr, st.cnt_k.ptr, st.off_k.ptr, nr, s);
+    sj::launch_fill_u32(st.words.ptr, 2, 0u, s);
+    sj::launch_rs_max(st.cnt.ptr, nr, st.words.ptr, s);
+    sj::HostStage hs;
+    SJ_HIP(hipMemcpyAsync(hs.p, st.off.ptr + nr, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(hs.as<uint32_t>() + 2, st.words.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    st.P = *hs.as<uint64_t>();
+    st.max_len = hs.as<uint32_t>()[2];
+    st.counted = true;
+}
+
+// Fill pass: neighbour ids per query in probe order, unsorted, then each row
+// sorted and written as (i, j) pairs at its offset in R's order.
+void rs_fill(sj_index &ix, uint32_t *pairs_dev, uint64_t cap, hipStream_t s) {
+    auto &st = ix.rs;
+    const uint64_t P = st.P;
+    if (P == 0) return;
+    if (!pairs_dev) throw Error(SJ_EINVAL, "pairs_dev is NULL");
+    if (cap < P)
+        throw Error(SJ_ECAPACITY, "output buffer holds " + std::to_string(cap) + " pairs, the result has " +
+                                      std::to_string(P));
+    sj::RsArgs a = rs_args(ix);
+    DevBuf<uint32_t> out_j(P);
+    a.off = st.off_k.ptr;
+    a.out_j = out_j.ptr;
+    a.out_cap = P;
+    a.overflow = st.words.ptr + 1;
+    sj::launch_join_rs(a, 1, s);
+    sj::launch_rowsort_cells(st.off_k.ptr, st.off.ptr, st.qperm.ptr, st.nr, out_j.ptr, pairs_dev, st.max_len, s);
+    sj::HostStage hs;
+    SJ_HIP(hipMemcpyAsync(hs.p, st.words.ptr + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    if (*hs.as<uint32_t>()) throw Error(SJ_EDEVICE, "internal: the two-set fill disagreed with its count");
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -1100,85 +1216,35 @@ int sj_join_fill_csr(sj_index *idx, uint64_t *row_off_dev, uint32_t *cols_dev, u
     });
 }
 
+int sj_join_rs_count(sj_index *idx, const double *R, uint64_t nr, int r_on_device, void *stream,
+                     uint64_t *total_pairs) {
+    hipStream_t s = as_stream(stream);
+    return guarded(s, [&] {
+        if (!idx) throw Error(SJ_EINVAL, "index is NULL");
+        rs_count(*idx, R, nr, r_on_device, s);
+        if (total_pairs) *total_pairs = idx->rs.P;
+    });
+}
+
+int sj_join_rs_fill(sj_index *idx, uint32_t *pairs_dev, uint64_t capacity_pairs, void *stream) {
+    hipStream_t s = as_stream(stream);
+    return guarded(s, [&] {
+        if (!idx) throw Error(SJ_EINVAL, "index is NULL");
+        if (!idx->rs.counted) throw Error(SJ_ESTATE, "sj_join_rs_fill needs a preceding sj_join_rs_count");
+        rs_fill(*idx, pairs_dev, capacity_pairs, s);
+    });
+}
+
 int sj_join_rs(sj_index *idx, const double *R, uint64_t nr, int r_on_device, uint32_t *pairs_dev,
                uint64_t capacity_pairs, void *stream, uint64_t *total_pairs) {
     hipStream_t s = as_stream(stream);
     return guarded(s, [&] {
         if (!idx) throw Error(SJ_EINVAL, "index is NULL");
-        if (nr && !R) throw Error(SJ_EINVAL, "R is NULL");
-        if (nr >= 0x7fffffffULL) throw Error(SJ_EINVAL, "too many query rows");
-        sj_index &ix = *idx;
         if (total_pairs) *total_pairs = 0;
-        if (nr == 0 || ix.n == 0) return;
-        const uint32_t d = ix.d;
-        DevBuf<double> staged;
-        const double *rp = R;
-        if (!r_on_device) {
-            staged.reset(nr * d);
-            SJ_HIP(hipMemcpyAsync(staged.ptr, R, nr * d * sizeof(double), hipMemcpyHostToDevice, s));
-            rp = staged.ptr;
-        }
-        // queries in S's cell order (the index's cell key and radix sort),
-        // so that a wave's queries share candidate cells
-        DevBuf<uint32_t> qperm(nr), qperm_alt(nr);
-        {
-            DevBuf<uint64_t> k64(nr), k64_alt(nr);
-            if (ix.key_bits <= 32) {
-                uint32_t *k = reinterpret_cast<uint32_t *>(k64.ptr), *k2 = reinterpret_cast<uint32_t *>(k64_alt.ptr);
-                sj::launch_cell_keys_u32(rp, nr, ix.grid, k, qperm.ptr, s);
-                if (sj::radix_sort_u32(k, qperm.ptr, k2, qperm_alt.ptr, nr, ix.key_bits, s)) std::swap(qperm, qperm_alt);
-            } else {
-                sj::launch_cell_keys_u64(rp, nr, ix.grid, k64.ptr, qperm.ptr, s);
-                if (sj::radix_sort_u64(k64.ptr, qperm.ptr, k64_alt.ptr, qperm_alt.ptr, nr, ix.key_bits, s))
-                    std::swap(qperm, qperm_alt);
-            }
-        }
-        sj::RsArgs a{};
-        a.R = rp;
-        a.nr = nr;
-        a.qperm = qperm.ptr;
-        a.X = ix.X.ptr;
-        a.ns = ix.n;
-        a.perm = ix.perm.ptr;
-        a.B = ix.B.ptr;
-        a.starts = ix.starts.ptr;
-        a.ncells = static_cast<uint32_t>(ix.ncells);
-        a.g = ix.grid;
-        a.eps2 = ix.eps * ix.eps;
-        // count pass; row offsets in R's order (output) and in probe order
-        // (fill); longest row and P
-        DevBuf<uint32_t> cnt(nr), cnt_k(nr), words(2);
-        DevBuf<uint64_t> off(nr + 1), off_k(nr + 1);
-        a.count = cnt.ptr;
-        a.count_k = cnt_k.ptr;
-        sj::launch_join_rs(a, 0, s);
-        sj::scan_exclusive_u32_to_u64(cnt.ptr, off.ptr, nr, s);
-        sj::scan_exclusive_u32_to_u64(cnt_k.ptr, off_k.ptr, nr, s);
-        sj::launch_fill_u32(words.ptr, 2, 0u, s);
-        sj::launch_rs_max(cnt.ptr, nr, words.ptr, s);
-        sj::HostStage hs;
-        SJ_HIP(hipMemcpyAsync(hs.p, off.ptr + nr, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-        SJ_HIP(hipMemcpyAsync(hs.as<uint32_t>() + 2, words.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        SJ_HIP(hipStreamSynchronize(s));
-        const uint64_t P = *hs.as<uint64_t>();
-        const uint32_t max_len = hs.as<uint32_t>()[2];
-        if (total_pairs) *total_pairs = P;
-        if (!pairs_dev || P == 0) return;
-        if (capacity_pairs < P)
-            throw Error(SJ_ECAPACITY, "output buffer holds " + std::to_string(capacity_pairs) +
-                                          " pairs, the result has " + std::to_string(P));
-        // fill pass (neighbour ids per query in probe order, unsorted), then
-        // each row sorted and written as (i, j) pairs at its offset in R's order
-        DevBuf<uint32_t> out_j(P);
-        a.off = off_k.ptr;
-        a.out_j = out_j.ptr;
-        a.out_cap = P;
-        a.overflow = words.ptr + 1;
-        sj::launch_join_rs(a, 1, s);
-        sj::launch_rowsort_cells(off_k.ptr, off.ptr, qperm.ptr, nr, out_j.ptr, pairs_dev, max_len, s);
-        SJ_HIP(hipMemcpyAsync(hs.p, words.ptr + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        SJ_HIP(hipStreamSynchronize(s));
-        if (*hs.as<uint32_t>()) throw Error(SJ_EDEVICE, "internal: the two-set fill disagreed with its count");
+        rs_count(*idx, R, nr, r_on_device, s);
+        if (total_pairs) *total_pairs = idx->rs.P;
+        if (pairs_dev) rs_fill(*idx, pairs_dev, capacity_pairs, s);
+        idx->rs.counted = false;  // the one-call form keeps no state
     });
 }
 

@@ -296,7 +296,9 @@ int sj_server_poll(sj_server *S, sj_completion *out, uint32_t cap, uint32_t *cou
     while (k < cap && !S->done.empty()) {
         const uint64_t id = S->done.front();
         S->done.pop_front();
-        Request *r = S->all[id];
+        const auto it = S->all.find(id);
+        if (it == S->all.end()) continue;  // released before it was polled
+        Request *r = it->second;
         sj_completion &c = out[k++];
         std::memset(&c, 0, sizeof(c));
         c.req_id = id;
@@ -323,6 +325,11 @@ int sj_server_release(sj_server *S, uint64_t req_id) {
         if (it == S->all.end() || it->second->t_done == Clock::time_point{}) return SJ_ESTATE;
         r = it->second;
         S->all.erase(it);
+        for (auto d = S->done.begin(); d != S->done.end(); ++d)
+            if (*d == req_id) {
+                S->done.erase(d);
+                break;
+            }
         S->mem_used -= r->held_bytes;
         --S->holders;
         S->cv_work.notify_all();

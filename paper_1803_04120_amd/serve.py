@@ -77,7 +77,10 @@ class Server:
         self._keep = {}  # req_id -> input kept alive until completion
 
     def submit(self, points, eps: float, *, unicomp: bool = True, precision: str = "fp32_band",
-               expected_pairs: int = 0) -> int:
+               expected_pairs: int = 0, sync: bool = True) -> int:
+        """Queue a request. The server reads device points on its own streams,
+        so with sync (the default) torch's current stream is synchronised first;
+        pass sync=False when the points are known to be complete."""
         try:
             import torch
             is_tensor = isinstance(points, torch.Tensor)
@@ -88,6 +91,8 @@ class Server:
             if t.dtype != torch.float64 or t.dim() != 2:
                 raise ValueError("points must be a (n, d) float64 tensor")
             ptr, n, d, on_dev, keep = t.data_ptr(), t.shape[0], t.shape[1], int(t.is_cuda), t
+            if on_dev and sync:
+                torch.cuda.current_stream(t.device).synchronize()
         else:
             a = np.ascontiguousarray(np.asarray(points, dtype=np.float64))
             ptr, n, d, on_dev, keep = a.ctypes.data, a.shape[0], a.shape[1], 0, a
@@ -163,7 +168,8 @@ def uniform_eps_for_k(n: int, d: int, k: float, box: float = 100.0) -> float:
 def run_stream(server: Server, requests, arrivals_s, on_complete=None, poll_ms: int = 1):
     """Open-loop replay: request r is submitted at arrivals_s[r] (seconds from
     the start) regardless of what is running. requests[r] is a dict with
-    points, eps, precision, unicomp, expected_pairs. on_complete(r_index,
+    points, eps, precision, unicomp, expected_pairs; device points must be
+    complete before the call (they are submitted without synchronising). on_complete(r_index,
     completion) may inspect the result before it is released.
     Returns per-request completions (in request order) and the makespan."""
     order = np.argsort(np.asarray(arrivals_s))
@@ -178,7 +184,7 @@ def run_stream(server: Server, requests, arrivals_s, on_complete=None, poll_ms: 
             q = requests[r]
             rid = server.submit(q["points"], q["eps"], unicomp=q.get("unicomp", True),
                                 precision=q.get("precision", "fp32_band"),
-                                expected_pairs=q.get("expected_pairs", 0))
+                                expected_pairs=q.get("expected_pairs", 0), sync=False)
             pending[rid] = r
             nxt += 1
         wait = poll_ms

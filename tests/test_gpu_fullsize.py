@@ -1,12 +1,17 @@
 """Parity at the full workload sizes (GPU).
 
-The brute-force oracle cannot produce whole results of millions of points,
-so each full-size join is checked on a seeded sample of result rows that the
-oracle computes one by one (all n candidates for each sampled row), plus
-exact equalities that hold at any size: unicomp on = off, FP32 pre-test =
-FP64, batched = unbatched, row lengths summing to P, symmetry of the row
-lengths with the oracle's counts. The joins run through the same entry
-points and launch configuration as bench.py (count pass, whole-result fill).
+Whole results are compared pair for pair with the host-core grid join
+(oracle/cpu_grid_join.c, itself checked against the brute force) wherever
+it finishes in about a minute on the host: the 2M-point 2-D sweep, the
+10M-point 3..6-D joins at 32 neighbours per point, the 5M-point clustered
+joins in both precisions and the two-set join. Every join is also checked
+on a seeded sample of result rows that the brute-force oracle computes one
+by one against all n candidates (4096 rows for the 10M-point joins at 256
+neighbours, whose whole results the host join would take many minutes to
+produce), plus exact equalities that hold at any size: unicomp on = off,
+FP32 pre-test = FP64, batched = unbatched, unicomp evaluations = (T + n) / 2.
+The joins run through the same entry points and launch configuration as
+bench.py (count pass, whole-result fill).
 """
 from __future__ import annotations
 
@@ -55,17 +60,26 @@ def _join(sj, x, eps, **kw):
     return out, off, stats
 
 
-def _check_rows(pts, eps, out, off, seed):
+def _check_rows(pts, eps, out, off, seed, nrows=SAMPLE_ROWS):
     n = pts.shape[0]
-    rows = np.sort(np.random.default_rng(seed).choice(n, SAMPLE_ROWS, replace=False))
+    rows = np.sort(np.random.default_rng(seed).choice(n, nrows, replace=False))
     roff, js = ref.rows_neighbors(pts, eps, rows)
+    host = out if isinstance(out, np.ndarray) else None
     for k, i in enumerate(rows):
         a, b = int(off[i]), int(off[i + 1])
-        seg = out[a:b].cpu().numpy().astype(np.int64)
+        seg = (host[a:b] if host is not None else out[a:b].cpu().numpy()).astype(np.int64)
         want = js[roff[k]:roff[k + 1]].astype(np.int64)
         assert np.all(seg[:, 0] == i), f"row {i}: wrong row ids"
         np.testing.assert_array_equal(seg[:, 1], want, err_msg=f"row {i} differs")
     return rows
+
+
+def _whole_vs_grid_join(pts, eps, got, off):
+    """The whole GPU result (host copy) against the host-core grid join."""
+    counts, want = ref.grid_join(pts, eps)
+    np.testing.assert_array_equal(np.diff(off), counts)
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
 
 
 def test_uniform_2d_2M_eps_sweep(sj):
@@ -105,7 +119,9 @@ def test_uniform_2d_2M_whole_result_vs_cpu_grid_join(sj, eps):
                                  "d5_k32", "d5_k256", "d6_k32", "d6_k256"])
 def test_uniform_10M(sj, key):
     """10,000,000 uniform points in 3..6-D at eps for mean 32 / 256
-    neighbours; unicomp on vs off must agree exactly."""
+    neighbours: the whole result against the host grid join (32
+    neighbours) or 4096 sampled rows against the brute force (256); unicomp
+    on vs off must agree exactly."""
     c = _calib()["uniform_n10M"][key]
     _say(f"uniform n=10M {key} eps={c['eps']}")
     pts = datagen.uniform(c["n"], c["d"], seed=c["seed"])
@@ -114,33 +130,52 @@ def test_uniform_10M(sj, key):
     assert off[-1] == out.shape[0]
     mean_k = out.shape[0] / c["n"] - 1
     assert abs(mean_k - c["k_mean"]) < 0.05 * c["k_mean"]
-    _check_rows(pts, c["eps"], out, off, seed=7)
     out0, _, st0 = _join(sj, x, c["eps"], unicomp=False)
     assert torch.equal(out, out0)
+    del out0
     # the paper's factor ~2: unicomp evaluates (T + n) / 2 candidates
     assert 2 * st["evals"] == st0["evals"] + c["n"]
-    del out, out0, x
+    if c["k_mean"] <= 32:
+        got = out.cpu().numpy()
+        del out
+        _check_rows(pts, c["eps"], got, off, seed=7, nrows=1024)
+        _say(f"uniform n=10M {key}: whole result vs CPU grid join")
+        _whole_vs_grid_join(pts, c["eps"], got, off)
+        del got
+    else:
+        _check_rows(pts, c["eps"], out, off, seed=7, nrows=4096)
+        del out
+    del x
     torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("key", ["d2", "d3"])
 def test_clustered_5M_fp32_band_equals_fp64(sj, key):
-    """5,000,000 clustered points (median 50 neighbours): the FP32 pre-test
-    with FP64 band re-decision gives exactly the FP64 pair set."""
+    """5,000,000 clustered points (median 50 neighbours): the whole FP64
+    result and the whole FP32 pre-test result (FP64 band re-decision) are
+    each compared with the host grid join, pair for pair."""
     c = _calib()["clustered_n5M"][key]
     _say(f"clustered n=5M {key} eps={c['eps']}")
     pts = datagen.clustered(c["n"], c["d"], seed=c["seed"])
     x = torch.from_numpy(pts).cuda()
     out, off, st = _join(sj, x, c["eps"], precision="fp64")
+    got64 = out.cpu().numpy()
+    del out
     out32, off32, st32 = _join(sj, x, c["eps"], precision="fp32_band")
     assert st32["precision_used"] == 1
-    assert torch.equal(out, out32)
     assert st32["band_rechecks"] > 0
-    rows = _check_rows(pts, c["eps"], out, off, seed=11)
+    got32 = out32.cpu().numpy()
+    del out32, x
+    torch.cuda.empty_cache()
+    rows = _check_rows(pts, c["eps"], got64, off, seed=11, nrows=1024)
     counts = np.diff(off)
     assert np.median(counts[rows] - 1) == pytest.approx(c["k_median"], rel=0.35)
-    del out, out32, x
-    torch.cuda.empty_cache()
+    _say(f"clustered n=5M {key}: whole results vs CPU grid join")
+    counts_o, want = ref.grid_join(pts, c["eps"])
+    np.testing.assert_array_equal(counts, counts_o)
+    np.testing.assert_array_equal(np.diff(off32), counts_o)
+    assert np.array_equal(got64, want), "FP64 result differs from the grid join"
+    assert np.array_equal(got32, want), "FP32+band result differs from the grid join"
 
 
 def test_batched_equals_unbatched_at_scale(sj):
@@ -203,5 +238,18 @@ def test_two_set_join_1M_queries_vs_2M_indexed(sj):
         b = np.searchsorted(got[:, 0], rows, side="right")
         seg = np.concatenate([got[x:y] for x, y in zip(a, b)], axis=0)
         np.testing.assert_array_equal(seg, want)
+        if e in (0.04, 0.2):
+            # whole set: the host grid join of S followed by R; its rows of
+            # R's points, restricted to the columns of S, are R x S
+            _say(f"two-set join eps={e}: whole result vs CPU grid join of S + R")
+            ns = S.shape[0]
+            _, both = ref.grid_join(np.concatenate([S, R], axis=0), e)
+            both = both.astype(np.int64)
+            keep = (both[:, 0] >= ns) & (both[:, 1] < ns)
+            want_all = both[keep]
+            del both
+            want_all[:, 0] -= ns
+            assert np.array_equal(got, want_all)
+            del want_all
     del s_dev, r_dev, buf
     torch.cuda.empty_cache()

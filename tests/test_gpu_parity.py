@@ -418,3 +418,27 @@ def test_convenience_host_and_device_output(sj):
             ctypes.memmove(host.ctypes.data, out.value, 8 * P)
         L.sj_free(out)
         assert_same(host.reshape(-1, 2).astype(np.int64), want, f"sj_selfjoin dev={on_dev} cap={cap}")
+
+
+@pytest.mark.parametrize("mode", ["full", "unicomp"])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6])
+def test_both_fill_kernels_in_every_dimension(sj, mode, d, monkeypatch):
+    """The fill pass either evaluates all adjacent cells (each point writes
+    its own row) or the unicomp subset (mirrored pairs placed by atomics);
+    the library picks by the pairs-to-evaluations ratio, SJ_FILL_MODE forces
+    one. Both must give the oracle's pairs in every dimension, and the
+    statistics must say which one ran."""
+    monkeypatch.setenv("SJ_FILL_MODE", mode)
+    n = 9001
+    pts = datagen.clustered(n, d, seed=1300 + d)
+    eps = {1: 0.01, 2: 0.3, 3: 1.2, 4: 3.0, 5: 5.0, 6: 7.0}[d]
+    _say(f"fill mode {mode} d={d}")
+    want = ref.pairs(pts, eps)
+    x = torch.from_numpy(pts).cuda()
+    for prec in ("fp64", "fp32_band"):
+        with sj.Index(x, eps) as ix:
+            ix.count(unicomp=True, precision=prec)
+            got = ix.fill().cpu().numpy().astype(np.int64)
+            st = ix.stats()
+        assert st["fill_unicomp"] == (1 if mode == "unicomp" else 0)
+        assert_same(got, want, f"fill {mode} d={d} {prec}")

@@ -95,3 +95,28 @@ def test_join_rs_self_and_edges(sj):
         big = torch.empty((want.shape[0] + 100, 2), dtype=torch.int32, device="cuda")
         got = ix.join_rs(q, out=big).cpu().numpy().astype(np.int64)
         np.testing.assert_array_equal(got, want)
+
+
+def test_join_rs_count_then_fill(sj):
+    """The two-call form: the count keeps the sorted queries and offsets, the
+    fill writes the pairs from them (host queries are copied by the count);
+    a fill with no count, or into a buffer below P, is refused."""
+    import ctypes
+    from paper_1803_04120_amd import _lib
+    L = _lib.load()
+    _say("two-set join count then fill")
+    S = datagen.clustered(8009, 3, seed=75)
+    R = datagen.uniform(3001, 3, seed=76)
+    want = ref.join_rs_numpy(R, S, 1.5)
+    with sj.Index(torch.from_numpy(S).cuda(), 1.5) as ix:
+        buf = torch.empty((want.shape[0], 2), dtype=torch.int32, device="cuda")
+        assert L.sj_join_rs_fill(ix._h, ctypes.c_void_p(buf.data_ptr()), want.shape[0], None) == _lib.SJ_ESTATE
+        for host in (True, False):
+            q = R if host else torch.from_numpy(R).cuda()
+            ptr = ctypes.c_void_p(q.ctypes.data if host else q.data_ptr())
+            total = ctypes.c_uint64(0)
+            _lib.check(L.sj_join_rs_count(ix._h, ptr, R.shape[0], 0 if host else 1, None, ctypes.byref(total)))
+            assert total.value == want.shape[0]
+            assert L.sj_join_rs_fill(ix._h, ctypes.c_void_p(buf.data_ptr()), total.value - 1, None) == _lib.SJ_ECAPACITY
+            _lib.check(L.sj_join_rs_fill(ix._h, ctypes.c_void_p(buf.data_ptr()), total.value, None))
+            np.testing.assert_array_equal(buf.cpu().numpy().astype(np.int64), want)

@@ -103,3 +103,40 @@ def test_open_loop_stream(sj):
     lat = np.array([c["latency_ms"] for c in done])
     assert np.all(lat > 0) and span > 0
     assert len(sizes) == len(reqs)
+
+
+def test_served_full_size_requests(sj):
+    """Requests at the stream's full size range: up to 2e6 points, clustered
+    4..6-D ones included, all in flight at once on four slots. Each served
+    result must equal the same request run alone and the host-core grid join
+    (pair for pair)."""
+    from paper_1803_04120_amd.serve import Server, uniform_eps_for_k
+    # (n, d, kind, k, eps factor): the clustered requests' eps is scaled down
+    # from the uniform closed form so their results stay at 1e8..6e8 pairs
+    specs = [(2_000_000, 4, "clustered", 40.0, 0.2), (1_200_000, 6, "clustered", 24.0, 0.1),
+             (2_000_000, 5, "uniform", 64.0, 1.0), (800_000, 4, "uniform", 100.0, 1.0),
+             (1_500_000, 3, "clustered", 16.0, 0.4), (300_000, 6, "uniform", 128.0, 1.0)]
+    reqs = []
+    for r, (n, d, kind, k, f) in enumerate(specs):
+        eps = uniform_eps_for_k(n, d, k) * f
+        pts = datagen.make(kind, n, d, seed=900 + r)
+        reqs.append(dict(points=torch.from_numpy(pts).cuda(), host=pts, eps=eps, n=n, d=d,
+                         precision="fp32_band" if r % 2 else "fp64", expected_pairs=int(n * (k + 1))))
+    print(f"[case] serve {len(reqs)} full-size requests", flush=True)
+    with Server(slots=4, mem_budget_bytes=96 << 30) as srv:
+        ids = [srv.submit(q["points"], q["eps"], precision=q["precision"], expected_pairs=q["expected_pairs"])
+               for q in reqs]
+        got = {}
+        while len(got) < len(ids):
+            for c in srv.poll(timeout_ms=200):
+                assert c["status"] == 0, c
+                got[c["req_id"]] = srv.result(c).cpu().numpy()
+                srv.release(c["req_id"])
+    for q, rid in zip(reqs, ids):
+        print(f"[case] full-size request n={q['n']} d={q['d']}: solo and CPU grid join", flush=True)
+        solo = sj.selfjoin(q["points"], q["eps"], precision=q["precision"]).cpu().numpy()
+        assert np.array_equal(got[rid], solo), f"served != solo for n={q['n']} d={q['d']}"
+        _, want = ref.grid_join(q["host"], q["eps"])
+        assert np.array_equal(solo, want), f"solo != grid join for n={q['n']} d={q['d']}"
+        del solo, want
+    torch.cuda.empty_cache()

@@ -113,3 +113,21 @@ def test_no_deadlock_when_every_running_request_waits_for_memory(serve):
         assert srv.info()["over_estimate"] >= 2
         for i in ids:
             srv.release(i)
+
+
+def test_release_before_poll(serve):
+    """A request released as soon as it has completed, before any poll
+    reported it, is never reported afterwards (and polling does not touch
+    the freed record)."""
+    with serve.Server(slots=2, mem_budget_bytes=1 << 40, dry_run=True) as srv:
+        a = srv.submit(np.zeros((2000, 2)), 1.0, expected_pairs=10)
+        b = srv.submit(np.zeros((2000, 2)), 1.0, expected_pairs=10)
+        t0 = time.time()
+        while srv.info()["completed"] < 2 and time.time() - t0 < 30:
+            time.sleep(0.005)
+        assert srv.info()["completed"] == 2
+        srv.release(a)
+        got = _drain(srv, 1)
+        assert list(got) == [b]
+        assert srv.poll(timeout_ms=20) == []
+        srv.release(b)
