@@ -422,6 +422,23 @@ int sj_profile_read(sj_kernel_time *out, uint32_t cap, uint32_t *count);
  * the kernels it reports. The string is copied. */
 int sj_profile_select(const char *prefix);
 
+/*
+ * Device memory held by the library outside the caller's buffers: blocks
+ * that calls have handed back and that are kept for reuse (cached_bytes;
+ * a later call takes the smallest cached block of at least its size and at
+ * most a quarter larger) and blocks in use by indexes, batches and served
+ * results (live_bytes). Either pointer may be NULL.
+ */
+int sj_memory_info(uint64_t *cached_bytes, uint64_t *live_bytes);
+
+/*
+ * Waits for the device to be idle and frees every cached block (a process
+ * that ran large joins and now needs the memory elsewhere). Live blocks
+ * are kept. A failed device allocation does the same by itself before it
+ * retries.
+ */
+int sj_release_cached_memory(void);
+
 /* Thread-local description of the last failure ("" if none). */
 const char *sj_last_error(void);
 

@@ -127,6 +127,8 @@ def load():
         "sj_index_search": (ctypes.c_int, [vp, ctypes.c_int, vp]),
         "sj_band_thresholds": (ctypes.c_int, [u32, dbl, dbl, ctypes.POINTER(ctypes.c_float),
                                               ctypes.POINTER(ctypes.c_float)]),
+        "sj_memory_info": (ctypes.c_int, [ctypes.POINTER(u64), ctypes.POINTER(u64)]),
+        "sj_release_cached_memory": (ctypes.c_int, []),
         "sj_profile_enable": (ctypes.c_int, [ctypes.c_int]),
         "sj_profile_select": (ctypes.c_int, [ctypes.c_char_p]),
         "sj_profile_read": (ctypes.c_int, [ctypes.POINTER(SjKernelTime), u32,
@@ -181,6 +183,18 @@ def last_run_stats() -> dict:
     st = SjStats()
     check(load().sj_last_run_stats(ctypes.byref(st)))
     return stats_dict(st)
+
+
+def memory_info() -> dict:
+    """Device bytes the library holds: cached for reuse and live."""
+    c, l = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    check(load().sj_memory_info(ctypes.byref(c), ctypes.byref(l)))
+    return {"cached_bytes": int(c.value), "live_bytes": int(l.value)}
+
+
+def release_cached_memory():
+    """Free the library's cached device blocks (waits for the device)."""
+    check(load().sj_release_cached_memory())
 
 
 def profile_enable(on: bool = True):

@@ -1547,6 +1547,18 @@ int sj_index_search(sj_index *idx, int unicomp, void *stream) {
     });
 }
 
+int sj_memory_info(uint64_t *cached_bytes, uint64_t *live_bytes) {
+    sj::pool_info(cached_bytes, live_bytes);
+    return SJ_OK;
+}
+
+int sj_release_cached_memory(void) {
+    return guarded(nullptr, [&] {
+        SJ_HIP(hipDeviceSynchronize());
+        sj::pool_trim();
+    });
+}
+
 int sj_profile_enable(int on) {
     if (on) sj::profile_reset();
     sj::profile_set(on != 0);

@@ -52,6 +52,8 @@ struct HostStage {
     T *as() const { return static_cast<T *>(p); }
 };
 void pool_trim();
+// Bytes of device memory held by the pool: cached (free for reuse) and live.
+void pool_info(uint64_t *cached, uint64_t *live);
 void pool_enter();
 void pool_leave_after_sync();
 

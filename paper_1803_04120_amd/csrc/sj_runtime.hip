@@ -104,13 +104,19 @@ void *dev_alloc(size_t bytes) {
     const size_t sz = round_size(bytes);
     Pool &P = pool();
     {
+        // best fit: the smallest cached block of at least sz and at most a
+        // quarter larger, so that requests of nearly equal size (the results
+        // of one workload at slightly different sizes) share blocks instead
+        // of each keeping its own
         std::lock_guard<std::mutex> lk(P.mu);
-        auto it = P.free_blocks.find({dev, sz});
-        if (it != P.free_blocks.end() && !it->second.empty()) {
+        const size_t limit = sz + sz / 4;
+        for (auto it = P.free_blocks.lower_bound({dev, sz});
+             it != P.free_blocks.end() && it->first.first == dev && it->first.second <= limit; ++it) {
+            if (it->second.empty()) continue;
             void *p = it->second.back();
             it->second.pop_back();
-            P.cached_bytes -= sz;
-            P.live[p] = {dev, sz};
+            P.cached_bytes -= it->first.second;
+            P.live[p] = it->first;
             return p;
         }
     }
@@ -138,6 +144,15 @@ void dev_free(void *p) {
         t_pending.push_back(p);
     else
         release_now(p);
+}
+
+void pool_info(uint64_t *cached, uint64_t *live) {
+    Pool &P = pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    uint64_t l = 0;
+    for (const auto &kv : P.live) l += kv.second.second;
+    if (cached) *cached = P.cached_bytes;
+    if (live) *live = l;
 }
 
 void pool_trim() {
