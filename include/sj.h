@@ -186,8 +186,12 @@ int sj_dbscan(const double *pts, uint64_t n, uint32_t d, double eps, uint32_t mi
  * *total_pairs receives P. If pairs_dev is NULL only P is computed;
  * otherwise capacity_pairs must be at least P (else SJ_ECAPACITY, with
  * *total_pairs set and nothing written). Queries outside S's bounding box
- * are allowed (they probe only the cells that exist). Independent of the
- * self-join state of the index (count/fill).
+ * are allowed (they probe only the cells that exist); a query with a NaN or
+ * infinite coordinate has no neighbours. The queries are sorted into S's
+ * grid and joined by the self-join's grid-row tiled kernel (full search);
+ * SJ_JOIN_KERNEL=ranges in the environment selects a one-query-per-thread
+ * kernel instead (same result). Independent of the self-join state of the
+ * index (count/fill).
  */
 int sj_join_rs(sj_index *idx, const double *R, uint64_t nr, int r_on_device, uint32_t *pairs_dev,
                uint64_t capacity_pairs, void *stream, uint64_t *total_pairs);

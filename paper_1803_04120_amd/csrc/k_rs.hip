@@ -170,6 +170,42 @@ __global__ __launch_bounds__(kThreads) void k_rs_max(const uint32_t *__restrict_
     }
 }
 
+// Tiled form: the cell key of every query row in S's grid, the row index as
+// payload, and the number of rows left out (counted per wave, only by waves
+// that have one: adds from every wave to one address would serialise). A
+// query whose
+// cell in some dimension is more than one cell outside the grid, or that has
+// a coordinate that is not finite, has no adjacent cell: it gets the key
+// 2^key_bits, past every cell id, and sorts last. A query one cell outside
+// (cell -1 or dims) takes the edge cell instead: that only widens its
+// candidate window, the distance test decides.
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_rs_query_keys(const double *__restrict__ R, uint64_t nr, GridParams g,
+                                                             int key_bits, K *__restrict__ keys,
+                                                             uint32_t *__restrict__ ids,
+                                                             uint32_t *__restrict__ nleft) {
+    const uint64_t i = blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x;
+    bool valid = true;
+    if (i < nr) {
+        valid = true;
+        uint64_t key = 0;
+        for (uint32_t j = 0; j < g.d; ++j) {
+            const double f = floor((R[i * g.d + j] - g.gmin[j]) / g.w);
+            const double top = static_cast<double>(g.dims[j]);
+            if (!(f >= -1.0) || !(f <= top)) {
+                valid = false;
+                break;
+            }
+            const uint64_t c = f <= 0.0 ? 0 : (f >= top - 1.0 ? g.dims[j] - 1 : static_cast<uint64_t>(f));
+            key += c * g.stride[j];
+        }
+        keys[i] = static_cast<K>(valid ? key : (uint64_t{1} << key_bits));
+        ids[i] = static_cast<uint32_t>(i);
+    }
+    const uint32_t w = wave_sum(valid ? 0u : 1u);
+    if (lane_id() == 0 && w) atomicAdd(nleft, w);
+}
+
 template <int D>
 void launch_rs_d(const RsArgs &a, int mode, hipStream_t s) {
     const unsigned nb = static_cast<unsigned>((a.nr + kThreads - 1) / kThreads);
@@ -198,6 +234,24 @@ void launch_join_rs(const RsArgs &a, int mode, hipStream_t s) {
         case 8: launch_rs_d<8>(a, mode, s); break;
         default: throw Error(SJ_EINVAL, "two-set join: dimension out of range");
     }
+}
+
+void launch_rs_query_keys_u32(const double *R, uint64_t nr, const GridParams &g, int key_bits, uint32_t *keys,
+                              uint32_t *ids, uint32_t *nleft, hipStream_t s) {
+    if (nr == 0) return;
+    KTimer kt_("rs_query_keys", s);
+    k_rs_query_keys<uint32_t><<<static_cast<unsigned>((nr + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+        R, nr, g, key_bits, keys, ids, nleft);
+    SJ_LAUNCH_CHECK();
+}
+
+void launch_rs_query_keys_u64(const double *R, uint64_t nr, const GridParams &g, int key_bits, uint64_t *keys,
+                              uint32_t *ids, uint32_t *nleft, hipStream_t s) {
+    if (nr == 0) return;
+    KTimer kt_("rs_query_keys", s);
+    k_rs_query_keys<uint64_t><<<static_cast<unsigned>((nr + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+        R, nr, g, key_bits, keys, ids, nleft);
+    SJ_LAUNCH_CHECK();
 }
 
 void launch_rs_max(const uint32_t *counts, uint64_t n, uint32_t *out, hipStream_t s) {

@@ -22,6 +22,11 @@
 // and the cells c0 - 1, c0 + 1 only if c0 is odd (block 0).
 //
 // Pair test, counters and emission are those of the per-point kernel.
+//
+// The distance join of a query set R with S (Section II: the self-join is
+// its case R = S) runs the same kernel with the full search: the queries are
+// R's points sorted into S's grid and cut into grid-row chunks of their own,
+// the segments and staged candidates are S's.
 #include <type_traits>
 
 #include "sj_internal.h"
@@ -104,17 +109,17 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         if (active) {
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                xp[j] = a.X[static_cast<size_t>(j) * a.n + p];
+                xp[j] = a.Xq[static_cast<size_t>(j) * a.nqs + p];
                 if (kBand)
-                    yp[j] = static_cast<CT>(a.Y[static_cast<size_t>(j) * a.n + p]);
+                    yp[j] = static_cast<CT>(a.Yq[static_cast<size_t>(j) * a.nqs + p]);
                 else
                     yp[j] = static_cast<CT>(xp[j]);
             }
-            c0p = t.cx[p];
+            c0p = t.cxq[p];
             if (kUni) p_cell_start = a.starts[a.cell_of[p]];
             if (kMode == kFill) {
                 my_row = a.offc[p] - a.out_base;
-                perm_p = a.perm[p];
+                perm_p = a.permq[p];
                 if (NS > 0) row_len = static_cast<uint32_t>(a.offc[p + 1] - a.offc[p]);
             }
         }

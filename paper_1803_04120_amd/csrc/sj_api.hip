@@ -196,18 +196,36 @@ struct sj_index {
     // their order, row offsets by query row and by probe position
     struct RsState {
         bool counted = false;
+        bool tiled = false;  // which kernel the count ran on
         const double *R = nullptr;
         DevBuf<double> staged;
         uint64_t nr = 0, P = 0;
         uint32_t max_len = 0;
-        DevBuf<uint32_t> qperm, cnt, cnt_k, words;
+        DevBuf<uint32_t> qperm, words;
+        // per-query kernel: counts and offsets by query row and by probe position
+        DevBuf<uint32_t> cnt, cnt_k;
         DevBuf<uint64_t> off, off_k;
+        // tiled kernel: the nv queries with adjacent cells, in S's grid and
+        // sorted by cell (qperm's first nv entries): coordinates (d x nv),
+        // dimension-0 cells, their cells and grid-row chunks; row lengths and
+        // offsets by query row (nr) and in cell order (nr, zero past nv)
+        uint32_t nv = 0, nchunks = 0, rows_per_chunk = 0;
+        DevBuf<double> Xq;
+        DevBuf<uint32_t> cxq, cell_of, starts, coords, own_cnt, len_orig, len_cell, nchunks_dev, row_stats;
+        DevBuf<uint64_t> B, off_orig, off_cell, summary;
+        DevBuf<unsigned long long> counters;
+        uint2 *chunks = nullptr;
+        size_t chunks_cap = 0;
+        DevBuf<uint2> segs;
+        uint64_t rows_longer[3] = {0, 0, 0};
+        uint64_t evals = 0;
     } rs;
 
     ~sj_index() {
         for (auto &r : ranges)
             if (r.rng) sj::dev_free(r.rng);
         if (chunks) sj::dev_free(chunks);
+        if (rs.chunks) sj::dev_free(rs.chunks);
     }
 };
 
@@ -420,6 +438,7 @@ sj::TileArgs tile_args(sj_index &ix) {
         t.stride[j] = ix.grid.stride[j];
     }
     t.cx = ix.cx.ptr;
+    t.cxq = ix.cx.ptr;
     t.chunks = ix.chunks;
     t.nchunks = ix.nchunks;
     t.nchunks_dev = ix.nchunks_dev.ptr;
@@ -491,6 +510,10 @@ sj::JoinArgs base_args(sj_index &ix, int mode) {
     a.X = ix.X.ptr;
     a.Y = ix.band_used ? ix.Y.ptr : nullptr;
     a.n = static_cast<uint32_t>(ix.n);
+    a.Xq = a.X;
+    a.Yq = a.Y;
+    a.nqs = a.n;
+    a.permq = ix.perm.ptr;
     a.cell_of = ix.cell_of.ptr;
     a.starts = ix.starts.ptr;
     a.roff = R.roff.ptr;
@@ -1040,29 +1063,12 @@ sj::RsArgs rs_args(sj_index &ix) {
     return a;
 }
 
-// Count pass of R x S: queries in S's cell order (the index's cell key and
-// radix sort), so that a wave's queries share candidate cells; row offsets
-// by query row (output) and by probe position (fill layout); P and the
-// longest row. State kept in ix.rs for rs_fill.
-void rs_count(sj_index &ix, const double *R, uint64_t nr, int r_on_device, hipStream_t s) {
+// Count pass of R x S on the per-query kernel (SJ_JOIN_KERNEL=ranges):
+// queries in S's cell order (the index's cell key and radix sort), so that a
+// wave's queries share candidate cells; row offsets by query row (output)
+// and by probe position (fill layout); P and the longest row.
+void rs_count_perquery(sj_index &ix, const double *rp, uint64_t nr, hipStream_t s) {
     auto &st = ix.rs;
-    st.counted = false;
-    st.P = 0;
-    st.nr = nr;
-    if (nr && !R) throw Error(SJ_EINVAL, "R is NULL");
-    if (nr >= 0x7fffffffULL) throw Error(SJ_EINVAL, "too many query rows");
-    if (nr == 0 || ix.n == 0) {
-        st.counted = true;
-        return;
-    }
-    const uint32_t d = ix.d;
-    const double *rp = R;
-    if (!r_on_device) {
-        st.staged.ensure(nr * d);
-        SJ_HIP(hipMemcpyAsync(st.staged.ptr, R, nr * d * sizeof(double), hipMemcpyHostToDevice, s));
-        rp = st.staged.ptr;
-    }
-    st.R = rp;
     st.qperm.ensure(nr);
     {
         DevBuf<uint32_t> qperm_alt(nr);
@@ -1096,19 +1102,14 @@ void rs_count(sj_index &ix, const double *R, uint64_t nr, int r_on_device, hipSt
     SJ_HIP(hipStreamSynchronize(s));
     st.P = *hs.as<uint64_t>();
     st.max_len = hs.as<uint32_t>()[2];
-    st.counted = true;
 }
 
-// Fill pass: neighbour ids per query in probe order, unsorted, then each row
-// sorted and written as (i, j) pairs at its offset in R's order.
-void rs_fill(sj_index &ix, uint32_t *pairs_dev, uint64_t cap, hipStream_t s) {
+// Fill pass of the per-query kernel: neighbour ids per query in probe
+// order, unsorted, then each row sorted and written as (i, j) pairs at its
+// offset in R's order.
+void rs_fill_perquery(sj_index &ix, uint32_t *pairs_dev, hipStream_t s) {
     auto &st = ix.rs;
     const uint64_t P = st.P;
-    if (P == 0) return;
-    if (!pairs_dev) throw Error(SJ_EINVAL, "pairs_dev is NULL");
-    if (cap < P)
-        throw Error(SJ_ECAPACITY, "output buffer holds " + std::to_string(cap) + " pairs, the result has " +
-                                      std::to_string(P));
     sj::RsArgs a = rs_args(ix);
     DevBuf<uint32_t> out_j(P);
     a.off = st.off_k.ptr;
@@ -1121,6 +1122,221 @@ void rs_fill(sj_index &ix, uint32_t *pairs_dev, uint64_t cap, hipStream_t s) {
     SJ_HIP(hipMemcpyAsync(hs.p, st.words.ptr + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
     if (*hs.as<uint32_t>()) throw Error(SJ_EDEVICE, "internal: the two-set fill disagreed with its count");
+}
+
+// Tile arguments of the two-set join: S's cells, masks and candidate cells,
+// the queries' chunks, segments and dimension-0 cells.
+sj::TileArgs rs_tile_args(sj_index &ix) {
+    auto &st = ix.rs;
+    sj::TileArgs t = tile_args(ix);
+    t.coords = st.coords.ptr;  // chunk geometry (the segments' search)
+    t.cxq = st.cxq.ptr;
+    t.chunks = st.chunks;
+    t.nchunks = st.nchunks;
+    t.nchunks_dev = st.nchunks_dev.ptr;
+    t.rows_per_chunk = st.rows_per_chunk;
+    t.segs = st.segs.ptr;
+    return t;
+}
+
+sj::JoinArgs rs_join_args(sj_index &ix) {
+    auto &st = ix.rs;
+    sj::JoinArgs a = base_args(ix, 0);
+    a.Y = nullptr;  // FP64 only
+    a.Xq = st.Xq.ptr;
+    a.Yq = nullptr;
+    a.nqs = static_cast<uint32_t>(st.nr);  // the SoA's stride (all rows gathered; the first nv are joined)
+    a.permq = st.qperm.ptr;
+    a.cell_of = st.cell_of.ptr;
+    a.own_cnt = st.own_cnt.ptr;
+    a.in_cnt = nullptr;
+    a.evals = st.counters.ptr;
+    a.band_rechecks = st.counters.ptr + sj::kCounterSlots * sj::kCounterStride;
+    return a;
+}
+
+// Count pass of R x S on the grid-row tiled kernel. R's rows take their
+// cells in S's grid and are sorted by cell (rows with no adjacent cell
+// last, left out); the sorted queries get their own cells, grid-row chunks
+// of at most 64 and, per chunk, the 3^(d-1) candidate segments of S's cell
+// order. The full search then counts each query's neighbours; row lengths
+// and offsets follow as in the self-join.
+void rs_count_tiled(sj_index &ix, const double *rp, uint64_t nr, hipStream_t s) {
+    auto &st = ix.rs;
+    const uint32_t d = ix.d;
+    const int bits = ix.key_bits + 1;  // one more: the key of the rows left out
+    st.qperm.ensure(nr);
+    st.words.ensure(2);  // [0] rows left out, [1] the fill's overflow flag
+    sj::launch_fill_u32(st.words.ptr, 2, 0u, s);
+    DevBuf<uint32_t> qalt(nr);
+    DevBuf<uint64_t> k64(nr), k64_alt(nr);
+    const bool k32 = bits <= 32;
+    if (k32) {
+        uint32_t *k = reinterpret_cast<uint32_t *>(k64.ptr), *k2 = reinterpret_cast<uint32_t *>(k64_alt.ptr);
+        sj::launch_rs_query_keys_u32(rp, nr, ix.grid, ix.key_bits, k, st.qperm.ptr, st.words.ptr, s);
+        if (sj::radix_sort_u32(k, st.qperm.ptr, k2, qalt.ptr, nr, bits, s)) {
+            std::swap(k64, k64_alt);
+            std::swap(st.qperm, qalt);
+        }
+    } else {
+        sj::launch_rs_query_keys_u64(rp, nr, ix.grid, ix.key_bits, k64.ptr, st.qperm.ptr, st.words.ptr, s);
+        if (sj::radix_sort_u64(k64.ptr, st.qperm.ptr, k64_alt.ptr, qalt.ptr, nr, bits, s)) {
+            std::swap(k64, k64_alt);
+            std::swap(st.qperm, qalt);
+        }
+    }
+    // cells of all rows (those left out form the last cell, if any), their
+    // coordinates and the cell-ordered SoA, before the one readback of the
+    // counts they depend on
+    st.cell_of.ensure(nr);
+    st.B.ensure(nr);
+    st.starts.ensure(nr + 1);
+    st.coords.ensure(nr * d);
+    st.Xq.ensure(nr * d);
+    st.cxq.ensure(nr);
+    if (k32)
+        sj::build_cells<uint32_t>(reinterpret_cast<uint32_t *>(k64.ptr), nr, st.cell_of.ptr, st.B.ptr,
+                                  st.starts.ptr, s);
+    else
+        sj::build_cells<uint64_t>(k64.ptr, nr, st.cell_of.ptr, st.B.ptr, st.starts.ptr, s);
+    DevBuf<uint32_t> max_pts(1);
+    sj::launch_cell_coords_masks(st.B.ptr, st.starts.ptr, nr, st.cell_of.ptr + (nr - 1), ix.grid, st.coords.ptr,
+                                 nullptr, sj::MaskOffsets{}, 0, max_pts.ptr, s);
+    sj::launch_gather_soa(rp, st.qperm.ptr, nr, d, st.Xq.ptr, ix.grid, st.cxq.ptr, s);
+    st.len_orig.ensure(nr);
+    st.len_cell.ensure(nr);
+    st.off_orig.ensure(nr + 1);
+    st.off_cell.ensure(nr + 1);
+    const size_t nctr = 2 * sj::kCounterSlots * sj::kCounterStride;
+    st.counters.ensure(nctr);
+    st.row_stats.ensure(sj::kRowStatWords);
+    st.nchunks_dev.ensure(1);
+    st.summary.ensure(8);
+    sj::ZeroSpans z{};
+    z.add(st.len_orig.ptr, nr);
+    z.add(st.len_cell.ptr, nr);
+    z.add(st.counters.ptr, 2 * nctr);
+    sj::launch_zero_spans(z, s);
+    sj::HostStage hs;
+    SJ_HIP(hipMemcpyAsync(hs.p, st.words.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(hs.as<uint32_t>() + 1, st.cell_of.ptr + (nr - 1), sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    const uint32_t nleft = hs.as<uint32_t>()[0];
+    const uint32_t nv = static_cast<uint32_t>(nr) - nleft;
+    const uint32_t ncq = hs.as<uint32_t>()[1] + 1 - (nleft ? 1u : 0u);
+    st.nv = nv;
+    if (nv > 0) {
+        // grid-row chunks of the queries and their candidate segments in S
+        uint64_t rows_bound = 1;
+        for (uint32_t j = 1; j < d; ++j)
+            rows_bound = ix.grid.dims[j] > (UINT64_MAX / 2) / rows_bound ? UINT64_MAX / 2 : rows_bound * ix.grid.dims[j];
+        st.nchunks = sj::build_chunks(st.coords.ptr, st.starts.ptr, ncq, nv, d, rows_bound, &st.chunks,
+                                      &st.chunks_cap, st.nchunks_dev.ptr, s);
+        uint32_t r3 = 1;
+        for (uint32_t j = 1; j < d; ++j) r3 *= 3;
+        st.rows_per_chunk = r3;
+        st.segs.reset(static_cast<size_t>(st.nchunks) * r3);
+        sj::build_chunk_segments(rs_tile_args(ix), st.cell_of.ptr, ix.starts.ptr, d, st.segs.ptr, s);
+        // count
+        st.own_cnt.ensure(nv);
+        sj::launch_join_tiled(rs_join_args(ix), rs_tile_args(ix), d, 0, sj::kCount, 0, s);
+        sj::launch_row_lengths(st.own_cnt.ptr, nullptr, st.qperm.ptr, nv, st.len_orig.ptr, st.len_cell.ptr,
+                               st.row_stats.ptr, s);
+    } else {
+        st.nchunks = 0;
+        sj::launch_fill_u32(st.nchunks_dev.ptr, 1, 0u, s);
+        sj::launch_fill_u32(st.row_stats.ptr, sj::kRowStatWords, 0u, s);
+    }
+    sj::scan_exclusive_u32_to_u64_x2(st.len_orig.ptr, st.off_orig.ptr, st.len_cell.ptr, st.off_cell.ptr, nr, s);
+    sj::launch_count_summary(st.off_orig.ptr, nr, st.row_stats.ptr, st.counters.ptr, st.nchunks_dev.ptr,
+                             st.summary.ptr, st.words.ptr + 1, s);
+    SJ_HIP(hipMemcpyAsync(hs.p, st.summary.ptr, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    const uint64_t *sm = hs.as<uint64_t>();
+    st.P = sm[0];
+    st.max_len = static_cast<uint32_t>(sm[1]);
+    st.evals = sm[2];
+    for (int k = 0; k < 3; ++k) st.rows_longer[k] = sm[5 + k];
+}
+
+// Fill pass of the tiled kernel: in 1..3-D with the row sort fused (rows
+// that fit the LDS slot are sorted there and written as (i, j) pairs at
+// their offset in R's order, longer ones go through out_j to the row-sort
+// kernels), from 4-D on into out_j in cell order, then every row sorted.
+void rs_fill_tiled(sj_index &ix, uint32_t *pairs_dev, hipStream_t s) {
+    auto &st = ix.rs;
+    const uint64_t P = st.P;
+    DevBuf<uint32_t> out_j(P);
+    sj::JoinArgs a = rs_join_args(ix);
+    a.out_j = out_j.ptr;
+    a.out_base = 0;
+    a.out_cap = P;
+    a.overflow = st.words.ptr + 1;  // cleared by the count summary
+    a.offc = st.off_cell.ptr;
+    const bool fused = use_fused_sort(ix.d);
+    uint32_t ns = 0;
+    if (fused) {
+        // the smallest LDS slot that at most 5% of the rows exceed
+        const double lim = 0.05 * static_cast<double>(st.nv);
+        ns = static_cast<double>(st.rows_longer[0]) <= lim ? 16u
+             : (static_cast<double>(st.rows_longer[1]) <= lim ? 24u : 32u);
+        a.off_orig = st.off_orig.ptr;
+        a.pairs = reinterpret_cast<uint2 *>(pairs_dev);
+    }
+    sj::launch_join_tiled(a, rs_tile_args(ix), ix.d, 0, sj::kFill, 0, s, ns);
+    if (fused)
+        sj::launch_rowsort_long(st.off_cell.ptr, st.off_orig.ptr, st.qperm.ptr, st.nv, out_j.ptr, pairs_dev,
+                                st.max_len, 64, s);
+    else
+        sj::launch_rowsort_cells(st.off_cell.ptr, st.off_orig.ptr, st.qperm.ptr, st.nv, out_j.ptr, pairs_dev,
+                                 st.max_len, s);
+    sj::HostStage hs;
+    SJ_HIP(hipMemcpyAsync(hs.p, st.words.ptr + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    if (*hs.as<uint32_t>()) throw Error(SJ_EDEVICE, "internal: the two-set fill disagreed with its count");
+}
+
+// Count pass of R x S; the state is kept in ix.rs for rs_fill.
+void rs_count(sj_index &ix, const double *R, uint64_t nr, int r_on_device, hipStream_t s) {
+    auto &st = ix.rs;
+    st.counted = false;
+    st.P = 0;
+    st.nr = nr;
+    st.nv = 0;
+    st.evals = 0;
+    if (nr && !R) throw Error(SJ_EINVAL, "R is NULL");
+    if (nr >= 0x7fffffffULL) throw Error(SJ_EINVAL, "too many query rows");
+    if (nr == 0 || ix.n == 0) {
+        st.counted = true;
+        return;
+    }
+    const double *rp = R;
+    if (!r_on_device) {
+        st.staged.ensure(nr * ix.d);
+        SJ_HIP(hipMemcpyAsync(st.staged.ptr, R, nr * ix.d * sizeof(double), hipMemcpyHostToDevice, s));
+        rp = st.staged.ptr;
+    }
+    st.R = rp;
+    st.tiled = use_tiled();
+    if (st.tiled)
+        rs_count_tiled(ix, rp, nr, s);
+    else
+        rs_count_perquery(ix, rp, nr, s);
+    st.counted = true;
+}
+
+void rs_fill(sj_index &ix, uint32_t *pairs_dev, uint64_t cap, hipStream_t s) {
+    auto &st = ix.rs;
+    if (st.P == 0) return;
+    if (!pairs_dev) throw Error(SJ_EINVAL, "pairs_dev is NULL");
+    if (cap < st.P)
+        throw Error(SJ_ECAPACITY, "output buffer holds " + std::to_string(cap) + " pairs, the result has " +
+                                      std::to_string(st.P));
+    if (st.tiled)
+        rs_fill_tiled(ix, pairs_dev, s);
+    else
+        rs_fill_perquery(ix, pairs_dev, s);
 }
 
 }  // namespace

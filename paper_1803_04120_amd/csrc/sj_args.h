@@ -36,9 +36,16 @@ struct SearchArgs {
 };
 
 struct JoinArgs {
-    const double *X;          // d x n, cell order
+    const double *X;          // d x n, cell order (the candidates)
     const float *Y;           // d x n, cell order, shifted (band path) or null
     uint32_t n;
+    // query points of the tiled kernel, d x nqs in cell order (for the
+    // self-join the candidates themselves; for R x S the queries of R in
+    // S's grid): coordinates, their FP32 copy, and each one's row id
+    const double *Xq;
+    const float *Yq;
+    uint32_t nqs;
+    const uint32_t *permq;
     const uint32_t *cell_of;
     const uint32_t *starts;
     const uint64_t *roff;
@@ -82,6 +89,7 @@ struct TileArgs {
     uint64_t dims[kMaxDim];
     uint64_t stride[kMaxDim];
     const uint32_t *cx;       // dimension-0 cell coordinate of each cell-ordered point
+    const uint32_t *cxq;      // the same for the query points (cx for the self-join)
     const uint2 *chunks;      // [first, end) point range of each chunk
     uint32_t nchunks;         // upper bound on the chunk count (launch size)
     const uint32_t *nchunks_dev;  // the chunk count (device)

@@ -252,6 +252,13 @@ void launch_batch_bounds(const uint64_t *off, uint64_t n, uint64_t total, uint32
 // Two-set join (k_rs.hip): mode 0 counts each query row's neighbours into
 // a.count, mode 1 writes them (S rows, unsorted) into a.out_j at a.off.
 void launch_join_rs(const RsArgs &a, int mode, hipStream_t s);
+// Tiled two-set join: keys[i] = cell id of query row i in g (clamped by one
+// cell at the grid's edge), 2^key_bits for a row with no adjacent cell;
+// ids[i] = i; *nleft (0 on entry) += rows of the second kind.
+void launch_rs_query_keys_u32(const double *R, uint64_t nr, const GridParams &g, int key_bits, uint32_t *keys,
+                              uint32_t *ids, uint32_t *nleft, hipStream_t s);
+void launch_rs_query_keys_u64(const double *R, uint64_t nr, const GridParams &g, int key_bits, uint64_t *keys,
+                              uint32_t *ids, uint32_t *nleft, hipStream_t s);
 // *out (0 on entry) = max of counts[0..n).
 void launch_rs_max(const uint32_t *counts, uint64_t n, uint32_t *out, hipStream_t s);
 

@@ -120,3 +120,46 @@ def test_join_rs_count_then_fill(sj):
             assert L.sj_join_rs_fill(ix._h, ctypes.c_void_p(buf.data_ptr()), total.value - 1, None) == _lib.SJ_ECAPACITY
             _lib.check(L.sj_join_rs_fill(ix._h, ctypes.c_void_p(buf.data_ptr()), total.value, None))
             np.testing.assert_array_equal(buf.cpu().numpy().astype(np.int64), want)
+
+
+@pytest.mark.parametrize("kind,d,ns,nr,eps", [("uniform", 1, 4001, 3001, 0.05), ("uniform", 2, 20011, 6007, 4.0),
+                                              ("clustered", 2, 12007, 5003, 2.0), ("clustered", 3, 9001, 4001, 3.0),
+                                              ("uniform", 4, 6007, 3001, 14.0), ("uniform", 5, 5003, 2003, 20.0),
+                                              ("uniform", 7, 3001, 1009, 40.0), ("uniform", 8, 2003, 1009, 45.0)])
+def test_tiled_and_per_query_kernels_agree(sj, kind, d, ns, nr, eps, monkeypatch):
+    """The grid-row tiled kernel (default) and the per-query kernel
+    (SJ_JOIN_KERNEL=ranges) give the oracle's pairs, with rows from a few
+    entries to hundreds (the fused row sort's LDS slot, the wave and block
+    row sorts in 1..3-D), 1..8-D, a third of the queries outside S's box."""
+    _say(f"tiled vs per-query {kind} d={d} ns={ns} nr={nr} eps={eps}")
+    S = datagen.make(kind, ns, d, seed=800 + d)
+    R = datagen.make(kind, nr, d, seed=800 + d if kind == "clustered" else 900 + d)
+    R[: nr // 3] = R[: nr // 3] * 1.2 - 10.0  # some beyond the box, some far out
+    want = ref.join_rs_numpy(R, S, eps)
+    assert want.shape[0] > nr
+    got_tiled = rs_pairs(sj, S, R, eps)
+    monkeypatch.setenv("SJ_JOIN_KERNEL", "ranges")
+    got_pq = rs_pairs(sj, S, R, eps)
+    monkeypatch.delenv("SJ_JOIN_KERNEL")
+    assert_same(got_tiled, want, f"tiled R x S {kind} d={d}")
+    assert_same(got_pq, want, f"per-query R x S {kind} d={d}")
+
+
+def test_join_rs_nonfinite_and_far_queries(sj):
+    """Queries with a NaN or infinite coordinate, or more than a cell outside
+    S's grid in one dimension, have no neighbours; the rest of the rows are
+    unaffected. All queries far away: an empty result."""
+    _say("non-finite and far queries")
+    S = datagen.uniform(7001, 3, seed=77)
+    R = datagen.uniform(2003, 3, seed=78)
+    R[5, 1] = np.nan
+    R[17, 0] = np.inf
+    R[29, 2] = -np.inf
+    R[31] = [np.nan, np.nan, np.nan]
+    R[40, 2] = 1e12
+    want = ref.join_rs_numpy(R, S, 2.5)
+    got = rs_pairs(sj, S, R, 2.5)
+    assert_same(got, want, "non-finite queries")
+    assert not np.isin(got[:, 0], [5, 17, 29, 31, 40]).any()
+    far = np.full((100, 3), 1e6)
+    assert rs_pairs(sj, S, far, 2.5).shape[0] == 0
