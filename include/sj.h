@@ -342,10 +342,13 @@ int sj_band_thresholds(uint32_t d, double eps, double extent, float *lo, float *
 /*
  * A server runs self-join requests as they arrive. `slots` worker threads,
  * each with its own HIP stream, take queued requests in arrival order when
- * the request's estimated device memory (index bytes + expected_pairs * 12)
- * fits in what `mem_budget_bytes` has left; the first request is admitted
- * whenever nothing else holds memory. After the count pass the exact result
- * size replaces the estimate (waiting for memory if it grew). Requests on
+ * the request's estimated device memory fits in what `mem_budget_bytes` has
+ * left: the index bytes plus 12 bytes for each of expected_pairs and a
+ * quarter more (a caller's expected mean is exceeded by about half the
+ * requests), or the index bytes alone when expected_pairs is 0. The first
+ * request is admitted whenever nothing else holds memory. After the count
+ * pass the exact result size replaces the estimate (waiting for memory if
+ * it grew). Requests on
  * different slots overlap on the device. Results stay in device memory,
  * counted against the budget, until sj_server_release.
  *
@@ -360,7 +363,8 @@ typedef struct sj_server sj_server;
 
 #define SJ_SERVER_DRY_RUN 1  /* flags: no device work (scheduler tests without a GPU):
                                  a request takes n/1e6 ms twice and its count pass
-                                 reports expected_pairs pairs (twice that for even ids) */
+                                 reports expected_pairs pairs (twice that for even ids;
+                                 n when expected_pairs is 0) */
 
 typedef struct sj_server_opts {
     uint32_t slots;             /* concurrent requests (worker threads/streams), 1..64 */
@@ -386,14 +390,16 @@ typedef struct sj_server_info_t {
     uint64_t running;
     uint64_t mem_used_bytes;
     uint64_t peak_mem_bytes;
-    uint64_t over_estimate;      /* requests whose result outgrew the estimate */
+    uint64_t over_estimate;      /* requests with expected_pairs > 0 whose result
+                                    outgrew the reservation */
     uint64_t completed;
 } sj_server_info_t;
 
 int  sj_server_create(const sj_server_opts *opts, sj_server **out);
 /* Queues a self-join request (the join of Section III with the method of
  * Sections IV-V; opts as for sj_join_count); *req_id identifies it. opts may
- * be NULL (defaults); expected_pairs 0 means "about n". Never blocks on
+ * be NULL (defaults); expected_pairs 0 means no estimate (the result's
+ * memory is reserved after the count pass). Never blocks on
  * device work; see above for the ordering of device points. */
 int  sj_server_submit(sj_server *srv, const double *pts, uint64_t n, uint32_t d, double eps,
                       int pts_on_device, const sj_join_opts *opts, uint64_t expected_pairs,

@@ -6,7 +6,8 @@
 // estimated device memory fits in what the budget has left (the first
 // request is always admitted when nothing else holds memory, so a request
 // larger than the budget still runs, alone). The estimate is the index
-// bytes plus the caller's expected result size; after the count pass the
+// bytes plus the caller's expected result size and a quarter (nothing for
+// the result without an expectation); after the count pass the
 // exact result size is known, and a request whose result needs more than
 // its estimate waits (holding its index) until the extra memory is free or
 // nothing else holds memory. Requests on different slots run concurrently
@@ -44,7 +45,8 @@ struct Request {
     double eps = 0;
     sj_join_opts opts{};
     uint64_t est_bytes = 0;
-    uint64_t est_pairs = 0;
+    uint64_t hint_pairs = 0;  // the caller's expected result size (0: none)
+    uint64_t est_pairs = 0;   // pairs reserved at admission
     uint64_t held_bytes = 0;
     Clock::time_point t_submit, t_start, t_done;
     int status = SJ_OK;
@@ -90,19 +92,20 @@ uint64_t index_bytes(uint64_t n, uint32_t d) {
 uint64_t result_bytes(uint64_t pairs) { return pairs * 12ull; }  // pairs + neighbour-id scratch
 
 // Dry-run backend (SJ_SERVER_DRY_RUN): no device work. A request "runs" for
-// n / 1e6 milliseconds and its count pass "finds" expected_pairs pairs, or
-// twice that for even request ids, so that the scheduler, the admission
-// steps and the accounting can be exercised without a GPU.
+// n / 1e6 milliseconds and its count pass "finds" expected_pairs pairs (n
+// without an expectation), or twice that for even request ids, so that the
+// scheduler, the admission steps and the accounting can be exercised
+// without a GPU.
 void run_request_dry(sj_server *S, Request *r, uint32_t slot) {
     std::this_thread::sleep_for(std::chrono::microseconds(r->n / 1000 + 50));
-    const uint64_t expected = r->est_pairs;
+    const uint64_t expected = r->hint_pairs ? r->hint_pairs : r->n;
     const uint64_t P = (r->id % 2 == 0) ? 2 * expected : expected;
     {
         const uint64_t need = index_bytes(r->n, r->d) + result_bytes(P);
         std::unique_lock<std::mutex> lk(S->mu);
         if (need > r->held_bytes) {
             const uint64_t extra = need - r->held_bytes;
-            ++S->over_estimate;
+            if (r->hint_pairs) ++S->over_estimate;
             // Waits until the extra memory fits, or until no other request
             // can free memory (it is the only holder, or every running
             // request is itself waiting here): the budget is soft, progress
@@ -149,7 +152,7 @@ void run_request(sj_server *S, Request *r, uint32_t slot, hipStream_t stream) {
         std::unique_lock<std::mutex> lk(S->mu);
         if (need > r->held_bytes) {
             const uint64_t extra = need - r->held_bytes;
-            ++S->over_estimate;
+            if (r->hint_pairs) ++S->over_estimate;
             // Waits until the extra memory fits, or until no other request
             // can free memory (it is the only holder, or every running
             // request is itself waiting here): the budget is soft, progress
@@ -266,7 +269,8 @@ int sj_server_submit(sj_server *S, const double *pts, uint64_t n, uint32_t d, do
     sj_default_opts(&r->opts);
     if (opts) r->opts = *opts;
     if (r->opts.min_batches == 0) r->opts.min_batches = 1;
-    r->est_pairs = expected_pairs ? expected_pairs : n;
+    r->hint_pairs = expected_pairs;
+    r->est_pairs = expected_pairs + expected_pairs / 4;
     r->est_bytes = index_bytes(n, d) + result_bytes(r->est_pairs);
     r->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(S->mu);
