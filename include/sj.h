@@ -306,11 +306,14 @@ int sj_bruteforce(const double *pts, uint64_t n, uint32_t d, double eps, int pts
  * `bytes` must equal the array's size, which sj_index_export_size reports.
  *   SJ_EXPORT_CELL_IDS    uint64[|G|]   B: linear ids of non-empty cells, ascending
  *   SJ_EXPORT_CELL_START  uint32[|G|+1] G: cell h holds A[start[h] .. start[h+1]-1]
- *   SJ_EXPORT_PERM        uint32[n]     A: point ids in cell order
+ *   SJ_EXPORT_PERM        uint32[n]     A: point ids in cell order (inside a cell by the
+ *                                       dimension-0 sub-cell floor(t * s), t = (x_0 - g_0^min) / w,
+ *                                       s from SJ_EXPORT_GRID, then by id)
  *   SJ_EXPORT_MASKS       uint32[sum_j ceil(|g_j|/32)]  M_j occupancy bitmaps, dimension 0 first
  *   SJ_EXPORT_RANGE_OFF   uint32[|G|+1] candidate ranges of cell h are rng[off[h] .. off[h+1]-1]
  *   SJ_EXPORT_RANGES      uint32[2*R]   (start, end) point ranges in cell order
- *   SJ_EXPORT_GRID        double[2*8+1] g_min[8], |g_j| as doubles [8], w
+ *   SJ_EXPORT_GRID        double[2*8+2] g_min[8], |g_j| as doubles [8], w, s (dimension-0
+ *                                       sub-cells per cell, a power of two <= 8)
  *   SJ_EXPORT_ROW_OFFSETS uint64[n+1]   result row i holds pairs [off[i], off[i+1]) (after sj_join_count)
  * The two range arrays describe the last join (or the last sj_index_search).
  */

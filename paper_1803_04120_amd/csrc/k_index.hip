@@ -3,7 +3,9 @@
 //   bbox        min/max per dimension and a NaN/Inf flag (g_j^min, g_j^max)
 //   cell ids    c_j = clamp(floor((x_j - g_j^min) / w), 0, |g_j| - 1),
 //               id = c_0 + |g_0| (c_1 + |g_1| (c_2 + ...))  (dimension 0 fastest,
-//               as in the worked example of Section IV-D)
+//               as in the worked example of Section IV-D); the sort key
+//               appends the dimension-0 sub-cell (width w / 2^sub_shift), so
+//               that inside a cell the points are ordered by it
 //   cells       after the sort by id: head flags, inclusive scan -> cell of
 //               each point, B (distinct ids) and G (first point of each cell)
 //   coords/M    per-cell coordinates and the per-dimension occupancy
@@ -151,6 +153,19 @@ __device__ __forceinline__ uint32_t cell_coord(double v, const GridParams &g, in
     return static_cast<uint32_t>(f <= 0.0 ? 0 : (f >= top ? g.dims[j] - 1 : static_cast<uint64_t>(f)));
 }
 
+// Dimension-0 coordinate in sub-cells of width w / 2^sub_shift, clamped to
+// the grid like cell_coord. t * 2^sub_shift is exact, so the sub-cell
+// shifted right by sub_shift is cell_coord(v, g, 0) (NaN gives 0).
+__device__ __forceinline__ uint32_t sub_coord0(double v, const GridParams &g) {
+    const double t = (v - g.gmin[0]) / g.w;
+    const double f = floor(t * static_cast<double>(1u << g.sub_shift));
+    const uint64_t top = (g.dims[0] << g.sub_shift) - 1;
+    return static_cast<uint32_t>(!(f > 0.0) ? 0 : (f >= static_cast<double>(top) ? top : static_cast<uint64_t>(f)));
+}
+
+// Sort key of every point: its cell id, shifted left by sub_shift with the
+// point's dimension-0 sub-cell inside the cell appended (sub_shift 0: the
+// cell id).
 template <typename K>
 __global__ __launch_bounds__(kThreads) void k_cell_keys(const double *__restrict__ pts, uint64_t n,
                                                          GridParams g, K *__restrict__ keys,
@@ -160,12 +175,14 @@ __global__ __launch_bounds__(kThreads) void k_cell_keys(const double *__restrict
     uint64_t key = 0;
     for (uint32_t j = 0; j < g.d; ++j)
         key += static_cast<uint64_t>(cell_coord(pts[i * g.d + j], g, static_cast<int>(j))) * g.stride[j];
+    if (g.sub_shift)
+        key = (key << g.sub_shift) | (sub_coord0(pts[i * g.d], g) & ((1u << g.sub_shift) - 1u));
     keys[i] = static_cast<K>(key);
     ids[i] = static_cast<uint32_t>(i);
 }
 
 template <typename K>
-__global__ __launch_bounds__(kThreads) void k_cell_tables(const K *__restrict__ k, uint64_t n,
+__global__ __launch_bounds__(kThreads) void k_cell_tables(const K *__restrict__ k, uint64_t n, int shift,
                                                            uint32_t *__restrict__ cell_of,
                                                            uint64_t *__restrict__ B,
                                                            uint32_t *__restrict__ starts) {
@@ -173,8 +190,8 @@ __global__ __launch_bounds__(kThreads) void k_cell_tables(const K *__restrict__ 
     if (r >= n) return;
     const uint32_t h = cell_of[r] - 1u;  // inclusive scan of head flags
     cell_of[r] = h;
-    if (r == 0 || k[r] != k[r - 1]) {
-        B[h] = static_cast<uint64_t>(k[r]);
+    if (r == 0 || (k[r] >> shift) != (k[r - 1] >> shift)) {
+        B[h] = static_cast<uint64_t>(k[r] >> shift);
         starts[h] = static_cast<uint32_t>(r);
     }
     if (r == n - 1) starts[h + 1] = static_cast<uint32_t>(n);
@@ -278,7 +295,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_soa(const double *__restric
     if (r >= n) return;
     const uint64_t i = perm[r];
     for (uint32_t j = 0; j < d; ++j) X[j * n + r] = pts[i * d + j];
-    cx[r] = cell_coord(pts[i * d], g, 0);
+    cx[r] = sub_coord0(pts[i * d], g);
 }
 
 // Even d with 16-byte aligned rows: one 16-byte load per coordinate pair.
@@ -298,7 +315,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_soa_v2(const double2 *__res
         X[(2 * k) * n + r] = v[k].x;
         X[(2 * k + 1) * n + r] = v[k].y;
     }
-    cx[r] = cell_coord(v[0].x, g, 0);
+    cx[r] = sub_coord0(v[0].x, g);
 }
 
 __global__ __launch_bounds__(kThreads) void k_make_f32(const double *__restrict__ X, uint64_t n,
@@ -408,19 +425,19 @@ void launch_cell_keys_u32(const double *pts, uint64_t n, const GridParams &g, ui
 }
 
 template <typename K>
-void build_cells(const K *sorted_keys, uint64_t n, uint32_t *cell_of, uint64_t *B, uint32_t *starts,
+void build_cells(const K *sorted_keys, uint64_t n, int shift, uint32_t *cell_of, uint64_t *B, uint32_t *starts,
                  hipStream_t s) {
-    scan_head_flags_inclusive<K>(sorted_keys, cell_of, n, s);
+    scan_head_flags_inclusive<K>(sorted_keys, shift, cell_of, n, s);
     {
         KTimer kt_("cell_tables", s);
-        k_cell_tables<K><<<blocks_for(n), kThreads, 0, s>>>(sorted_keys, n, cell_of, B, starts);
+        k_cell_tables<K><<<blocks_for(n), kThreads, 0, s>>>(sorted_keys, n, shift, cell_of, B, starts);
         SJ_LAUNCH_CHECK();
     }
 }
 
-template void build_cells<uint64_t>(const uint64_t *, uint64_t, uint32_t *, uint64_t *, uint32_t *,
+template void build_cells<uint64_t>(const uint64_t *, uint64_t, int, uint32_t *, uint64_t *, uint32_t *,
                                     hipStream_t);
-template void build_cells<uint32_t>(const uint32_t *, uint64_t, uint32_t *, uint64_t *, uint32_t *,
+template void build_cells<uint32_t>(const uint32_t *, uint64_t, int, uint32_t *, uint64_t *, uint32_t *,
                                     hipStream_t);
 
 void launch_cell_coords_masks(const uint64_t *B, const uint32_t *starts, uint64_t ncells_bound,

@@ -28,8 +28,9 @@ struct ArrayLoad {
 template <typename K>
 struct HeadFlagLoad {
     const K *k;
+    int shift;  // keys equal after this right shift are one cell
     __device__ __forceinline__ uint32_t operator()(size_t i) const {
-        return (i == 0 || k[i] != k[i - 1]) ? 1u : 0u;
+        return (i == 0 || (k[i] >> shift) != (k[i - 1] >> shift)) ? 1u : 0u;
     }
 };
 
@@ -264,10 +265,10 @@ void scan_long_rows_exclusive(const uint64_t *off, uint32_t lo, uint32_t *pos, s
 }
 
 template <typename K>
-void scan_head_flags_inclusive(const K *sorted_keys, uint32_t *out, size_t n, hipStream_t s) {
-    scan_one<uint32_t, true>(HeadFlagLoad<K>{sorted_keys}, out, n, nullptr, s);
+void scan_head_flags_inclusive(const K *sorted_keys, int shift, uint32_t *out, size_t n, hipStream_t s) {
+    scan_one<uint32_t, true>(HeadFlagLoad<K>{sorted_keys, shift}, out, n, nullptr, s);
 }
-template void scan_head_flags_inclusive<uint32_t>(const uint32_t *, uint32_t *, size_t, hipStream_t);
-template void scan_head_flags_inclusive<uint64_t>(const uint64_t *, uint32_t *, size_t, hipStream_t);
+template void scan_head_flags_inclusive<uint32_t>(const uint32_t *, int, uint32_t *, size_t, hipStream_t);
+template void scan_head_flags_inclusive<uint64_t>(const uint64_t *, int, uint32_t *, size_t, hipStream_t);
 
 }  // namespace sj

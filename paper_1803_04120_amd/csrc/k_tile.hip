@@ -10,16 +10,22 @@
 // [c0(first) - 1, c0(last) + 1]; because points are stored in cell order,
 // each of those rows is ONE contiguous point segment, found with two binary
 // searches in B. The wave stages a segment's coordinates (and the dimension-0
-// cell coordinate of every candidate) in its LDS slot, tile by tile; each
-// lane then finds, by binary search over the staged dimension-0 coordinates,
-// the window of candidates in cells c0 - 1 .. c0 + 1 of its own point and
-// evaluates exactly those -- the same candidate set as the per-point search
-// of Algorithm 1, read from LDS instead of global memory.
+// sub-cell coordinate of every candidate) in its LDS slot, tile by tile; each
+// lane then finds, by binary search over the staged sub-cell coordinates,
+// its window of candidates and evaluates exactly those. Inside a cell the
+// points are ordered by their dimension-0 sub-cell (width w / S), so the
+// window can be the sub-cells within w of the lane's own -- S on each side,
+// 2 + 1/S cell widths instead of the 3 of cells c0 - 1 .. c0 + 1 -- a subset
+// of the per-point search of Algorithm 1 that holds every pair within eps
+// (its members differ by at most eps <= w in dimension 0), read from LDS
+// instead of global memory.
 //
 // unicomp: rows whose block k >= 1 is gated by an odd dimension-k coordinate
 // are the same for all points of a chunk (they share dimensions 1..d-1); in
 // the chunk's own row a point evaluates its own cell as the triangle q >= p
-// and the cells c0 - 1, c0 + 1 only if c0 is odd (block 0).
+// and the cells c0 - 1, c0 + 1 only if c0 is odd (block 0). The sub-cell
+// window is symmetric (q is in p's window exactly when p is in q's), so each
+// pair within eps is still evaluated exactly once.
 //
 // Pair test, counters and emission are those of the per-point kernel.
 //
@@ -236,8 +242,15 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             }
         };
         auto evaluate_tile = [&](uint32_t T0, uint32_t len, bool own_row) {
-            uint32_t lo_c = c0p > 0 ? c0p - 1 : 0, hi_c = c0p + 1;
-            if (kUni && own_row && !(c0p & 1u)) lo_c = hi_c = c0p;
+            // the sub-cells within w of p's own in dimension 0 (S of them on
+            // each side: a neighbour differs by at most eps <= w); unicomp's
+            // own row with an even cell: the own cell's sub-cells only
+            const uint32_t S = 1u << t.sub_shift;
+            uint32_t lo_c = c0p >= S ? c0p - S : 0, hi_c = c0p + S;
+            if (kUni && own_row && !((c0p >> t.sub_shift) & 1u)) {
+                lo_c = (c0p >> t.sub_shift) << t.sub_shift;
+                hi_c = lo_c + S - 1;
+            }
             if (scx[0] > hi_c || scx[len - 1] < lo_c) return;
             // both window ends by one branchless search over the TS staged
             // entries (those past len hold ~0u), the two chains interleaved

@@ -279,6 +279,17 @@ void compute_grid(sj_index &ix) {
             int bits = 0;
             while (bits < 64 && (maxid >> bits) != 0) ++bits;
             ix.key_bits = bits;
+            // dimension-0 sub-cells per cell: 8, fewer when the sub-cell
+            // coordinate or the sort key would not fit (SJ_SUBCELL_SHIFT=0..3
+            // overrides)
+            uint32_t sh = 3;
+            if (const char *e = std::getenv("SJ_SUBCELL_SHIFT")) {
+                const int v = std::atoi(e);
+                if (v >= 0 && v <= 3) sh = static_cast<uint32_t>(v);
+            }
+            // (sub-cell coordinates plus the window's S stay below 2^32)
+            while (sh > 0 && ((ix.grid.dims[0] << sh) >= 0xfffffff0ULL || bits + static_cast<int>(sh) > 64)) --sh;
+            ix.grid.sub_shift = sh;
             return;
         }
         w = w * 2.0;
@@ -345,24 +356,26 @@ void build(sj_index &ix, const double *pts, int on_device, hipStream_t s) {
         ix.bmax[j] = hb[sj::kMaxDim + j];
     }
     compute_grid(ix);
-    // cell ids and the sort by cell (A)
-    if (ix.key_bits <= 32) {
+    // cell ids and the sort by cell (A), inside a cell by dimension-0 sub-cell
+    const int sh = static_cast<int>(ix.grid.sub_shift);
+    const int sort_bits = ix.key_bits + sh;
+    if (sort_bits <= 32) {
         uint32_t *keys = reinterpret_cast<uint32_t *>(keys64.ptr);
         uint32_t *keys_alt = reinterpret_cast<uint32_t *>(keys64_alt.ptr);
         sj::launch_cell_keys_u32(dp, n, ix.grid, keys, ix.perm.ptr, s);
-        if (sj::radix_sort_u32(keys, ix.perm.ptr, keys_alt, ids_alt.ptr, n, ix.key_bits, s)) {
+        if (sj::radix_sort_u32(keys, ix.perm.ptr, keys_alt, ids_alt.ptr, n, sort_bits, s)) {
             std::swap(keys, keys_alt);
             std::swap(ix.perm, ids_alt);
         }
-        sj::build_cells<uint32_t>(keys, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
+        sj::build_cells<uint32_t>(keys, n, sh, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
     } else {
         uint64_t *keys = keys64.ptr, *keys_alt = keys64_alt.ptr;
         sj::launch_cell_keys_u64(dp, n, ix.grid, keys, ix.perm.ptr, s);
-        if (sj::radix_sort_u64(keys, ix.perm.ptr, keys_alt, ids_alt.ptr, n, ix.key_bits, s)) {
+        if (sj::radix_sort_u64(keys, ix.perm.ptr, keys_alt, ids_alt.ptr, n, sort_bits, s)) {
             std::swap(keys, keys_alt);
             std::swap(ix.perm, ids_alt);
         }
-        sj::build_cells<uint64_t>(keys, n, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
+        sj::build_cells<uint64_t>(keys, n, sh, ix.cell_of.ptr, ix.B.ptr, ix.starts.ptr, s);
     }
     // per-cell coordinates and occupancy masks M_j (Section IV-C)
     uint64_t words = 0;
@@ -439,6 +452,7 @@ sj::TileArgs tile_args(sj_index &ix) {
     }
     t.cx = ix.cx.ptr;
     t.cxq = ix.cx.ptr;
+    t.sub_shift = ix.grid.sub_shift;
     t.chunks = ix.chunks;
     t.nchunks = ix.nchunks;
     t.nchunks_dev = ix.nchunks_dev.ptr;
@@ -1073,13 +1087,15 @@ void rs_count_perquery(sj_index &ix, const double *rp, uint64_t nr, hipStream_t 
     {
         DevBuf<uint32_t> qperm_alt(nr);
         DevBuf<uint64_t> k64(nr), k64_alt(nr);
+        sj::GridParams g = ix.grid;
+        g.sub_shift = 0;  // plain cell ids
         if (ix.key_bits <= 32) {
             uint32_t *k = reinterpret_cast<uint32_t *>(k64.ptr), *k2 = reinterpret_cast<uint32_t *>(k64_alt.ptr);
-            sj::launch_cell_keys_u32(rp, nr, ix.grid, k, st.qperm.ptr, s);
+            sj::launch_cell_keys_u32(rp, nr, g, k, st.qperm.ptr, s);
             if (sj::radix_sort_u32(k, st.qperm.ptr, k2, qperm_alt.ptr, nr, ix.key_bits, s))
                 std::swap(st.qperm, qperm_alt);
         } else {
-            sj::launch_cell_keys_u64(rp, nr, ix.grid, k64.ptr, st.qperm.ptr, s);
+            sj::launch_cell_keys_u64(rp, nr, g, k64.ptr, st.qperm.ptr, s);
             if (sj::radix_sort_u64(k64.ptr, st.qperm.ptr, k64_alt.ptr, qperm_alt.ptr, nr, ix.key_bits, s))
                 std::swap(st.qperm, qperm_alt);
         }
@@ -1195,10 +1211,10 @@ void rs_count_tiled(sj_index &ix, const double *rp, uint64_t nr, hipStream_t s) 
     st.Xq.ensure(nr * d);
     st.cxq.ensure(nr);
     if (k32)
-        sj::build_cells<uint32_t>(reinterpret_cast<uint32_t *>(k64.ptr), nr, st.cell_of.ptr, st.B.ptr,
+        sj::build_cells<uint32_t>(reinterpret_cast<uint32_t *>(k64.ptr), nr, 0, st.cell_of.ptr, st.B.ptr,
                                   st.starts.ptr, s);
     else
-        sj::build_cells<uint64_t>(k64.ptr, nr, st.cell_of.ptr, st.B.ptr, st.starts.ptr, s);
+        sj::build_cells<uint64_t>(k64.ptr, nr, 0, st.cell_of.ptr, st.B.ptr, st.starts.ptr, s);
     DevBuf<uint32_t> max_pts(1);
     sj::launch_cell_coords_masks(st.B.ptr, st.starts.ptr, nr, st.cell_of.ptr + (nr - 1), ix.grid, st.coords.ptr,
                                  nullptr, sj::MaskOffsets{}, 0, max_pts.ptr, s);
@@ -1710,7 +1726,7 @@ int sj_index_export_size(const sj_index *idx, int what, uint64_t *bytes) {
         case SJ_EXPORT_RANGES:
             *bytes = idx->last_ranges >= 0 ? idx->ranges[idx->last_ranges].count * 2 * sizeof(uint32_t) : 0;
             break;
-        case SJ_EXPORT_GRID: *bytes = (2 * sj::kMaxDim + 1) * sizeof(double); break;
+        case SJ_EXPORT_GRID: *bytes = (2 * sj::kMaxDim + 2) * sizeof(double); break;
         case SJ_EXPORT_ROW_OFFSETS: *bytes = (idx->counted && idx->n) ? (idx->n + 1) * sizeof(uint64_t) : 0; break;
         default: set_error("unknown export"); return SJ_EINVAL;
     }
@@ -1741,12 +1757,13 @@ int sj_index_export(const sj_index *idx, int what, void *host_dst, uint64_t byte
             case SJ_EXPORT_RANGES: src = idx->ranges[idx->last_ranges].rng; break;
             case SJ_EXPORT_ROW_OFFSETS: src = idx->off_orig.ptr; break;
             case SJ_EXPORT_GRID: {
-                double g[2 * sj::kMaxDim + 1] = {};
+                double g[2 * sj::kMaxDim + 2] = {};
                 for (uint32_t j = 0; j < idx->d; ++j) {
                     g[j] = idx->grid.gmin[j];
                     g[sj::kMaxDim + j] = static_cast<double>(idx->grid.dims[j]);
                 }
                 g[2 * sj::kMaxDim] = idx->grid.w;
+                g[2 * sj::kMaxDim + 1] = static_cast<double>(1u << idx->grid.sub_shift);
                 std::memcpy(host_dst, g, sizeof(g));
                 return;
             }

@@ -21,6 +21,10 @@ struct GridParams {
     uint64_t dims[kMaxDim];
     uint64_t stride[kMaxDim];
     uint32_t d;
+    // Within a cell, points are ordered by their dimension-0 sub-cell of
+    // width w / 2^sub_shift (then by id): the tiled join narrows each
+    // point's dimension-0 window to the sub-cells within w of its own.
+    uint32_t sub_shift;
 };
 
 struct SearchArgs {
@@ -88,8 +92,9 @@ struct TileArgs {
     uint32_t mask_off[kMaxDim];
     uint64_t dims[kMaxDim];
     uint64_t stride[kMaxDim];
-    const uint32_t *cx;       // dimension-0 cell coordinate of each cell-ordered point
+    const uint32_t *cx;       // dimension-0 sub-cell coordinate of each cell-ordered point
     const uint32_t *cxq;      // the same for the query points (cx for the self-join)
+    uint32_t sub_shift;       // sub-cells per cell in dimension 0: 2^sub_shift
     const uint2 *chunks;      // [first, end) point range of each chunk
     uint32_t nchunks;         // upper bound on the chunk count (launch size)
     const uint32_t *nchunks_dev;  // the chunk count (device)

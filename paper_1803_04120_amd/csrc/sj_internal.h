@@ -129,10 +129,11 @@ void scan_row_chunks_exclusive(const uint32_t *row_pt, const uint64_t *row_of, u
 // pos[r] = rows before r longer than lo entries (lengths off[r+1] - off[r]),
 // pos[rows] = their number.
 void scan_long_rows_exclusive(const uint64_t *off, uint32_t lo, uint32_t *pos, size_t rows, hipStream_t s);
-// Inclusive scan of the head flags (key[r] != key[r-1], 1 at r = 0) of a
-// sorted key array: out[r] = 1 + number of distinct keys before r.
+// Inclusive scan of the head flags (key[r] >> shift != key[r-1] >> shift, 1
+// at r = 0) of a sorted key array: out[r] = 1 + number of distinct shifted
+// keys before r.
 template <typename K>
-void scan_head_flags_inclusive(const K *sorted_keys, uint32_t *out, size_t n, hipStream_t s);
+void scan_head_flags_inclusive(const K *sorted_keys, int shift, uint32_t *out, size_t n, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) by the low `bits` bits of key.
 // The passes alternate between the two buffer pairs: returns false when the
@@ -152,12 +153,15 @@ void launch_cell_keys_u64(const double *pts, uint64_t n, const GridParams &g, ui
                           uint32_t *ids, hipStream_t s);
 void launch_cell_keys_u32(const double *pts, uint64_t n, const GridParams &g, uint32_t *keys,
                           uint32_t *ids, hipStream_t s);
-// head flags + inclusive scan + cell tables. cell_of receives the cell of
-// each cell-ordered point, B the distinct ids, starts the first point of
-// each cell (starts[|G|] is written as n); |G| = cell_of[n - 1] + 1 (left on
-// the device: no host sync).
+// Sort keys: the cell id, or with g.sub_shift > 0 the cell id shifted left by
+// it and the dimension-0 sub-cell appended (ids[i] = i).
+// head flags + inclusive scan + cell tables over sorted keys; keys equal
+// after a right shift by `shift` are one cell. cell_of receives the cell of
+// each cell-ordered point, B the distinct shifted keys, starts the first
+// point of each cell (starts[|G|] is written as n); |G| = cell_of[n - 1] + 1
+// (left on the device: no host sync).
 template <typename K>
-void build_cells(const K *sorted_keys, uint64_t n, uint32_t *cell_of, uint64_t *B, uint32_t *starts,
+void build_cells(const K *sorted_keys, uint64_t n, int shift, uint32_t *cell_of, uint64_t *B, uint32_t *starts,
                  hipStream_t s);
 // Word offset of each dimension's occupancy mask.
 struct MaskOffsets {

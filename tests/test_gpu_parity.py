@@ -292,7 +292,17 @@ def test_index_matches_grid_oracle(sj, kind, d, n, eps):
         np.testing.assert_array_equal(grid[8:8 + d].astype(np.int64), g.dims)
         assert grid[16] == g.w
         np.testing.assert_array_equal(ix.export(sj._lib.SJ_EXPORT_CELL_IDS), g.B)
-        np.testing.assert_array_equal(ix.export(sj._lib.SJ_EXPORT_PERM).astype(np.int64), g.A)
+        # A: the paper's order by cell; inside a cell (an order the paper
+        # leaves open) by the dimension-0 sub-cell floor(t * s), then by id
+        s_sub = int(grid[17])
+        assert s_sub in (1, 2, 4, 8)
+        t = (pts[:, 0] - g.gmin[0]) / g.w
+        sub = np.clip(np.floor(t * s_sub), 0, s_sub * g.dims[0] - 1).astype(np.int64) % s_sub
+        key2 = g.keys.astype(np.int64) * s_sub + sub
+        a_want = np.argsort(key2, kind="stable")
+        a_got = ix.export(sj._lib.SJ_EXPORT_PERM).astype(np.int64)
+        np.testing.assert_array_equal(a_got, a_want)
+        np.testing.assert_array_equal(np.sort(g.keys[a_got]), g.keys[g.A])  # same cells as the paper's A
         starts = ix.export(sj._lib.SJ_EXPORT_CELL_START).astype(np.int64)
         np.testing.assert_array_equal(starts[:-1], g.G[:, 0])
         assert starts[-1] == n
@@ -347,17 +357,40 @@ def test_worked_example_search(sj):
 
 @pytest.mark.parametrize("kind,d,eps", [("uniform", 2, 1.5), ("clustered", 2, 0.5),
                                         ("uniform", 3, 6.0), ("uniform", 5, 20.0)])
-def test_unicomp_evaluation_counts(sj, join_kernel, kind, d, eps):
-    """Distance evaluations: full search = the oracle's T, unicomp = (T+n)/2."""
+def test_unicomp_evaluation_counts(sj, join_kernel, kind, d, eps, monkeypatch):
+    """Distance evaluations: full search = the oracle's T, unicomp = (T+n)/2
+    (the per-point kernel, and the tiled kernel without dimension-0
+    sub-cells). With sub-cells (the default, s of them per cell) the tiled
+    kernel evaluates, for each point, the points of its adjacent cells whose
+    sub-cell differs from its own by at most s (T_s, counted here by brute
+    force over all ordered pairs), and unicomp (T_s + n) / 2."""
     _say(f"evaluation counts {kind} d={d}")
-    pts = datagen.make(kind, 6000, d, seed=3)
+    n = 6000
+    pts = datagen.make(kind, n, d, seed=3)
     g = og.GridIndex(pts, eps)
     T = g.evaluations(unicomp=False)
-    with sj.Index(torch.from_numpy(pts).cuda(), eps) as ix:
-        ix.count(unicomp=False)
-        assert ix.stats()["evals"] == T
-        ix.count(unicomp=True)
-        assert ix.stats()["evals"] == (T + 6000) // 2
+    for shift in ((None, 0) if join_kernel == "tiled" else (None,)):
+        if shift is None:
+            monkeypatch.delenv("SJ_SUBCELL_SHIFT", raising=False)
+        else:
+            monkeypatch.setenv("SJ_SUBCELL_SHIFT", str(shift))
+        with sj.Index(torch.from_numpy(pts).cuda(), eps) as ix:
+            s_sub = int(ix.export(sj._lib.SJ_EXPORT_GRID)[17])
+            want = T
+            if join_kernel == "tiled" and s_sub > 1:
+                sub = np.clip(np.floor((pts[:, 0] - g.gmin[0]) / g.w * s_sub), 0,
+                              s_sub * g.dims[0] - 1).astype(np.int64)
+                cc = g.coords.astype(np.int64)
+                want = 0
+                for a in range(0, n, 500):
+                    adj = np.all(np.abs(cc[a:a + 500, None, :] - cc[None, :, :]) <= 1, axis=2)
+                    want += int(np.count_nonzero(adj & (np.abs(sub[a:a + 500, None] - sub[None, :]) <= s_sub)))
+                assert want < T
+            ix.count(unicomp=False)
+            assert ix.stats()["evals"] == want
+            ix.count(unicomp=True)
+            assert ix.stats()["evals"] == (want + n) // 2
+    monkeypatch.delenv("SJ_SUBCELL_SHIFT", raising=False)
 
 
 # ---------------------------------------------------------------- batching
