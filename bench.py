@@ -42,7 +42,7 @@ Beside `value` (pairs/s of the timed steps) the line carries:
                    host threads; cpu_baseline_1core the same on one thread;
   cpu_grid_baseline  the host-core grid join on whole joins of the workload.
 
-  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-legs]
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-legs] [--legs A,B]
                   [--no-cpu-baseline] [--no-serve]
 """
 from __future__ import annotations
@@ -100,6 +100,9 @@ def parse():
     ap.add_argument("--unicomp", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_band"])
     ap.add_argument("--no-legs", action="store_true", help="only the headline workload")
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated legs to run (unicomp_off, fp32_band, batched, clustered_5M, "
+                         "uniform2d_2M, uniform2d_10k, brute_force, rs_join, serving); default all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of each host baseline sample")
@@ -488,27 +491,68 @@ def brute_leg(sj, _lib, torch):
     return res
 
 
-def rs_leg(sj, torch):
+def rs_model(name, nq, ns, d, P, evals):
+    """(algorithmic HBM bytes, FP64 operations) of one two-set join launch:
+    every query's coordinates, sub-cell, row id and row offsets once, S's
+    coordinates, sub-cell and id once, the result once; (3d - 1) operations
+    per distance evaluation."""
+    ops = evals * (3 * d - 1)
+    if name.startswith("tiled_count"):
+        return nq * (8 * d + 4 + 4 + 4) + ns * (8 * d + 4), ops
+    if name.startswith("tiled_fill_sort"):
+        return nq * (8 * d + 4 + 4 + 8 + 8) + ns * (8 * d + 4 + 4) + 8 * P, ops
+    if name.startswith("tiled_fill"):
+        return nq * (8 * d + 4 + 4 + 8) + ns * (8 * d + 4 + 4) + 4 * P, ops
+    return None
+
+
+def rs_leg(sj, _lib, torch):
+    """R x S on the tiled kernel: 10^6 uniform 2-D queries against the 2M
+    indexed points, five eps; timed calls, then one profiled call per eps
+    for the count and fill kernels' rooflines."""
     from paper_1803_04120_amd import datagen
     S = torch.from_numpy(datagen.uniform(2_000_000, 2, 2)).cuda()
     R = torch.from_numpy(datagen.uniform(1_000_000, 2, 1002)).cuda()
     out = torch.empty((26_000_000, 2), dtype=torch.int32, device="cuda")
-    per = []
+    per, kern = [], {}
     for e in (0.04, 0.08, 0.12, 0.16, 0.2):
         with sj.Index(S, e) as ix:
             ix.join_rs(R, out=out)
+            st = _lib.last_run_stats()
             reps = 3
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(reps):
                 got = ix.join_rs(R, out=out)
             torch.cuda.synchronize()
-            per.append((e, int(got.shape[0]), (time.perf_counter() - t0) / reps))
-    tp, tt = sum(p for _, p, _ in per), sum(t for _, _, t in per)
+            per.append((e, int(got.shape[0]), (time.perf_counter() - t0) / reps, int(st["evals"])))
+            _lib.profile_select("")
+            _lib.profile_enable(True)
+            ix.join_rs(R, out=out)
+            torch.cuda.synchronize()
+            _lib.profile_enable(False)
+            for name, (cnt, ms) in _lib.profile_read().items():
+                m = rs_model(name, 1_000_000, 2_000_000, 2, int(got.shape[0]), int(st["evals"]))
+                if m is None:
+                    continue
+                k = kern.setdefault(name, [0, 0.0, 0, 0])
+                k[0] += cnt
+                k[1] += ms
+                k[2] += m[0]
+                k[3] += m[1]
+    tp, tt = sum(p for _, p, _, _ in per), sum(t for _, _, t, _ in per)
     log(f"[bench] two-set join: {tp / tt:.4g} pairs/s")
+    roof = {}
+    for name, (cnt, ms, b, o) in kern.items():
+        r, hbm, valu = roofline_of(name, cnt, ms, b, o)
+        r["hbm_frac"], r["valu_frac"] = hbm["frac"], valu["frac"]
+        r["traffic"] = measured_traffic(name, "uniform2d_q1M_s2M_eps_sweep")
+        roof[name] = r
     return {"queries": 1_000_000, "indexed": 2_000_000, "pairs_per_s": tp / tt, "ms_per_sweep": 1e3 * tt,
-            "per_eps": [{"eps": e, "pairs": p, "ms": round(1e3 * t, 3)} for e, p, t in per],
-            "note": "count + fill + row sort per call (sj_join_rs), index on the 2M uniform 2-D points"}
+            "per_eps": [{"eps": e, "pairs": p, "ms": round(1e3 * t, 3), "evals": ev} for e, p, t, ev in per],
+            "roofline": roof,
+            "note": "count + fill + row sort per call (sj_join_rs, grid-row tiled kernel), index on the 2M "
+                    "uniform 2-D points"}
 
 
 def dbscan_leg(sj, torch, wl):
@@ -699,18 +743,25 @@ def main():
     torch.cuda.empty_cache()
 
     legs = {}
+    chosen = None if args.legs == "all" else set(args.legs.split(","))
+
+    def want(name):
+        return chosen is None or name in chosen
     if not args.no_legs:
         if args.workload == DEFAULT_WORKLOAD:
-            legs["unicomp_off"] = sweep_leg(sj, _lib, torch, wl, 2, unicomp=False, label="unicomp off")
-            legs["unicomp_off"]["vs_unicomp_on"] = round(legs["unicomp_off"]["pairs_per_s"] / value, 4)
-            legs["fp32_band"] = sweep_leg(sj, _lib, torch, wl, 2, precision="fp32_band", label="fp32+band")
-            legs["fp32_band"]["vs_fp64"] = round(legs["fp32_band"]["pairs_per_s"] / value, 4)
-            legs["batched"] = batched_leg(sj, torch, wl, 1 << 27)
-            legs["batched"]["vs_unbatched"] = round(legs["batched"]["pairs_per_s"] / value, 4)
+            if want("unicomp_off"):
+                legs["unicomp_off"] = sweep_leg(sj, _lib, torch, wl, 2, unicomp=False, label="unicomp off")
+                legs["unicomp_off"]["vs_unicomp_on"] = round(legs["unicomp_off"]["pairs_per_s"] / value, 4)
+            if want("fp32_band"):
+                legs["fp32_band"] = sweep_leg(sj, _lib, torch, wl, 2, precision="fp32_band", label="fp32+band")
+                legs["fp32_band"]["vs_fp64"] = round(legs["fp32_band"]["pairs_per_s"] / value, 4)
+            if want("batched"):
+                legs["batched"] = batched_leg(sj, torch, wl, 1 << 27)
+                legs["batched"]["vs_unbatched"] = round(legs["batched"]["pairs_per_s"] / value, 4)
         for name, key, steps in (("clustered_5M", "clustered_n5M_d2-3_median50", 3),
                                  ("uniform2d_2M", "uniform2d_n2M_eps_sweep", 20),
                                  ("uniform2d_10k", "uniform2d_n10k_eps1", 50)):
-            if key == args.workload:
+            if key == args.workload or not want(name):
                 continue
             w2 = Workload(key, W[key], torch)
             legs[name] = {"workload": key, "fp64": sweep_leg(sj, _lib, torch, w2, steps, label=key)}
@@ -733,9 +784,11 @@ def main():
                                                  "sample": "the whole 10,000-point join"}
             del w2
             torch.cuda.empty_cache()
-        legs["brute_force"] = brute_leg(sj, _lib, torch)
-        legs["rs_join"] = rs_leg(sj, torch)
-        if not args.no_serve:
+        if want("brute_force"):
+            legs["brute_force"] = brute_leg(sj, _lib, torch)
+        if want("rs_join"):
+            legs["rs_join"] = rs_leg(sj, _lib, torch)
+        if not args.no_serve and want("serving"):
             legs["serving"] = serving_leg(args, sj, torch)
 
     if args.calib_copy:

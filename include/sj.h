@@ -277,8 +277,10 @@ int sj_index_stats(const sj_index *idx, sj_stats *out);
 /*
  * Statistics of the last join run on the calling thread, whatever produced
  * it: a count or fill pass, the batched join (Section V-A), the convenience
- * sj_selfjoin (whose index is gone when it returns), the two-set join or the
- * brute force (whose evals is n^2). Fields a run does not produce are 0.
+ * sj_selfjoin (whose index is gone when it returns), the two-set join (n is
+ * then the number of query rows, the grid fields are S's, and evals is
+ * counted by the tiled kernel only) or the brute force (whose evals is n^2).
+ * Fields a run does not produce are 0.
  * SJ_ESTATE if no join has run on this thread.
  */
 int sj_last_run_stats(sj_stats *out);

@@ -238,6 +238,71 @@ __global__ __launch_bounds__(kThreads) void k_compact_long(const uint64_t *__res
     if (r < rows && off[r + 1] - off[r] > lo) list[pos[r]] = static_cast<uint32_t>(r);
 }
 
+// The all-ascending (mirror) form of the bitonic sorter over 64 R values of
+// one wave, lane l holding element e = 64 k + l in v[k]: the merge of two
+// sorted blocks of size kk/2 first compares each e with its mirror
+// e ^ (kk - 1), then with e ^ j for j = kk/4 .. 1, the lower index taking
+// the minimum. Every block stays ascending, so the padding (kPad, the largest
+// value) never leaves the positions at or past the row's length: registers
+// k >= kact hold only padding at every stage, and every exchange with one of
+// them is skipped (kact is uniform across the wave). A row of 257 entries
+// costs 5 registers' work, not 8.
+template <int R>
+__device__ __forceinline__ void wave_bitonic_mirror(uint32_t (&v)[R], uint32_t kact) {
+    const uint32_t lane = static_cast<uint32_t>(lane_id());
+    // partner lane ^ m in the same register; hb: the highest bit of m
+    auto lane_stage = [&](int m, uint32_t hb) {
+        const bool lower = (lane & hb) == 0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (static_cast<uint32_t>(k) < kact) {
+                // (the 16-register network is not unrolled whole: a partner
+                // distance known only at run time would make the DPP choice a
+                // branch per exchange)
+                const uint32_t p = R <= 8 ? lane_xor(v[k], m)
+                                          : static_cast<uint32_t>(__shfl_xor(static_cast<int>(v[k]), m, 64));
+                v[k] = lower ? (v[k] < p ? v[k] : p) : (v[k] < p ? p : v[k]);
+            }
+        }
+    };
+    // registers k < k ^ r: elements (k, l) and (k ^ r, 63 - l)
+    auto reg_mirror = [&](int r) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int kp = k ^ r;
+            if (k < kp && static_cast<uint32_t>(kp) < kact) {
+                const uint32_t a = v[k], b = v[kp];
+                const uint32_t ra = static_cast<uint32_t>(__shfl_xor(static_cast<int>(a), 63, 64));
+                const uint32_t rb = static_cast<uint32_t>(__shfl_xor(static_cast<int>(b), 63, 64));
+                v[k] = a < rb ? a : rb;
+                v[kp] = b < ra ? ra : b;
+            }
+        }
+    };
+    // registers k < k ^ r, same lane
+    auto reg_half = [&](int r) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int kp = k ^ r;
+            if (k < kp && static_cast<uint32_t>(kp) < kact) cas_asc(v[k], v[kp]);
+        }
+    };
+#pragma unroll
+    for (int kk = 2; kk <= 64 * R; kk <<= 1) {
+        if (kk <= 64)
+            lane_stage(kk - 1, static_cast<uint32_t>(kk >> 1));
+        else
+            reg_mirror((kk - 1) >> 6);
+#pragma unroll
+        for (int j = kk >> 2; j > 0; j >>= 1) {
+            if (j >= 64)
+                reg_half(j >> 6);
+            else
+                lane_stage(j, static_cast<uint32_t>(j));
+        }
+    }
+}
+
 // One row of 65..1024 entries per wave, in registers: R = 4, 8 or 16 by the
 // row's length (uniform across the wave).
 template <int R>
@@ -249,7 +314,7 @@ __device__ __forceinline__ void wave_sort_row(const RowRef &x, const RowDst &o, 
         const uint32_t e = static_cast<uint32_t>(k) * 64 + lane;
         v[k] = e < x.len ? out_j[x.in + e] : kPad;
     }
-    group_bitonic<R, 1>(v, nullptr);
+    wave_bitonic_mirror<R>(v, (x.len + 63) / 64);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const uint32_t e = static_cast<uint32_t>(k) * 64 + lane;
@@ -257,6 +322,10 @@ __device__ __forceinline__ void wave_sort_row(const RowRef &x, const RowDst &o, 
     }
 }
 
+// kWide = false: the rows of 65..512 entries (4 or 8 registers); true: those
+// of 513..1024 (16 registers), a launch of its own so that the 16-register
+// network's registers do not cost the common case waves per SIMD.
+template <bool kWide>
 __global__ __launch_bounds__(kThreads) void k_rowsort_wave(RowMap m, RowDst o, const uint32_t *__restrict__ out_j,
                                                             const uint32_t *__restrict__ list,
                                                             const uint32_t *__restrict__ count) {
@@ -264,11 +333,11 @@ __global__ __launch_bounds__(kThreads) void k_rowsort_wave(RowMap m, RowDst o, c
     const uint32_t nlong = *count;
     for (uint32_t w = blockIdx.x * kWaves + wave; w < nlong; w += gridDim.x * kWaves) {
         const RowRef x = row_ref(m, list[w]);
-        if (x.len <= 256)
+        if (!kWide && x.len <= 256)
             wave_sort_row<4>(x, o, out_j);
-        else if (x.len <= 512)
+        else if (!kWide && x.len <= 512)
             wave_sort_row<8>(x, o, out_j);
-        else if (x.len <= kWaveCap)
+        else if (kWide && x.len > 512 && x.len <= kWaveCap)
             wave_sort_row<16>(x, o, out_j);
         // longer: a workgroup kernel's
     }
@@ -397,10 +466,15 @@ void rowsort_long(const RowMap &m, const RowDst &o, uint32_t *out_j, uint32_t ma
     if (max_len <= 64) return;
     DevBuf<uint32_t> pos, list;
     compact_rows(m, 64, pos, list, s);
+    const unsigned gw = static_cast<unsigned>(std::min<uint64_t>((m.rows + kWaves - 1) / kWaves, 8192));
     {
         KTimer kt_("rowsort_wave", s);
-        const unsigned gw = static_cast<unsigned>(std::min<uint64_t>((m.rows + kWaves - 1) / kWaves, 8192));
-        k_rowsort_wave<<<gw, kThreads, 0, s>>>(m, o, out_j, list.ptr, pos.ptr + m.rows);
+        k_rowsort_wave<false><<<gw, kThreads, 0, s>>>(m, o, out_j, list.ptr, pos.ptr + m.rows);
+        SJ_LAUNCH_CHECK();
+    }
+    if (max_len > 512) {
+        KTimer kt_("rowsort_wave16", s);
+        k_rowsort_wave<true><<<gw, kThreads, 0, s>>>(m, o, out_j, list.ptr, pos.ptr + m.rows);
         SJ_LAUNCH_CHECK();
     }
     if (max_len <= kWaveCap) return;

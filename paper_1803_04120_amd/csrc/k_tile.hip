@@ -71,6 +71,10 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     using CT = typename std::conditional<kBand, float, double>::type;
     constexpr bool kAgg = (kMode == kCount) && kUni;  // mirrored counts summed in LDS
     constexpr bool kPerm = (kMode == kFill);          // candidate ids staged in LDS
+    // unicomp fill: the lanes that hit each staged candidate collected as a
+    // mask in LDS, its mirrored entries written after the tile with one
+    // global slot reservation per candidate
+    constexpr bool kMirAgg = (kMode == kFill) && kUni;
     // staged coordinates; the fused fill reuses the slot after the last
     // tile for its write-out table (row destination, row id, length)
     constexpr size_t kStageBytes = sizeof(CT) * TS * D;
@@ -79,6 +83,8 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     __shared__ uint32_t sc_all[kWaves][TS];
     __shared__ uint32_t sa_all[kWaves][(kAgg || kPerm) ? TS : 1];
     __shared__ uint32_t sr_all[kWaves][NS > 0 ? 64 * kRowStride : 1];
+    __shared__ unsigned long long sm_all[kWaves][kMirAgg ? TS : 1];
+    __shared__ uint32_t sp_all[kWaves][kMirAgg ? 64 : 1];
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
     CT *sx = reinterpret_cast<CT *>(sx_all[wave]);
@@ -88,6 +94,8 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     uint32_t *scx = sc_all[wave];
     uint32_t *saux = sa_all[wave];
     uint32_t *srow = sr_all[wave] + lane * (NS > 0 ? kRowStride : 0);
+    unsigned long long *smask = sm_all[wave];
+    uint32_t *sperm = sp_all[wave];  // the chunk's point ids by lane
 
     uint32_t own = 0, evals = 0, rechecks = 0;
     // chunks go to workgroups in launch order, which the hardware deals out
@@ -129,6 +137,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 if (NS > 0) row_len = static_cast<uint32_t>(a.offc[p + 1] - a.offc[p]);
             }
         }
+        if (kMirAgg) sperm[lane] = perm_p;  // read after the first tile's barrier
         // fused fill: rows that fit stay in the lane's LDS slot
         const bool row_in_lds = NS > 0 && row_len <= static_cast<uint32_t>(NS);
         // chunk geometry (uniform)
@@ -192,14 +201,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 else
                     atomicOr(a.overflow, 1u);
                 ++own;
-                if (mirror) {
-                    const uint32_t slot = atomicAdd(&a.cur[q], 1u);
-                    const uint64_t at2 = a.offc[q] - a.out_base + a.own_cnt[q] + slot;
-                    if (at2 < a.out_cap)
-                        a.out_j[at2] = perm_p;
-                    else
-                        atomicOr(a.overflow, 1u);
-                }
+                if (kMirAgg && mirror) atomicOr(&smask[i], 1ull << lane);
             }
         };
         // candidates [i0, i1) of the staged tile, kUnroll of them loaded and
@@ -378,6 +380,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 scx[i] = t.cx[q];
                 if (kAgg) saux[i] = 0;
                 if (kPerm) saux[i] = a.perm[q];
+                if (kMirAgg) smask[i] = 0;
             }
             for (uint32_t i = len + lane; i < static_cast<uint32_t>(TS); i += 64) scx[i] = ~0u;
             const Tile nxt = advance(cur);
@@ -389,6 +392,28 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 for (uint32_t i = lane; i < len; i += 64) {
                     const uint32_t cnt = saux[i];
                     if (cnt) atomicAdd(&a.in_cnt[cur.T0 + i], cnt);
+                }
+            }
+            if (kMirAgg) {
+                // each candidate's mirrored entries: one slot reservation in
+                // its row, then the ids of the lanes that hit it, in a run
+                wave_sync_lds();
+                for (uint32_t i = lane; i < len; i += 64) {
+                    unsigned long long m = smask[i];
+                    if (m) {
+                        const uint32_t q = cur.T0 + i;
+                        const uint32_t slot = atomicAdd(&a.cur[q], static_cast<uint32_t>(__popcll(m)));
+                        uint64_t at = a.offc[q] - a.out_base + a.own_cnt[q] + slot;
+                        while (m) {
+                            const int b = __builtin_ctzll(m);
+                            m &= m - 1;
+                            if (at < a.out_cap)
+                                a.out_j[at] = sperm[b];
+                            else
+                                atomicOr(a.overflow, 1u);
+                            ++at;
+                        }
+                    }
                 }
             }
             cur = nxt;

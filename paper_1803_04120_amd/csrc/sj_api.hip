@@ -219,13 +219,17 @@ struct sj_index {
         DevBuf<uint2> segs;
         uint64_t rows_longer[3] = {0, 0, 0};
         uint64_t evals = 0;
+        sj_stats stats{};  // of the last two-set join (sj_last_run_stats)
     } rs;
+    // second stream of the batched join (default priority), created on first use
+    hipStream_t side_stream = nullptr;
 
     ~sj_index() {
         for (auto &r : ranges)
             if (r.rng) sj::dev_free(r.rng);
         if (chunks) sj::dev_free(chunks);
         if (rs.chunks) sj::dev_free(rs.chunks);
+        if (side_stream) (void)hipStreamDestroy(side_stream);
     }
 };
 
@@ -714,21 +718,23 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
                            ix.opts.sort_output != 0);
 }
 
-// The fill pass may evaluate the unicomp subset (every mirrored pair then
-// takes a global slot with an atomic) or all adjacent cells (each point
-// writes only its own row, no atomics, twice the distance evaluations).
-// Both fill the same rows. When pairs are a large fraction of the unicomp
-// evaluations the atomics cost more than the extra evaluations: the unicomp
-// fill is taken below 8%.
+// The fill pass may evaluate the unicomp subset (every candidate's mirrored
+// entries then take a slot in its row with one atomic per tile) or all
+// adjacent cells (each point writes only its own row, no atomics, twice the
+// distance evaluations; in 1..3-D its rows are sorted inside the fill).
+// Both fill the same rows. Measured on the 10M-point joins: from 4-D on the
+// unicomp fill is faster at every density (4-D: 4.1 against 4.6 ms at 32
+// neighbours, 19.2 against 24.2 ms at 256; 5-D: 45 against 72 ms); in 3-D
+// the full fill with its fused row sort is as fast or faster (4.4 against
+// 2.5 + 2.3 ms of row sorts at 32 neighbours), so there the unicomp fill is
+// taken only when pairs are under 8% of the unicomp evaluations.
 // SJ_FILL_MODE=full|unicomp overrides the choice.
 bool choose_unicomp_fill(const sj_index &ix) {
     if (!ix.opts.unicomp) return false;
     const char *e = std::getenv("SJ_FILL_MODE");
     if (e && std::strcmp(e, "full") == 0) return false;
     if (e && std::strcmp(e, "unicomp") == 0) return true;
-    // measured on the 10M-point joins: unicomp fill faster at 5.0% (5-D, 32
-    // neighbours: 12.1 against 16.1 ms), even at 5.3% (5-D, 256), slower at
-    // about 12% (4-D: 6.7 against 5.0 ms, and 92 against 27 ms)
+    if (ix.d >= 4) return true;
     return static_cast<double>(ix.pairs) < 0.08 * static_cast<double>(ix.stats.evals);
 }
 
@@ -799,23 +805,41 @@ int join_batched_cells(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
     const bool fused = tiled && use_fused_sort(ix.d);
     const uint32_t ns = fused ? fused_slot(ix) : 0;
     const int nsets = nb > 1 ? 2 : 1;
-    DevBuf<uint32_t> out_j[2], pairs[2];
+    DevBuf<uint32_t> out_j[2], pairs[2], len_b[2];
+    DevBuf<uint64_t> off_b[2];
     for (int k = 0; k < nsets; ++k) {
         out_j[k].reset(std::max<uint64_t>(1, maxbatch));
         pairs[k].reset(2 * std::max<uint64_t>(1, maxbatch));
+        len_b[k].reset(n);
+        off_b[k].reset(n + 1);
     }
-    DevBuf<uint32_t> len_b(n);
-    DevBuf<uint64_t> off_b(n + 1);
-    hipEvent_t ev[2];
+    if (!tiled) ensure_ranges(ix, 0, s);
+    // Batches alternate between the caller's stream and a second one, each
+    // with its own buffers: a batch's fill launch holds few rounds of
+    // long-running waves, and its tail overlaps the next batch's start.
+    // Batch b reuses the buffers of batch b - 2, which ran on the same
+    // stream and was delivered before b is enqueued.
+    hipStream_t ss[2] = {s, s};
+    if (nsets > 1) {
+        if (!ix.side_stream) SJ_HIP(hipStreamCreateWithFlags(&ix.side_stream, hipStreamNonBlocking));
+        ss[1] = ix.side_stream;
+    }
+    hipEvent_t ev[3];
     SJ_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     SJ_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    SJ_HIP(hipEventCreateWithFlags(&ev[2], hipEventDisableTiming));
     struct EvGuard {
         hipEvent_t *e;
+        hipStream_t side;
         ~EvGuard() {
+            // no work of this call may outlive it on the second stream (its
+            // freed blocks are released once the caller's stream is synchronised)
+            if (side) (void)hipStreamSynchronize(side);
             (void)hipEventDestroy(e[0]);
             (void)hipEventDestroy(e[1]);
+            (void)hipEventDestroy(e[2]);
         }
-    } evg{ev};
+    } evg{ev, nsets > 1 ? ss[1] : nullptr};
     int rc = 0;
     auto deliver = [&](uint32_t b) {
         const int k = b & 1;
@@ -825,14 +849,20 @@ int join_batched_cells(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
     ix.overflow.ensure(1);
     sj::launch_fill_u32(ix.overflow.ptr, 1, 0u, s);
     ix.overflow_clear = false;
+    if (nsets > 1) {
+        // the second stream starts after everything before on the caller's
+        SJ_HIP(hipEventRecord(ev[2], s));
+        SJ_HIP(hipStreamWaitEvent(ss[1], ev[2], 0));
+    }
     for (uint32_t b = 0; b < nb && rc == 0; ++b) {
         const int k = b & 1;
+        hipStream_t st = ss[k];
         const uint64_t r0 = pos[b], r1 = pos[b + 1], bp = boff[b + 1] - boff[b];
         if (bp > 0) {
             // the batch's row offsets in order of i
-            sj::launch_fill_u32(len_b.ptr, n, 0u, s);
-            sj::launch_batch_lengths(ix.len_cell.ptr, ix.perm.ptr, r0, r1, len_b.ptr, s);
-            sj::scan_exclusive_u32_to_u64(len_b.ptr, off_b.ptr, n, s);
+            sj::launch_fill_u32(len_b[k].ptr, n, 0u, st);
+            sj::launch_batch_lengths(ix.len_cell.ptr, ix.perm.ptr, r0, r1, len_b[k].ptr, st);
+            sj::scan_exclusive_u32_to_u64(len_b[k].ptr, off_b[k].ptr, n, st);
             sj::JoinArgs a = base_args(ix, 0);
             a.out_j = out_j[k].ptr;
             a.offc = ix.off_cell.ptr;
@@ -844,12 +874,11 @@ int join_batched_cells(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
                 t.chunk0 = unit[b];
                 t.chunk_end = unit[b + 1];
                 if (fused) {
-                    a.off_orig = off_b.ptr;
+                    a.off_orig = off_b[k].ptr;
                     a.pairs = reinterpret_cast<uint2 *>(pairs[k].ptr);
                 }
-                sj::launch_join_tiled(a, t, ix.d, 0, sj::kFill, ix.band_used, s, ns);
+                sj::launch_join_tiled(a, t, ix.d, 0, sj::kFill, ix.band_used, st, ns);
             } else {
-                ensure_ranges(ix, 0, s);
                 a = base_args(ix, 0);
                 a.out_j = out_j[k].ptr;
                 a.offc = ix.off_cell.ptr;
@@ -859,16 +888,21 @@ int join_batched_cells(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
                 a.qlist = nullptr;
                 a.qbase = static_cast<uint32_t>(r0);
                 a.nq = static_cast<uint32_t>(r1 - r0);
-                sj::launch_join(a, ix.d, 0, sj::kFill, ix.band_used, s);
+                sj::launch_join(a, ix.d, 0, sj::kFill, ix.band_used, st);
             }
-            sj::launch_rowsort_range(ix.off_cell.ptr, r0, r1, boff[b], off_b.ptr, ix.perm.ptr, out_j[k].ptr,
-                                     pairs[k].ptr, ix.max_row, fused ? 64u : 0u, s, nullptr,
+            sj::launch_rowsort_range(ix.off_cell.ptr, r0, r1, boff[b], off_b[k].ptr, ix.perm.ptr, out_j[k].ptr,
+                                     pairs[k].ptr, ix.max_row, fused ? 64u : 0u, st, nullptr,
                                      ix.opts.sort_output != 0);
         }
-        SJ_HIP(hipEventRecord(ev[k], s));
+        SJ_HIP(hipEventRecord(ev[k], st));
         if (b >= 1) deliver(b - 1);
     }
     if (rc == 0) deliver(nb - 1);
+    if (nsets > 1) {
+        // the caller's stream continues after the second stream's batches
+        SJ_HIP(hipEventRecord(ev[2], ss[1]));
+        SJ_HIP(hipStreamWaitEvent(s, ev[2], 0));
+    }
     check_overflow(ix, s);
     ix.stats.batches = nb;
     ix.stats.ms_fill = now_ms() - t0;
@@ -1273,6 +1307,7 @@ void rs_count_tiled(sj_index &ix, const double *rp, uint64_t nr, hipStream_t s) 
     st.P = sm[0];
     st.max_len = static_cast<uint32_t>(sm[1]);
     st.evals = sm[2];
+    st.stats.chunks = sm[4];
     for (int k = 0; k < 3; ++k) st.rows_longer[k] = sm[5 + k];
 }
 
@@ -1335,11 +1370,29 @@ void rs_count(sj_index &ix, const double *R, uint64_t nr, int r_on_device, hipSt
     }
     st.R = rp;
     st.tiled = use_tiled();
+    const double t0 = now_ms();
+    st.stats = sj_stats{};
     if (st.tiled)
         rs_count_tiled(ix, rp, nr, s);
     else
         rs_count_perquery(ix, rp, nr, s);
     st.counted = true;
+    // statistics of the run: the queries as n, S's grid
+    sj_stats &r = st.stats;
+    r.n = nr;
+    r.d = ix.d;
+    r.key_bits = static_cast<uint32_t>(ix.key_bits);
+    r.cells = ix.ncells;
+    for (uint32_t j = 0; j < ix.d; ++j) r.grid_dims[j] = ix.grid.dims[j];
+    r.eps = ix.eps;
+    r.cell_width = ix.grid.w;
+    r.max_cell_points = ix.max_cell;
+    r.precision_used = SJ_FP64;
+    r.evals = st.evals;  // counted by the tiled kernel only
+    r.pairs = st.P;
+    r.max_row_pairs = st.max_len;
+    r.ms_count = now_ms() - t0;
+    note_run(r);
 }
 
 void rs_fill(sj_index &ix, uint32_t *pairs_dev, uint64_t cap, hipStream_t s) {
@@ -1349,10 +1402,14 @@ void rs_fill(sj_index &ix, uint32_t *pairs_dev, uint64_t cap, hipStream_t s) {
     if (cap < st.P)
         throw Error(SJ_ECAPACITY, "output buffer holds " + std::to_string(cap) + " pairs, the result has " +
                                       std::to_string(st.P));
+    const double t0 = now_ms();
     if (st.tiled)
         rs_fill_tiled(ix, pairs_dev, s);
     else
         rs_fill_perquery(ix, pairs_dev, s);
+    st.stats.ms_fill = now_ms() - t0;
+    st.stats.batches = 1;
+    note_run(st.stats);
 }
 
 }  // namespace

@@ -71,6 +71,35 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *total, T *lds) {
 // with a partner distance of 16 or more exchange registers within the lane,
 // shorter ones exchange with lane l ^ j of the same group. Every lane of the
 // wave must take part.
+// The value x of lane (lane ^ m). Partners inside the lane's 16-lane row
+// are DPP moves, plain VALU operations: quad permutations for m = 1, 2, 3,
+// the 8- and 16-lane mirrors for m = 7, 15, and for m = 4, 8 the row shift
+// towards the partner (by 4 or 8 lanes up or down). Any other m goes
+// through the LDS crossbar. Every lane of the wave must take part; m is a
+// constant after unrolling.
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x, int m) {
+    const int xi = static_cast<int>(x);
+    const uint32_t lane = static_cast<uint32_t>(lane_id());
+    switch (m) {
+        case 1: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(xi, 0xB1, 0xF, 0xF, true));  // [1,0,3,2]
+        case 2: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(xi, 0x4E, 0xF, 0xF, true));  // [2,3,0,1]
+        case 3: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(xi, 0x1B, 0xF, 0xF, true));  // [3,2,1,0]
+        case 4: {
+            const int up = __builtin_amdgcn_mov_dpp(xi, 0x104, 0xF, 0xF, true);  // row_shl:4, lane + 4
+            const int dn = __builtin_amdgcn_mov_dpp(xi, 0x114, 0xF, 0xF, true);  // row_shr:4, lane - 4
+            return static_cast<uint32_t>((lane & 4u) ? dn : up);
+        }
+        case 7: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(xi, 0x141, 0xF, 0xF, true));  // half mirror
+        case 8: {
+            const int up = __builtin_amdgcn_mov_dpp(xi, 0x108, 0xF, 0xF, true);  // row_shl:8, lane + 8
+            const int dn = __builtin_amdgcn_mov_dpp(xi, 0x118, 0xF, 0xF, true);  // row_shr:8, lane - 8
+            return static_cast<uint32_t>((lane & 8u) ? dn : up);
+        }
+        case 15: return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(xi, 0x140, 0xF, 0xF, true));  // mirror
+        default: return static_cast<uint32_t>(__shfl_xor(xi, m, 64));
+    }
+}
+
 __device__ __forceinline__ void group16_bitonic64(uint32_t (&v)[4]) {
     const uint32_t l = static_cast<uint32_t>(lane_id()) & 15u;
 #pragma unroll
@@ -94,7 +123,7 @@ __device__ __forceinline__ void group16_bitonic64(uint32_t (&v)[4]) {
             } else {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const uint32_t p = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v[k]), j, 16));
+                    const uint32_t p = lane_xor(v[k], j);
                     const uint32_t e = static_cast<uint32_t>(k) * 16 + l;
                     const bool asc = (e & static_cast<uint32_t>(kk)) == 0;
                     const bool lower = (l & static_cast<uint32_t>(j)) == 0;

@@ -163,3 +163,22 @@ def test_join_rs_nonfinite_and_far_queries(sj):
     assert not np.isin(got[:, 0], [5, 17, 29, 31, 40]).any()
     far = np.full((100, 3), 1e6)
     assert rs_pairs(sj, S, far, 2.5).shape[0] == 0
+
+
+def test_join_rs_run_statistics(sj):
+    """sj_last_run_stats after a two-set join: the query rows as n, the pairs
+    and longest row of the result, S's cells, and the tiled kernel's
+    distance evaluations (at least one per pair)."""
+    from paper_1803_04120_amd import _lib
+    S = datagen.uniform(6007, 3, seed=79)
+    R = datagen.uniform(2003, 3, seed=80)
+    want = ref.join_rs_numpy(R, S, 4.0)
+    with sj.Index(torch.from_numpy(S).cuda(), 4.0) as ix:
+        got = ix.join_rs(torch.from_numpy(R).cuda())
+        cells = ix.stats()["cells"]
+    st = _lib.last_run_stats()
+    assert st["n"] == R.shape[0] and st["d"] == 3
+    assert st["pairs"] == got.shape[0] == want.shape[0]
+    assert st["max_row_pairs"] == int(np.bincount(want[:, 0]).max())
+    assert st["cells"] == cells
+    assert st["evals"] >= st["pairs"] and st["batches"] == 1
