@@ -641,7 +641,7 @@ struct Scratch {
 
 void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t cap,
                bool unicomp_fill, uint32_t *out_j, uint32_t *pairs, Scratch &sc, hipStream_t s,
-               uint32_t *cols = nullptr) {
+               uint32_t *cols = nullptr, bool sort_rows = true) {
     const uint64_t n = ix.n;
     const int mode = unicomp_fill ? 1 : 0;
     const bool whole = (i0 == 0 && i1 == n);
@@ -710,6 +710,7 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
         ix.overflow_clear = false;
         sj::launch_join(a, ix.d, 0, sj::kFill, ix.band_used, s);
     }
+    if (!sort_rows) return;  // the rows stay in out_j (cell order) for the caller
     if (whole)
         sj::launch_rowsort_cells(ix.off_cell.ptr, ix.off_orig.ptr, ix.perm.ptr, n, out_j, pairs,
                                  ix.max_row, s, cols, ix.opts.sort_output != 0);
@@ -801,14 +802,29 @@ int join_batched_cells(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
     uint64_t maxbatch = 0;
     for (uint32_t b = 0; b < nb; ++b) maxbatch = std::max(maxbatch, boff[b + 1] - boff[b]);
     if (maxbatch > cap) throw Error(SJ_EDEVICE, "internal: a planned batch exceeds the capacity");
-    ix.stats.fill_unicomp = 0;  // every point writes its own row
-    const bool fused = tiled && use_fused_sort(ix.d);
+    // Where the unicomp fill is the faster one and the neighbour ids of the
+    // whole result (4 bytes per pair, half the pairs' size) fit in half the
+    // free device memory, every row is filled once, unicomp, in cell order,
+    // and each run only sorts its rows out of that table. Otherwise each run
+    // fills its own rows with the full search (unicomp's mirrored entries
+    // would land in other runs' rows). SJ_BATCH_FILL=whole|runs overrides.
+    bool whole_fill = false;
+    if (tiled && choose_unicomp_fill(ix)) {
+        size_t free_b = 0, total_b = 0;
+        whole_fill = hipMemGetInfo(&free_b, &total_b) == hipSuccess && 4 * P <= free_b / 2;
+    }
+    if (const char *e = std::getenv("SJ_BATCH_FILL")) {
+        if (std::strcmp(e, "runs") == 0) whole_fill = false;
+        if (std::strcmp(e, "whole") == 0) whole_fill = tiled && ix.opts.unicomp;
+    }
+    ix.stats.fill_unicomp = whole_fill ? 1u : 0u;  // else every point writes its own row
+    const bool fused = tiled && !whole_fill && use_fused_sort(ix.d);
     const uint32_t ns = fused ? fused_slot(ix) : 0;
     const int nsets = nb > 1 ? 2 : 1;
-    DevBuf<uint32_t> out_j[2], pairs[2], len_b[2];
+    DevBuf<uint32_t> out_j[2], pairs[2], len_b[2], out_all;
     DevBuf<uint64_t> off_b[2];
     for (int k = 0; k < nsets; ++k) {
-        out_j[k].reset(std::max<uint64_t>(1, maxbatch));
+        if (!whole_fill) out_j[k].reset(std::max<uint64_t>(1, maxbatch));
         pairs[k].reset(2 * std::max<uint64_t>(1, maxbatch));
         len_b[k].reset(n);
         off_b[k].reset(n + 1);
@@ -848,6 +864,12 @@ int join_batched_cells(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
     };
     ix.overflow.ensure(1);
     sj::launch_fill_u32(ix.overflow.ptr, 1, 0u, s);
+    ix.overflow_clear = true;
+    if (whole_fill) {
+        out_all.reset(P);
+        Scratch sc;
+        fill_rows(ix, 0, n, 0, P, true, out_all.ptr, nullptr, sc, s, nullptr, false);
+    }
     ix.overflow_clear = false;
     if (nsets > 1) {
         // the second stream starts after everything before on the caller's
@@ -869,7 +891,12 @@ int join_batched_cells(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
             a.out_base = boff[b];
             a.out_cap = bp;
             a.overflow = ix.overflow.ptr;
-            if (tiled) {
+            if (whole_fill) {
+                // the run's rows from the whole table (rows in cell order at
+                // off_cell), sorted into the run's buffer
+                sj::launch_rowsort_range(ix.off_cell.ptr, r0, r1, 0, off_b[k].ptr, ix.perm.ptr, out_all.ptr,
+                                         pairs[k].ptr, ix.max_row, 0u, st, nullptr, ix.opts.sort_output != 0);
+            } else if (tiled) {
                 sj::TileArgs t = tile_args(ix);
                 t.chunk0 = unit[b];
                 t.chunk_end = unit[b + 1];
@@ -890,9 +917,10 @@ int join_batched_cells(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
                 a.nq = static_cast<uint32_t>(r1 - r0);
                 sj::launch_join(a, ix.d, 0, sj::kFill, ix.band_used, st);
             }
-            sj::launch_rowsort_range(ix.off_cell.ptr, r0, r1, boff[b], off_b[k].ptr, ix.perm.ptr, out_j[k].ptr,
-                                     pairs[k].ptr, ix.max_row, fused ? 64u : 0u, st, nullptr,
-                                     ix.opts.sort_output != 0);
+            if (!whole_fill)
+                sj::launch_rowsort_range(ix.off_cell.ptr, r0, r1, boff[b], off_b[k].ptr, ix.perm.ptr, out_j[k].ptr,
+                                         pairs[k].ptr, ix.max_row, fused ? 64u : 0u, st, nullptr,
+                                         ix.opts.sort_output != 0);
         }
         SJ_HIP(hipEventRecord(ev[k], st));
         if (b >= 1) deliver(b - 1);

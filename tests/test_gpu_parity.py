@@ -395,9 +395,14 @@ def test_unicomp_evaluation_counts(sj, join_kernel, kind, d, eps, monkeypatch):
 
 # ---------------------------------------------------------------- batching
 @pytest.mark.parametrize("cap,minb", [(0, 3), (5000, 1), (20000, 3), (777, 1)])
-@pytest.mark.parametrize("uni", [True, False])
-def test_batches_partition_the_result(sj, cap, minb, uni):
-    _say(f"batches cap={cap} min={minb} uni={uni}")
+@pytest.mark.parametrize("uni,fill", [(True, None), (True, "whole"), (True, "runs"), (False, None)])
+def test_batches_partition_the_result(sj, cap, minb, uni, fill, monkeypatch):
+    """Runs partition the result, each sorted by (i, j), whether each run
+    fills its own rows (SJ_BATCH_FILL=runs) or one unicomp fill of every row
+    precedes the runs' sorts (whole)."""
+    _say(f"batches cap={cap} min={minb} uni={uni} fill={fill}")
+    if fill:
+        monkeypatch.setenv("SJ_BATCH_FILL", fill)
     pts = datagen.clustered(12000, 2, seed=21)
     eps = 0.4
     want = ref.pairs(pts, eps)
@@ -425,6 +430,21 @@ def test_batches_partition_the_result(sj, cap, minb, uni):
             assert np.all(np.diff(key) > 0), "a run is not sorted by (i, j)"
             assert set(np.unique(run[:, 0])) <= set(perm[r0:r1].tolist())
         assert_same(g[np.lexsort((g[:, 1], g[:, 0]))], want, f"batched cap={cap}")
+
+
+@pytest.mark.parametrize("d,eps", [(4, 14.0), (5, 20.0)])
+def test_batches_whole_fill_in_high_d(sj, d, eps):
+    """From 4-D on the batched join fills every row once with unicomp and
+    sorts each run out of that table (the default when it fits in memory):
+    the runs, merged, are the oracle's pairs."""
+    _say(f"batches whole fill d={d}")
+    pts = datagen.uniform(7001, d, seed=22 + d)
+    want = ref.pairs(pts, eps)
+    with sj.Index(torch.from_numpy(pts).cuda(), eps) as ix:
+        got, info = ix.join_batched(unicomp=True, batch_capacity_pairs=max(want.shape[0] // 5, 4096), min_batches=3)
+        assert ix.stats()["fill_unicomp"] == 1 and len(info) >= 3
+    g = got.cpu().numpy().astype(np.int64)
+    assert_same(g[np.lexsort((g[:, 1], g[:, 0]))], want, f"batched whole fill d={d}")
 
 
 def test_convenience_host_and_device_output(sj):
