@@ -84,7 +84,8 @@ typedef struct sj_stats {
     uint32_t precision_used;    /* SJ_FP64 or SJ_FP32_BAND actually used in the last join */
     uint64_t ranges;            /* candidate point ranges of the last join's cell search */
     uint64_t evals;             /* distance evaluations of the last count pass */
-    uint64_t band_rechecks;     /* FP64 re-decisions in the last count pass (FP32 path) */
+    uint64_t band_rechecks;     /* candidates of the last count pass re-decided by the exact FP64 sum: from the
+                                   FP32 band, or (grid-row kernel, 4-D and up) from the FP64 fused-square band */
     uint64_t pairs;             /* pairs of the last join */
     uint64_t max_row_pairs;     /* longest result row of the last join */
     uint32_t batches;           /* batches of the last join */

@@ -53,6 +53,14 @@ struct TileSize {
     static constexpr int value = half < 64 ? 64 : half;  // at least one candidate per lane
 };
 
+// From this many dimensions on, the FP64 pair test takes the fused-square
+// filter (2 operations per dimension instead of 3; the exact left-to-right
+// sum only for candidates whose filter value falls in the band around eps^2).
+#ifndef SJ_FUSED_MIN_D
+#define SJ_FUSED_MIN_D 4
+#endif
+constexpr int kFusedMinD = SJ_FUSED_MIN_D;
+
 __device__ __forceinline__ bool t_occupied(const TileArgs &t, uint32_t j, uint32_t c) {
     if (!t.masks) return true;
     return (t.masks[t.mask_off[j] + (c >> 5)] >> (c & 31u)) & 1u;
@@ -85,6 +93,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     __shared__ uint32_t sr_all[kWaves][NS > 0 ? 64 * kRowStride : 1];
     __shared__ unsigned long long sm_all[kWaves][kMirAgg ? TS : 1];
     __shared__ uint32_t sp_all[kWaves][kMirAgg ? 64 : 1];
+    __shared__ uint32_t sb_all[kWaves];  // set when a candidate of the tile fell in the fused-square band
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
     CT *sx = reinterpret_cast<CT *>(sx_all[wave]);
@@ -96,6 +105,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     uint32_t *srow = sr_all[wave] + lane * (NS > 0 ? kRowStride : 0);
     unsigned long long *smask = sm_all[wave];
     uint32_t *sperm = sp_all[wave];  // the chunk's point ids by lane
+    uint32_t *sband = &sb_all[wave];
 
     uint32_t own = 0, evals = 0, rechecks = 0;
     // chunks go to workgroups in launch order, which the hardware deals out
@@ -120,6 +130,9 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         uint32_t perm_p = 0;
         uint32_t row_len = 0;  // fused fill: the row length from the count pass
         uint64_t row_dst = 0;  // fused fill: offset of the row of p in the result
+        uint32_t n_own = 0;    // other fills: entries of p's own evaluation (count pass)
+        uint32_t *wrow = a.out_j;
+        uint32_t wlim = 0;
         if (active) {
 #pragma unroll
             for (int j = 0; j < D; ++j) {
@@ -135,9 +148,17 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 my_row = a.offc[p] - a.out_base;
                 perm_p = a.permq[p];
                 if (NS > 0) row_len = static_cast<uint32_t>(a.offc[p + 1] - a.offc[p]);
+                if (NS == 0) {
+                    n_own = kUni ? a.own_cnt[p] : static_cast<uint32_t>(a.offc[p + 1] - a.offc[p]);
+                    if (n_own > 0 && my_row + n_own <= a.out_cap) {
+                        wrow = a.out_j + my_row;
+                        wlim = n_own - 1;
+                    }
+                }
             }
         }
         if (kMirAgg) sperm[lane] = perm_p;  // read after the first tile's barrier
+        if (!kBand && D >= kFusedMinD) *sband = 0u;
         // fused fill: rows that fit stay in the lane's LDS slot
         const bool row_in_lds = NS > 0 && row_len <= static_cast<uint32_t>(NS);
         // chunk geometry (uniform)
@@ -164,6 +185,23 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                     acc = __dadd_rn(acc, __dmul_rn(d0, d0));
                 }
                 return acc <= a.eps2;
+            } else if (D >= kFusedMinD) {
+                // fused-square filter: the sum by fused multiply-adds is
+                // within 2 gamma_d of the definition's left-to-right sum, so
+                // outside [flo, fhi] it decides as the definition does; a
+                // candidate inside is left out here and noted, and the tile
+                // is passed again for those candidates (test_band)
+                double f = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const double d0 = __dsub_rn(xp[j], static_cast<double>(sx[i * D + j]));
+                    f = j == 0 ? __dmul_rn(d0, d0) : __fma_rn(d0, d0, f);
+                }
+                const bool in = f < a.flo;
+                // a uniform branch on the compare masks, to a store only (no
+                // value carried through the loop)
+                if (__builtin_amdgcn_ballot_w64(f <= a.fhi) & ~__builtin_amdgcn_ballot_w64(in)) *sband = 1u;
+                return in;
             } else {
                 double acc = 0.0;
 #pragma unroll
@@ -173,6 +211,21 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 }
                 return acc <= a.eps2;
             }
+        };
+        // second pass over a tile with band candidates: those candidates
+        // only, decided by the definition's left-to-right sum
+        auto test_band = [&](uint32_t i) -> bool {
+            double dv[D];
+            double f = 0.0, acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                dv[j] = __dsub_rn(xp[j], static_cast<double>(sx[i * D + j]));
+                f = j == 0 ? __dmul_rn(dv[j], dv[j]) : __fma_rn(dv[j], dv[j], f);
+                acc = __dadd_rn(acc, __dmul_rn(dv[j], dv[j]));
+            }
+            const bool band = !(f < a.flo) && f <= a.fhi;
+            rechecks += band ? 1u : 0u;
+            return band && acc <= a.eps2;
         };
         // One tested candidate (staged index i, point q, id its point id from
         // the staged ids, h the test result). The fused fill stores every
@@ -195,11 +248,10 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 }
                 own += h ? 1u : 0u;
             } else if (h) {
-                const uint64_t at = my_row + own;
-                if (at < a.out_cap)
-                    a.out_j[at] = id;
-                else
-                    atomicOr(a.overflow, 1u);
+                // inside the row's own entries as the count pass sized them
+                // (a row that finds more rewrites its last entry; the
+                // disagreement is flagged at the end of the chunk)
+                wrow[own < wlim ? own : wlim] = id;
                 ++own;
                 if (kMirAgg && mirror) atomicOr(&smask[i], 1ull << lane);
             }
@@ -210,9 +262,16 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         // registers of two waves per SIMD; the count takes one branch per
         // step for the rare mirrored hits)
         constexpr int kUnroll = D <= 3 ? 4 : 2;
-        auto run = [&](uint32_t T0, uint32_t i0, uint32_t i1) {
+        auto run = [&](auto redo, uint32_t T0, uint32_t i0, uint32_t i1) {
+            constexpr bool kRedo = decltype(redo)::value;
+            auto tst = [&](uint32_t i, uint32_t q) -> bool {
+                if constexpr (kRedo)
+                    return test_band(i);
+                else
+                    return test(i, q);
+            };
             if (i0 >= i1) return;
-            evals += i1 - i0;
+            if (!kRedo) evals += i1 - i0;
             uint32_t i = i0;
             for (; i + kUnroll <= i1; i += kUnroll) {
                 bool h[kUnroll];
@@ -220,7 +279,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) id[u] = kPerm ? saux[i + u] : 0u;
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) h[u] = test(i + u, T0 + i + u);
+                for (int u = 0; u < kUnroll; ++u) h[u] = tst(i + u, T0 + i + u);
                 if (kMode == kCount) {
                     bool any = false;
 #pragma unroll
@@ -240,10 +299,10 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             }
             for (; i < i1; ++i) {
                 const uint32_t id = kPerm ? saux[i] : 0u;
-                emit(test(i, T0 + i), i, T0 + i, id, kUni && T0 + i != p);
+                emit(tst(i, T0 + i), i, T0 + i, id, kUni && T0 + i != p);
             }
         };
-        auto evaluate_tile = [&](uint32_t T0, uint32_t len, bool own_row) {
+        auto evaluate_tile = [&](auto redo, uint32_t T0, uint32_t len, bool own_row) {
             // the sub-cells within w of p's own in dimension 0 (S of them on
             // each side: a neighbour differs by at most eps <= w); unicomp's
             // own row with an even cell: the own cell's sub-cells only
@@ -271,10 +330,10 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 // cell, p), a contiguous run of the tile
                 const uint32_t s_lo = p_cell_start > T0 ? (p_cell_start - T0 < len ? p_cell_start - T0 : len) : 0;
                 const uint32_t s_hi = p > T0 ? (p - T0 < len ? p - T0 : len) : 0;
-                run(T0, i_lo, i_hi < s_lo ? i_hi : s_lo);
-                run(T0, i_lo > s_hi ? i_lo : s_hi, i_hi);
+                run(redo, T0, i_lo, i_hi < s_lo ? i_hi : s_lo);
+                run(redo, T0, i_lo > s_hi ? i_lo : s_hi, i_hi);
             } else {
-                run(T0, i_lo, i_hi);
+                run(redo, T0, i_lo, i_hi);
             }
         };
         // Row index of an offset vector o (o_j in {-1,0,1}, j = 1..d-1):
@@ -385,7 +444,13 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             for (uint32_t i = len + lane; i < static_cast<uint32_t>(TS); i += 64) scx[i] = ~0u;
             const Tile nxt = advance(cur);
             wave_sync_lds();
-            if (active) evaluate_tile(cur.T0, len, cur.own_row);
+            if (active) evaluate_tile(std::false_type{}, cur.T0, len, cur.own_row);
+            if (!kBand && D >= kFusedMinD) {
+                if (__builtin_amdgcn_readfirstlane(*sband)) {
+                    *sband = 0u;
+                    if (active) evaluate_tile(std::true_type{}, cur.T0, len, cur.own_row);
+                }
+            }
             if (kAgg) {
                 // one global add per candidate that collected mirrored hits
                 wave_sync_lds();
@@ -419,6 +484,8 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             cur = nxt;
         }
         if (kMode == kCount && active) a.own_cnt[p] = own;
+        if (kMode == kFill && NS == 0 && active && (own != n_own || my_row + n_own > a.out_cap))
+            atomicOr(a.overflow, 1u);  // count and fill disagree, or the row is past the buffer
         if (kMode == kFill && NS > 0 && !kUni) {
             // the row of p is complete: sort it in registers; a row longer
             // than the LDS slot is in out_j for the row-sort kernels
@@ -529,7 +596,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     }
     if (kMode == kCount) {
         add_counter(a.evals, evals);
-        if (kBand) add_counter(a.band_rechecks, rechecks);
+        if (kBand || D >= kFusedMinD) add_counter(a.band_rechecks, rechecks);
     }
 }
 

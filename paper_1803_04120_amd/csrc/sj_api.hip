@@ -95,6 +95,34 @@ int guarded(hipStream_t s, F &&f) {
 std::mutex g_out_mu;
 std::map<void *, bool> g_out_bufs;  // ptr -> on device
 
+// Band of the FP64 fused-square filter. With d_j the rounded differences and
+// T = sum d_j^2 exactly, both the definition's sum S (rounded squares added
+// left to right) and the fused sum F (F_1 = fl(d_1^2), F_j = fma(d_j, d_j,
+// F_{j-1})) put at most d roundings on every term, so |S - T| and |F - T|
+// are at most gamma_d T (gamma_d = d u / (1 - d u), u = 2^-53) and
+// |F - S| <= 2 gamma_d / (1 - gamma_d) F. F < eps2 (1 - delta) then implies
+// S < eps2 and F > eps2 (1 + delta) implies S > eps2 for any
+// delta >= 2 gamma_d / (1 - gamma_d) (1.8e-15 at d = 8); delta = 2^-45 is
+// 15 times that at d = 8, twice at d = 64. The bounds hold without underflow; for eps2 below 2^-900 the
+// absolute error of subnormal results (a few 2^-1074) is no longer small
+// next to delta eps2, and for eps2 above 2^1000 F may overflow: then every
+// finite F goes to the exact sum. eps2 = 0: F > 0 exactly when S > 0
+// (rounding is monotone and each term enters both sums the same way while
+// the partial sums are zero), so lo = hi = 0 is exact.
+void fused_band(double eps2, double *lo, double *hi) {
+    const double delta = std::ldexp(1.0, -45);
+    static_assert(sj::kMaxDim <= 64, "delta covers 2 gamma_d / (1 - gamma_d) up to d = 64");
+    if (eps2 == 0.0) {
+        *lo = *hi = 0.0;
+    } else if (eps2 >= std::ldexp(1.0, -900) && eps2 <= std::ldexp(1.0, 1000)) {
+        *lo = eps2 * (1.0 - delta);
+        *hi = eps2 * (1.0 + delta);
+    } else {
+        *lo = -1.0;
+        *hi = std::numeric_limits<double>::infinity();
+    }
+}
+
 // FP32 pre-test thresholds (the reading documented with the band kernel):
 // gamma(k, u) = k u / (1 - k u); tau = X 2^-24 (1 + 2^-28) + 2^-126;
 // Delta(E) = 4 tau sqrt(dE) + 4 d tau^2 + gamma(d+2, 2^-24)(sqrt E + 2 tau sqrt d)^2
@@ -541,6 +569,7 @@ sj::JoinArgs base_args(sj_index &ix, int mode) {
     a.eps2 = ix.eps * ix.eps;
     a.lo = ix.lo;
     a.hi = ix.hi;
+    fused_band(a.eps2, &a.flo, &a.fhi);
     a.own_cnt = ix.own_cnt.ptr;
     a.in_cnt = ix.in_cnt.ptr;
     a.offc = nullptr;

@@ -59,6 +59,9 @@ struct JoinArgs {
     uint32_t qbase;           // first query position when qlist is null
     double eps2;
     float lo, hi;
+    // fused-square filter band around eps2: a fused multiply-add sum below
+    // flo is a pair, above fhi (or NaN) is not, else the exact sum decides
+    double flo, fhi;
     // count outputs
     uint32_t *own_cnt;
     uint32_t *in_cnt;

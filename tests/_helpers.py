@@ -61,3 +61,75 @@ def pairs_from_unordered(n: int, unordered) -> np.ndarray:
         out.append((i, j))
         out.append((j, i))
     return sorted_pairs(out)
+
+
+def ordered_square_sum(dv):
+    """sum_j dv_j^2 as the pair predicate defines it: each square rounded,
+    then added left to right with one rounding per addition (Python floats
+    are IEEE doubles and are never contracted)."""
+    s = 0.0
+    for v in dv:
+        s = s + v * v
+    return s
+
+
+def fused_square_sum(dv):
+    """sum_j dv_j^2 by fused multiply-adds: F_1 = fl(dv_1^2), then
+    F_j = fl(dv_j^2 + F_{j-1}) with one rounding each (exact rational
+    arithmetic, then a correctly rounded conversion to double)."""
+    from fractions import Fraction
+    f = float(Fraction(dv[0]) * Fraction(dv[0]))
+    for v in dv[1:]:
+        f = float(Fraction(v) * Fraction(v) + Fraction(f))
+    return f
+
+
+def straddling_points(d: int, eps: float, count: int, seed: int):
+    """Pairs of points whose squared distance the two sums above decide
+    differently against eps^2 (one <= eps^2 < the other), plus points at
+    exactly eps along an axis. Base points x lie in [4, 64)^d and their
+    partners y within eps, so x - y is exact (Sterbenz) and the rounded
+    differences are the chosen ones. Returns (points, number of straddling
+    pairs)."""
+    g = np.random.default_rng(seed)
+    eps2 = eps * eps
+    pts = []
+    found = 0
+    for _ in range(400 * count):
+        if found >= count:
+            break
+        x = g.uniform(4.0, 64.0, size=d)
+        v = g.normal(size=d)
+        v *= eps / np.linalg.norm(v)
+        y = x + v
+        # step y_0 by its ulp around the point where the ordered sum crosses
+        # eps^2 (vectorised), then test the neighbours of the crossing
+        ulp = np.spacing(y[0])
+        k = np.arange(-48, 49, dtype=np.float64)
+        ys0 = y[0] + k * ulp
+        dv = x[None, :] - np.concatenate([ys0[:, None], np.repeat(y[None, 1:], k.size, 0)], axis=1)
+        s = np.zeros(k.size)
+        for j in range(d):
+            s = s + dv[:, j] * dv[:, j]
+        inside = s <= eps2
+        flips = np.nonzero(inside[1:] != inside[:-1])[0]
+        for f in flips[:1]:
+            for idx in range(max(0, f - 2), min(k.size, f + 4)):
+                row = [float(t) for t in dv[idx]]
+                S = ordered_square_sum(row)
+                F = fused_square_sum(row)
+                if (S <= eps2) != (F <= eps2):
+                    yy = y.copy()
+                    yy[0] = ys0[idx]
+                    pts.extend([x, yy])
+                    found += 1
+                    break
+    # axis-aligned partners at exactly eps and one ulp beyond
+    for _ in range(count):
+        x = g.uniform(4.0, 64.0, size=d)
+        a = int(g.integers(d))
+        for off in (eps, np.nextafter(eps, 1.0)):
+            y = x.copy()
+            y[a] = x[a] + off
+            pts.extend([x.copy(), y])
+    return np.ascontiguousarray(np.array(pts, dtype=np.float64)), found

@@ -13,7 +13,7 @@ import pytest
 from oracle import grid as og
 from oracle import reference as ref
 from paper_1803_04120_amd import datagen
-from tests._helpers import golden, worked_example_points
+from tests._helpers import golden, straddling_points, worked_example_points
 
 pytestmark = pytest.mark.gpu
 
@@ -188,6 +188,24 @@ def test_lattice_boundaries(sj, d):
             for prec in ("fp64", "fp32_band"):
                 got = gpu_pairs(sj, pts * scale, 1.0 * scale, unicomp=uni, precision=prec)
                 assert_same(got, want, f"lattice d={d} scale={scale} uni={uni} {prec}")
+
+
+@pytest.mark.parametrize("d", [3, 4, 5, 6, 7, 8])
+def test_fused_filter_straddling_pairs(sj, d):
+    """Pairs whose squared distance a fused multiply-add sum and the
+    predicate's left-to-right sum put on different sides of eps^2: the FP64
+    grid-row kernel's fused-square filter (4-D and up) must send them to the
+    exact sum and count them as re-decisions."""
+    _say(f"fused-filter straddling pairs d={d}")
+    eps = 0.7
+    pts, found = straddling_points(d, eps, 40, seed=d)
+    assert found == 40
+    want = ref.pairs(pts, eps)
+    for uni in (True, False):
+        got = gpu_pairs(sj, pts, eps, unicomp=uni, precision="fp64")
+        assert_same(got, want, f"straddling d={d} uni={uni}")
+        if d >= 4:  # the filter's dimensions (below them the exact sum runs directly)
+            assert sj.last_run_stats()["band_rechecks"] >= found
 
 
 def test_pairs_at_exact_eps_and_next_float(sj):

@@ -8,6 +8,7 @@ import pytest
 
 from oracle import reference as ref
 from paper_1803_04120_amd import datagen
+from tests._helpers import straddling_points
 
 pytestmark = pytest.mark.gpu
 
@@ -52,6 +53,20 @@ def test_join_rs_matches_oracle(sj, kind, d, ns, nr, eps):
     want = ref.join_rs_numpy(R, S, eps)
     assert want.shape[0] > nr // 4  # real neighbours
     assert_same(rs_pairs(sj, S, R, eps), want, f"R x S {kind} d={d}")
+
+
+@pytest.mark.parametrize("d", [4, 6, 8])
+def test_join_rs_straddling_pairs(sj, d):
+    """Query/point pairs that a fused multiply-add sum and the predicate's
+    left-to-right sum decide differently: the two-set join's fused-square
+    filter must hand them to the exact sum."""
+    _say(f"straddling pairs d={d}")
+    eps = 0.7
+    pts, found = straddling_points(d, eps, 40, seed=50 + d)
+    assert found == 40
+    R = np.ascontiguousarray(pts[0::2])
+    S = np.ascontiguousarray(pts[1::2])
+    assert_same(rs_pairs(sj, S, R, eps), ref.join_rs_numpy(R, S, eps), f"straddling R x S d={d}")
 
 
 def test_join_rs_queries_outside_the_index_box(sj):
