@@ -83,6 +83,10 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     // mask in LDS, its mirrored entries written after the tile with one
     // global slot reservation per candidate
     constexpr bool kMirAgg = (kMode == kFill) && kUni;
+    // hit bits: recorded by the count pass and read back by the fill pass of
+    // the FP64 search from 4-D on (the fill then stages no coordinates and
+    // tests nothing)
+    constexpr bool kBits = !kBand && NS == 0 && D >= kFusedMinD && D >= static_cast<int>(kHitBitsMinDim);
     // staged coordinates; the fused fill reuses the slot after the last
     // tile for its write-out table (row destination, row id, length)
     constexpr size_t kStageBytes = sizeof(CT) * TS * D;
@@ -114,6 +118,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     const uint32_t chunk = t.chunk0 + blockIdx.x * kWaves + wave;
     const uint32_t nch = *t.nchunks_dev;
     if (chunk < (t.chunk_end < nch ? t.chunk_end : nch)) {  // uniform across the wave
+        const bool bits_on = kBits && t.bits != nullptr;
         // segment table of the chunk, 64 rows per register load; the first
         // load is issued before anything else (it needs only the chunk index)
         const uint2 *segs = t.segs + static_cast<size_t>(chunk) * t.rows_per_chunk;
@@ -262,8 +267,22 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         // registers of two waves per SIMD; the count takes one branch per
         // step for the rare mirrored hits)
         constexpr int kUnroll = D <= 3 ? 4 : 2;
-        auto run = [&](auto redo, uint32_t T0, uint32_t i0, uint32_t i1) {
+        // fill with hit bits: the set bits of the run's words, in order
+        auto replay = [&](uint32_t T0, uint32_t i0, uint32_t i1, uint64_t wb) {
+            const uint32_t ns = i1 - i0;
+            for (uint32_t k = 0; 32 * k < ns; ++k) {
+                uint32_t w = t.bits[(wb + k) * 64 + static_cast<uint64_t>(lane)];
+                while (w) {
+                    const uint32_t b = static_cast<uint32_t>(__builtin_clz(w));
+                    w &= ~(0x80000000u >> b);
+                    const uint32_t i = i0 + 32 * k + b;
+                    emit(true, i, T0 + i, saux[i], kUni && T0 + i != p);
+                }
+            }
+        };
+        auto run = [&](auto redo, auto with_bits, uint32_t T0, uint32_t i0, uint32_t i1, uint64_t wb) {
             constexpr bool kRedo = decltype(redo)::value;
+            constexpr bool kB = kBits && decltype(with_bits)::value;
             auto tst = [&](uint32_t i, uint32_t q) -> bool {
                 if constexpr (kRedo)
                     return test_band(i);
@@ -271,7 +290,17 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                     return test(i, q);
             };
             if (i0 >= i1) return;
+            if (kMode == kFill && kB) {
+                replay(T0, i0, i1, wb);
+                return;
+            }
             if (!kRedo) evals += i1 - i0;
+            // count with hit bits: the run's outcomes shifted into hw, a word
+            // stored each 32 candidates (ts counts the wave's steps: every
+            // lane still in the loop has taken as many)
+            constexpr bool rec = kMode == kCount && !kRedo && kB;
+            uint32_t hw = 0, ts = 0;
+            uint32_t *const wrow_bits = kB ? t.bits + wb * 64 + static_cast<uint64_t>(lane) : nullptr;
             uint32_t i = i0;
             for (; i + kUnroll <= i1; i += kUnroll) {
                 bool h[kUnroll];
@@ -280,11 +309,29 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 for (int u = 0; u < kUnroll; ++u) id[u] = kPerm ? saux[i + u] : 0u;
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) h[u] = tst(i + u, T0 + i + u);
+                if (rec) {
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u) hw = (hw << 1) | (h[u] ? 1u : 0u);
+                    ts += kUnroll;
+                    if ((ts & 31u) == 0u) {
+                        wrow_bits[static_cast<uint64_t>((ts >> 5) - 1) * 64] = hw;
+                        own += static_cast<uint32_t>(__popc(hw));
+                        hw = 0;
+                    }
+                }
+                if (kMode == kCount && kRedo && kB) {
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u)
+                        if (h[u]) {
+                            const uint32_t sk = i + u - i0;
+                            atomicOr(wrow_bits + static_cast<uint64_t>(sk >> 5) * 64, 0x80000000u >> (sk & 31u));
+                        }
+                }
                 if (kMode == kCount) {
                     bool any = false;
 #pragma unroll
                     for (int u = 0; u < kUnroll; ++u) {
-                        own += h[u] ? 1u : 0u;
+                        if (!rec) own += h[u] ? 1u : 0u;  // recorded: counted per word
                         any = any || h[u];
                     }
                     if (kUni && any) {
@@ -299,10 +346,38 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             }
             for (; i < i1; ++i) {
                 const uint32_t id = kPerm ? saux[i] : 0u;
-                emit(tst(i, T0 + i), i, T0 + i, id, kUni && T0 + i != p);
+                const bool h = tst(i, T0 + i);
+                if (rec) {
+                    // own hits counted with the word below
+                    hw = (hw << 1) | (h ? 1u : 0u);
+                    if (kUni && h && T0 + i != p) atomicAdd(&saux[i], 1u);
+                    continue;
+                }
+                if (kMode == kCount && kRedo && kB && h) {
+                    const uint32_t sk = i - i0;
+                    atomicOr(wrow_bits + static_cast<uint64_t>(sk >> 5) * 64, 0x80000000u >> (sk & 31u));
+                }
+                emit(h, i, T0 + i, id, kUni && T0 + i != p);
+            }
+            if (rec) {
+                const uint32_t ns = i1 - i0, r = ns & 31u;
+                if (r) {
+                    wrow_bits[static_cast<uint64_t>(ns >> 5) * 64] = hw << (32u - r);
+                    own += static_cast<uint32_t>(__popc(hw));
+                }
             }
         };
-        auto evaluate_tile = [&](auto redo, uint32_t T0, uint32_t len, bool own_row) {
+        // the run with or without hit bits, chosen once per run (uniform)
+        auto run_sel = [&](auto redo, uint32_t T0, uint32_t i0, uint32_t i1, uint64_t wb) {
+            if constexpr (kBits) {
+                if (bits_on) {
+                    run(redo, std::true_type{}, T0, i0, i1, wb);
+                    return;
+                }
+            }
+            run(redo, std::false_type{}, T0, i0, i1, wb);
+        };
+        auto evaluate_tile = [&](auto redo, uint32_t T0, uint32_t len, bool own_row, uint64_t wb) {
             // the sub-cells within w of p's own in dimension 0 (S of them on
             // each side: a neighbour differs by at most eps <= w); unicomp's
             // own row with an even cell: the own cell's sub-cells only
@@ -330,10 +405,10 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 // cell, p), a contiguous run of the tile
                 const uint32_t s_lo = p_cell_start > T0 ? (p_cell_start - T0 < len ? p_cell_start - T0 : len) : 0;
                 const uint32_t s_hi = p > T0 ? (p - T0 < len ? p - T0 : len) : 0;
-                run(redo, T0, i_lo, i_hi < s_lo ? i_hi : s_lo);
-                run(redo, T0, i_lo > s_hi ? i_lo : s_hi, i_hi);
+                run_sel(redo, T0, i_lo, i_hi < s_lo ? i_hi : s_lo, wb);
+                run_sel(redo, T0, i_lo > s_hi ? i_lo : s_hi, i_hi, wb + (len + 31) / 32);
             } else {
-                run(redo, T0, i_lo, i_hi);
+                run_sel(redo, T0, i_lo, i_hi, wb);
             }
         };
         // Row index of an offset vector o (o_j in {-1,0,1}, j = 1..d-1):
@@ -422,8 +497,13 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         // fused fill: the row's place in the result (needs perm_p; used at
         // the end)
         if (NS > 0 && active) row_dst = a.off_orig[perm_p];
+        // hit bits: the chunk's next free word row (uniform); a tile takes
+        // ceil(len / 32) word rows per run (two runs in unicomp's own row)
+        uint64_t wcur = bits_on ? t.cbase[chunk] : 0;
         while (cur.valid) {
             const uint32_t len = (cur.P1 - cur.T0) < static_cast<uint32_t>(TS) ? (cur.P1 - cur.T0) : TS;
+            const uint64_t wb = wcur;
+            wcur += static_cast<uint64_t>((len + 31) / 32) * ((kUni && cur.own_row) ? 2u : 1u);
             wave_sync_lds();
             // stage the tile straight from memory. Holding the next tile in
             // registers while this one is evaluated was measured: no faster
@@ -432,10 +512,12 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             // (the registers cost waves per SIMD).
             for (uint32_t i = lane; i < len; i += 64) {
                 const size_t q = cur.T0 + i;
+                if (!(kMode == kFill && bits_on)) {
 #pragma unroll
-                for (int j = 0; j < D; ++j)
-                    sx[i * D + j] = kBand ? static_cast<CT>(a.Y[static_cast<size_t>(j) * a.n + q])
-                                          : static_cast<CT>(a.X[static_cast<size_t>(j) * a.n + q]);
+                    for (int j = 0; j < D; ++j)
+                        sx[i * D + j] = kBand ? static_cast<CT>(a.Y[static_cast<size_t>(j) * a.n + q])
+                                              : static_cast<CT>(a.X[static_cast<size_t>(j) * a.n + q]);
+                }
                 scx[i] = t.cx[q];
                 if (kAgg) saux[i] = 0;
                 if (kPerm) saux[i] = a.perm[q];
@@ -444,11 +526,11 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             for (uint32_t i = len + lane; i < static_cast<uint32_t>(TS); i += 64) scx[i] = ~0u;
             const Tile nxt = advance(cur);
             wave_sync_lds();
-            if (active) evaluate_tile(std::false_type{}, cur.T0, len, cur.own_row);
-            if (!kBand && D >= kFusedMinD) {
+            if (active) evaluate_tile(std::false_type{}, cur.T0, len, cur.own_row, wb);
+            if (!kBand && D >= kFusedMinD && !(kMode == kFill && bits_on)) {
                 if (__builtin_amdgcn_readfirstlane(*sband)) {
                     *sband = 0u;
-                    if (active) evaluate_tile(std::true_type{}, cur.T0, len, cur.own_row);
+                    if (active) evaluate_tile(std::true_type{}, cur.T0, len, cur.own_row, wb);
                 }
             }
             if (kAgg) {
@@ -719,6 +801,46 @@ __global__ __launch_bounds__(kThreads) void k_chunk_segments(TileArgs t, const u
     segs[idx] = sg;
 }
 
+// Word rows of hit bits each chunk's count pass takes: for every candidate
+// row the chunk visits (all rows; unicomp: its own row and the rows of the
+// blocks k >= 1 whose dimension-k coordinate is odd), ceil(segment / 32) per
+// run -- a tile of len candidates takes ceil(len / 32) and the tiles of a
+// segment are multiples of 32 but the last -- twice in unicomp's own row
+// (the triangle's two runs). One thread per chunk; slot nslots - 1 (past the
+// chunks) gets 0, so that the exclusive scan ends in the total. *big is
+// set when a chunk needs 2^32 - 1 or more.
+__global__ __launch_bounds__(kThreads) void k_chunk_words(TileArgs t, const uint32_t *__restrict__ cell_of,
+                                                           uint32_t d, int unicomp, uint32_t nslots,
+                                                           uint32_t *__restrict__ cwords, uint32_t *__restrict__ big) {
+    const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= nslots) return;
+    const uint32_t nch = *t.nchunks_dev;
+    uint64_t w = 0;
+    if (c < nch && c + 1 < nslots) {
+        const uint2 ch = t.chunks[c];
+        const uint32_t hf = cell_of[ch.x];
+        uint32_t odd = 0;
+        for (uint32_t j = 1; j < d; ++j) odd |= (t.coords[static_cast<size_t>(hf) * d + j] & 1u) << j;
+        for (uint32_t r = 0; r < t.rows_per_chunk; ++r) {
+            const uint2 sg = t.segs[static_cast<size_t>(c) * t.rows_per_chunk + r];
+            if (sg.x >= sg.y) continue;
+            uint32_t rr = r, top = 0;
+            for (uint32_t j = 1; j < d; ++j) {
+                if (rr % 3 != 1) top = j;
+                rr /= 3;
+            }
+            const bool own = top == 0;
+            if (unicomp && !own && !((odd >> top) & 1u)) continue;
+            w += static_cast<uint64_t>((sg.y - sg.x + 31) / 32) * ((unicomp && own) ? 2u : 1u);
+        }
+    }
+    if (w >= 0xffffffffull) {
+        atomicOr(big, 1u);
+        w = 0;
+    }
+    cwords[c] = static_cast<uint32_t>(w);
+}
+
 __global__ void k_zero_word(uint32_t *p) {
     if (threadIdx.x == 0) *p = 0;
 }
@@ -763,6 +885,15 @@ void build_chunk_segments(const TileArgs &t, const uint32_t *cell_of, const uint
     KTimer kt_("chunk_segments", s);
     k_chunk_segments<<<static_cast<unsigned>((total + kThreads - 1) / kThreads), kThreads, 0, s>>>(
         t, cell_of, starts, d, segs);
+    SJ_LAUNCH_CHECK();
+}
+
+void launch_chunk_words(const TileArgs &t, const uint32_t *cell_of, uint32_t d, int unicomp, uint32_t nslots,
+                        uint32_t *cwords, uint32_t *big, hipStream_t s) {
+    if (!nslots) return;
+    KTimer kt_("chunk_words", s);
+    k_chunk_words<<<(nslots + kThreads - 1) / kThreads, kThreads, 0, s>>>(t, cell_of, d, unicomp, nslots, cwords,
+                                                                          big);
     SJ_LAUNCH_CHECK();
 }
 

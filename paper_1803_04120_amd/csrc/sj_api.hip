@@ -200,6 +200,13 @@ struct sj_index {
     uint32_t rows_per_chunk = 0;
     DevBuf<uint2> segs;
     bool chunks_ready = false;
+    // hit bits of the last count pass (grid-row kernel, FP64, 5-D and up):
+    // word rows per chunk, their exclusive scan, the bits; bits_uni is the
+    // search (1 unicomp, 0 full) they were recorded for, -1 when none
+    DevBuf<uint32_t> cwords;
+    DevBuf<uint64_t> cbase;
+    DevBuf<uint32_t> hitbits;
+    int bits_uni = -1;
     // join state
     bool counted = false;
     sj_join_opts opts{};
@@ -550,6 +557,50 @@ void ensure_f32(sj_index &ix, hipStream_t s) {
     ix.y_ready = true;
 }
 
+// Hit bits for the fill pass (grid-row kernel, FP64, 5-D and up): the count
+// pass records each tested candidate's outcome so that the fill of the same
+// search reads them instead of testing again. Sized exactly from the chunks'
+// segments (one read-back); taken only when they fit in 40% of the device
+// memory that is free or cached by the pool (SJ_HIT_BITS=0: never).
+void prepare_hit_bits(sj_index &ix, int uni, sj::TileArgs &tt, hipStream_t s) {
+    ix.bits_uni = -1;
+    ix.hitbits.release();
+    if (ix.band_used || ix.d < sj::kHitBitsMinDim) return;
+    const char *e = std::getenv("SJ_HIT_BITS");
+    if (e && std::strcmp(e, "0") == 0) return;
+    const uint32_t nslots = ix.nchunks + 1;
+    ix.cwords.ensure(nslots + 1);  // the last word: the overflow flag
+    ix.cbase.ensure(nslots);
+    uint32_t *big = ix.cwords.ptr + nslots;
+    sj::launch_fill_u32(big, 1, 0u, s);
+    sj::launch_chunk_words(tt, ix.cell_of.ptr, ix.d, uni, nslots, ix.cwords.ptr, big, s);
+    sj::scan_exclusive_u32_to_u64(ix.cwords.ptr, ix.cbase.ptr, nslots, s);
+    sj::HostStage hs;
+    SJ_HIP(hipMemcpyAsync(hs.p, ix.cbase.ptr + (nslots - 1), sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(hs.as<uint32_t>() + 2, big, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    const uint64_t rows = *hs.as<uint64_t>();
+    if (hs.as<uint32_t>()[2] || rows == 0) return;
+    const uint64_t bytes = rows * 64 * sizeof(uint32_t);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    uint64_t cached = 0;
+    sj::pool_info(&cached, nullptr);
+    if (static_cast<double>(bytes) > 0.4 * static_cast<double>(free_b + cached)) return;
+    try {
+        ix.hitbits.reset(rows * 64);
+    } catch (const Error &err) {
+        if (err.code != SJ_ENOMEM) throw;
+        return;
+    }
+    tt.bits = ix.hitbits.ptr;
+    tt.cbase = ix.cbase.ptr;
+    ix.bits_uni = uni;
+}
+
 sj::JoinArgs base_args(sj_index &ix, int mode) {
     sj::JoinArgs a{};
     const auto &R = ix.ranges[mode];
@@ -622,8 +673,13 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     z.add(ix.counters.ptr, 2 * nctr);
     sj::launch_zero_spans(z, s);
     sj::JoinArgs a = base_args(ix, uni);
+    sj::TileArgs tt{};
+    if (tiled) {
+        tt = tile_args(ix);
+        prepare_hit_bits(ix, uni, tt, s);
+    }
     if (tiled)
-        sj::launch_join_tiled(a, tile_args(ix), ix.d, uni, sj::kCount, ix.band_used, s);
+        sj::launch_join_tiled(a, tt, ix.d, uni, sj::kCount, ix.band_used, s);
     else
         sj::launch_join(a, ix.d, uni, sj::kCount, ix.band_used, s);
     sj::launch_row_lengths(ix.own_cnt.ptr, uni ? ix.in_cnt.ptr : nullptr, ix.perm.ptr, n,
@@ -714,7 +770,19 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
         }
         if (whole && !ix.overflow_clear) sj::launch_fill_u32(a.overflow, 1, 0u, s);
         ix.overflow_clear = false;
-        sj::launch_join_tiled(a, tile_args(ix), ix.d, mode, sj::kFill, ix.band_used, s, ns);
+        // the count's hit bits when they were recorded for this search
+        sj::TileArgs tt = tile_args(ix);
+        const bool replay = !fused && ix.bits_uni == mode && ix.hitbits.ptr;
+        if (replay) {
+            tt.bits = ix.hitbits.ptr;
+            tt.cbase = ix.cbase.ptr;
+        }
+        sj::launch_join_tiled(a, tt, ix.d, mode, sj::kFill, ix.band_used, s, ns);
+        if (replay) {
+            // read once: the memory goes back to the pool when the call ends
+            ix.hitbits.release();
+            ix.bits_uni = -1;
+        }
         if (fused) {
             // the fused fill sorts rows of up to 64 itself
             sj::launch_rowsort_long(ix.off_cell.ptr, ix.off_orig.ptr, ix.perm.ptr, n, out_j, pairs,

@@ -12,6 +12,11 @@ namespace sj {
 
 constexpr int kMaxDim = 8;
 
+// From this many dimensions on, the grid-row kernel's count pass records hit
+// bits for the fill pass (below it the fill is bound by its writes, not by
+// its tests, and recording costs more than it saves).
+constexpr uint32_t kHitBitsMinDim = 5;
+
 // ---------------------------------------------------------------------
 // Grid description (Section IV-B), passed by value to kernels.
 // ---------------------------------------------------------------------
@@ -105,6 +110,14 @@ struct TileArgs {
     uint32_t chunk_end;       // end of the launch's chunk range (~0u: up to the count)
     uint32_t rows_per_chunk;  // 3^(d-1)
     const uint2 *segs;        // [chunk * rows_per_chunk + row] candidate point segment
+    // hit bits (null: off): the count pass records every tested candidate's
+    // outcome, the fill pass of the same search reads them instead of
+    // testing again. A run of s candidates of one lane takes ceil(s / 32)
+    // words, one word row of 64 lanes each ([word row][lane], candidate k
+    // of the run at bit 31 - k % 32 of word k / 32); a chunk's word rows
+    // start at cbase[chunk].
+    uint32_t *bits;
+    const uint64_t *cbase;
 };
 
 // Distance join of a query set R with an indexed set S (k_rs.hip).

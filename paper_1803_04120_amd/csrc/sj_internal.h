@@ -217,6 +217,10 @@ uint32_t build_chunks(const uint32_t *coords, const uint32_t *starts, uint32_t n
                       hipStream_t s);
 void build_chunk_segments(const TileArgs &t, const uint32_t *cell_of, const uint32_t *starts,
                           uint32_t d, uint2 *segs, hipStream_t s);
+// Word rows of hit bits per chunk (k_tile.hip): cwords[0, nslots) with
+// cwords[nslots - 1] = 0; *big set (atomic or) if a chunk overflows 32 bits.
+void launch_chunk_words(const TileArgs &t, const uint32_t *cell_of, uint32_t d, int unicomp, uint32_t nslots,
+                        uint32_t *cwords, uint32_t *big, hipStream_t s);
 void launch_join_tiled(const JoinArgs &a, const TileArgs &t, uint32_t d, int unicomp, int mode,
                        int band, hipStream_t s, uint32_t fused_sort = 0);
 
