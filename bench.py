@@ -147,6 +147,7 @@ class Workload:
             lens = np.diff(off.astype(np.int64))
             info.append(dict(tag=j["tag"], n=j["n"], d=j["d"], eps=j["eps"], pairs=P, cells=st["cells"],
                              evals=st["evals"], band_rechecks=st["band_rechecks"],
+                             hit_bit_bytes=st["hit_bit_bytes"],
                              max_cell=st["max_cell_points"], max_row=st["max_row_pairs"],
                              unicomp=unicomp, row_classes=row_classes(lens)))
         self.info = info
@@ -182,14 +183,17 @@ def kernel_model(name, i):
     kernel `name` in join i (sizes from the count pass), or None when the
     kernel is not modelled. Bytes count each array the kernel must touch
     once; operations count (3d - 1) per distance evaluation (d subtractions,
-    d multiplications, d - 1 additions)."""
+    d multiplications, d - 1 additions). With hit bits (5-D and up) the
+    count pass performs every evaluation once and writes the bits, and the
+    fill pass performs none: it reads the bits and writes the pairs."""
     n, d, P, cells = i["n"], i["d"], i["pairs"], i["cells"]
     U = i["evals"] if i["unicomp"] else (i["evals"] + n) // 2  # unicomp evaluations (U = (T + n) / 2)
     T = 2 * U - n
     ops_per_eval = 3 * d - 1
+    bits = i.get("hit_bit_bytes", 0)
     if name.startswith("tiled_count"):
         ev = U if "unicomp" in name else T
-        return n * (8 * d + 4 + 4) + 8 * (cells + 1), ev * ops_per_eval
+        return n * (8 * d + 4 + 4) + 8 * (cells + 1) + bits, ev * ops_per_eval
     if name.startswith("tiled_fill_sort"):
         # coordinates, cell coordinate, cell-order and final row offsets,
         # permutation entry per point; one 8-byte (i, j) pair per result pair
@@ -198,6 +202,8 @@ def kernel_model(name, i):
     if name.startswith("tiled_fill"):
         ev = U if "unicomp" in name else T
         extra = 4 * d * n if name.endswith("fp32band") else 0
+        if bits:
+            return n * (4 + 8 + 4) + bits + 4 * P, 0
         return n * (8 * d + 4 + 8 + 4) + extra + 4 * P, ev * ops_per_eval
     rc = i["row_classes"]
     if name == "rowsort_wave":

@@ -96,6 +96,8 @@ typedef struct sj_stats {
     uint64_t chunks;            /* wave work units of the grid-row tiled join (0 if unused) */
     uint32_t fill_unicomp;      /* 1 if the last fill evaluated the unicomp subset */
     uint32_t reserved0;
+    uint64_t hit_bit_bytes;     /* device bytes of the hit bits the last count pass recorded for its fill
+                                   (grid-row kernel, FP64, 5-D and up; 0 when none were recorded) */
 } sj_stats;
 
 /* ---- the index (Section IV-C: B, G, A, M plus the cell-ordered points) -- */

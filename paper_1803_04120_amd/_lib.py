@@ -66,7 +66,8 @@ class SjStats(ctypes.Structure):
                 ("ms_fill", ctypes.c_double),
                 ("chunks", ctypes.c_uint64),
                 ("fill_unicomp", ctypes.c_uint32),
-                ("reserved0", ctypes.c_uint32)]
+                ("reserved0", ctypes.c_uint32),
+                ("hit_bit_bytes", ctypes.c_uint64)]
 
 
 class SjKernelTime(ctypes.Structure):

@@ -564,6 +564,7 @@ void ensure_f32(sj_index &ix, hipStream_t s) {
 // memory that is free or cached by the pool (SJ_HIT_BITS=0: never).
 void prepare_hit_bits(sj_index &ix, int uni, sj::TileArgs &tt, hipStream_t s) {
     ix.bits_uni = -1;
+    ix.stats.hit_bit_bytes = 0;
     ix.hitbits.release();
     if (ix.band_used || ix.d < sj::kHitBitsMinDim) return;
     const char *e = std::getenv("SJ_HIT_BITS");
@@ -599,6 +600,7 @@ void prepare_hit_bits(sj_index &ix, int uni, sj::TileArgs &tt, hipStream_t s) {
     tt.bits = ix.hitbits.ptr;
     tt.cbase = ix.cbase.ptr;
     ix.bits_uni = uni;
+    ix.stats.hit_bit_bytes = bytes;
 }
 
 sj::JoinArgs base_args(sj_index &ix, int mode) {
@@ -637,6 +639,7 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     ix.pairs = 0;
     ix.max_row = 0;
     ix.stats.evals = ix.stats.band_rechecks = 0;
+    ix.stats.hit_bit_bytes = 0;
     ix.stats.pairs = 0;
     ix.stats.max_row_pairs = 0;
     ix.stats.unicomp_used = o.unicomp ? 1u : 0u;

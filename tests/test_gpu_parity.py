@@ -208,6 +208,24 @@ def test_fused_filter_straddling_pairs(sj, d):
             assert sj.last_run_stats()["band_rechecks"] >= found
 
 
+@pytest.mark.parametrize("d,uni", [(5, True), (6, False), (8, True)])
+def test_hit_bits_replay_matches_recompute(sj, d, uni, monkeypatch):
+    """From 5-D on the count pass records hit bits and the fill replays
+    them: the pair set must be the oracle's with and without them
+    (SJ_HIT_BITS=0), and the statistics must say which ran."""
+    n, eps = {5: (9001, 16.0), 6: (7919, 22.0), 8: (3001, 40.0)}[d]
+    _say(f"hit bits d={d} uni={uni}")
+    pts = datagen.uniform(n, d, seed=3000 + d)
+    want = ref.pairs(pts, eps)
+    got = gpu_pairs(sj, pts, eps, unicomp=uni)
+    assert sj.last_run_stats()["hit_bit_bytes"] > 0
+    assert_same(got, want, f"hit bits d={d} uni={uni}")
+    monkeypatch.setenv("SJ_HIT_BITS", "0")
+    got0 = gpu_pairs(sj, pts, eps, unicomp=uni)
+    assert sj.last_run_stats()["hit_bit_bytes"] == 0
+    assert_same(got0, want, f"no hit bits d={d} uni={uni}")
+
+
 def test_pairs_at_exact_eps_and_next_float(sj):
     """Pairs at exactly eps and at nextafter(eps) along every axis must be
     decided as the FP64 definition decides them, in both precisions."""
