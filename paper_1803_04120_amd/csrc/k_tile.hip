@@ -84,9 +84,11 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     // global slot reservation per candidate
     constexpr bool kMirAgg = (kMode == kFill) && kUni;
     // hit bits: recorded by the count pass and read back by the fill pass of
-    // the FP64 search from 4-D on (the fill then stages no coordinates and
-    // tests nothing)
-    constexpr bool kBits = !kBand && NS == 0 && D >= kFusedMinD && D >= static_cast<int>(kHitBitsMinDim);
+    // the same FP64 search (the fill then stages no coordinates and tests
+    // nothing). The FP32 pre-test's count spills registers with them (about
+    // 1 KiB per lane from 6-D on) and runs 2.5 times slower, so it goes
+    // without.
+    constexpr bool kBits = !kBand && NS == 0 && D >= static_cast<int>(kHitBitsMinDim);
     // staged coordinates; the fused fill reuses the slot after the last
     // tile for its write-out table (row destination, row id, length)
     constexpr size_t kStageBytes = sizeof(CT) * TS * D;

@@ -208,22 +208,34 @@ def test_fused_filter_straddling_pairs(sj, d):
             assert sj.last_run_stats()["band_rechecks"] >= found
 
 
-@pytest.mark.parametrize("d,uni", [(5, True), (6, False), (8, True)])
-def test_hit_bits_replay_matches_recompute(sj, d, uni, monkeypatch):
+@pytest.mark.parametrize("d,uni,prec", [(5, True, "fp64"), (6, False, "fp64"), (8, True, "fp64")])
+def test_hit_bits_replay_matches_recompute(sj, d, uni, prec, monkeypatch):
     """From 5-D on the count pass records hit bits and the fill replays
     them: the pair set must be the oracle's with and without them
     (SJ_HIT_BITS=0), and the statistics must say which ran."""
     n, eps = {5: (9001, 16.0), 6: (7919, 22.0), 8: (3001, 40.0)}[d]
-    _say(f"hit bits d={d} uni={uni}")
+    _say(f"hit bits d={d} uni={uni} {prec}")
     pts = datagen.uniform(n, d, seed=3000 + d)
     want = ref.pairs(pts, eps)
-    got = gpu_pairs(sj, pts, eps, unicomp=uni)
+    got = gpu_pairs(sj, pts, eps, unicomp=uni, precision=prec)
     assert sj.last_run_stats()["hit_bit_bytes"] > 0
-    assert_same(got, want, f"hit bits d={d} uni={uni}")
+    assert_same(got, want, f"hit bits d={d} uni={uni} {prec}")
     monkeypatch.setenv("SJ_HIT_BITS", "0")
-    got0 = gpu_pairs(sj, pts, eps, unicomp=uni)
+    got0 = gpu_pairs(sj, pts, eps, unicomp=uni, precision=prec)
     assert sj.last_run_stats()["hit_bit_bytes"] == 0
-    assert_same(got0, want, f"no hit bits d={d} uni={uni}")
+    assert_same(got0, want, f"no hit bits d={d} uni={uni} {prec}")
+
+
+def test_fp32_band_takes_no_hit_bits(sj):
+    """The FP32 pre-test path records no hit bits (its count would spill
+    registers) and still matches the oracle."""
+    _say("fp32 band without hit bits")
+    pts = datagen.uniform(7919, 6, seed=3006)
+    want = ref.pairs(pts, 22.0)
+    got = gpu_pairs(sj, pts, 22.0, precision="fp32_band")
+    st = sj.last_run_stats()
+    assert st["hit_bit_bytes"] == 0 and st["precision_used"] == 1
+    assert_same(got, want, "fp32 band 6-D")
 
 
 def test_pairs_at_exact_eps_and_next_float(sj):
