@@ -240,10 +240,11 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         // misses into the slot's spare last word -- so the common path has
         // no branch; a row longer than the slot keeps its first entries there
         // and writes the rest to out_j.
-        auto emit = [&](bool h, uint32_t i, uint32_t q, uint32_t id, bool mirror) {
+        auto emit = [&](bool h, uint32_t i, uint32_t q, uint32_t id) {
             if (kMode == kCount) {
                 own += h ? 1u : 0u;
-                if (h && mirror) atomicAdd(&saux[i], 1u);
+                // every unicomp hit, the self pair too (taken back after the tile)
+                if (kUni && h) atomicAdd(&saux[i], 1u);
             } else if (NS > 0) {
                 const uint32_t slot = own < static_cast<uint32_t>(NS) ? own : static_cast<uint32_t>(NS);
                 srow[h ? slot : static_cast<uint32_t>(NS)] = id;
@@ -260,7 +261,8 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 // disagreement is flagged at the end of the chunk)
                 wrow[own < wlim ? own : wlim] = id;
                 ++own;
-                if (kMirAgg && mirror) atomicOr(&smask[i], 1ull << lane);
+                // every unicomp hit, the self pair too (its bit cleared after the tile)
+                if (kMirAgg) atomicOr(&smask[i], 1ull << lane);
             }
         };
         // candidates [i0, i1) of the staged tile, kUnroll of them loaded and
@@ -278,7 +280,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                     const uint32_t b = static_cast<uint32_t>(__builtin_clz(w));
                     w &= ~(0x80000000u >> b);
                     const uint32_t i = i0 + 32 * k + b;
-                    emit(true, i, T0 + i, saux[i], kUni && T0 + i != p);
+                    emit(true, i, T0 + i, saux[i]);
                 }
             }
         };
@@ -304,7 +306,8 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             uint32_t hw = 0, ts = 0;
             uint32_t *const wrow_bits = kB ? t.bits + wb * 64 + static_cast<uint64_t>(lane) : nullptr;
             uint32_t i = i0;
-            for (; i + kUnroll <= i1; i += kUnroll) {
+            const uint32_t nit = (i1 - i0) / kUnroll;
+            for (uint32_t it = 0; it < nit; ++it, i += kUnroll) {
                 bool h[kUnroll];
                 uint32_t id[kUnroll];
 #pragma unroll
@@ -339,11 +342,11 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                     if (kUni && any) {
 #pragma unroll
                         for (int u = 0; u < kUnroll; ++u)
-                            if (h[u] && T0 + i + u != p) atomicAdd(&saux[i + u], 1u);
+                            if (h[u]) atomicAdd(&saux[i + u], 1u);
                     }
                 } else {
 #pragma unroll
-                    for (int u = 0; u < kUnroll; ++u) emit(h[u], i + u, T0 + i + u, id[u], kUni && T0 + i + u != p);
+                    for (int u = 0; u < kUnroll; ++u) emit(h[u], i + u, T0 + i + u, id[u]);
                 }
             }
             for (; i < i1; ++i) {
@@ -352,14 +355,14 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                 if (rec) {
                     // own hits counted with the word below
                     hw = (hw << 1) | (h ? 1u : 0u);
-                    if (kUni && h && T0 + i != p) atomicAdd(&saux[i], 1u);
+                    if (kUni && h) atomicAdd(&saux[i], 1u);
                     continue;
                 }
                 if (kMode == kCount && kRedo && kB && h) {
                     const uint32_t sk = i - i0;
                     atomicOr(wrow_bits + static_cast<uint64_t>(sk >> 5) * 64, 0x80000000u >> (sk & 31u));
                 }
-                emit(h, i, T0 + i, id, kUni && T0 + i != p);
+                emit(h, i, T0 + i, id);
             }
             if (rec) {
                 const uint32_t ns = i1 - i0, r = ns & 31u;
@@ -535,6 +538,11 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                     if (active) evaluate_tile(std::true_type{}, cur.T0, len, cur.own_row, wb);
                 }
             }
+            if (kAgg && cur.own_row && active && p >= cur.T0 && p - cur.T0 < len) {
+                // the self pair is no mirrored hit: its add taken back (p is
+                // always in its own window, so it was tested and hit)
+                atomicSub(&saux[p - cur.T0], 1u);
+            }
             if (kAgg) {
                 // one global add per candidate that collected mirrored hits
                 wave_sync_lds();
@@ -542,6 +550,10 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                     const uint32_t cnt = saux[i];
                     if (cnt) atomicAdd(&a.in_cnt[cur.T0 + i], cnt);
                 }
+            }
+            if (kMirAgg && cur.own_row && active && p >= cur.T0 && p - cur.T0 < len) {
+                // the self pair is no mirrored entry
+                atomicAnd(&smask[p - cur.T0], ~(1ull << lane));
             }
             if (kMirAgg) {
                 // each candidate's mirrored entries: one slot reservation in
