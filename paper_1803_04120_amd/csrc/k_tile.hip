@@ -77,12 +77,14 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     constexpr int TS = TileSize<D, NS>::value;
     constexpr int kRowStride = NS + 1;  // padded so lanes' slots fall in different banks
     using CT = typename std::conditional<kBand, float, double>::type;
+    constexpr bool kFillM = kMode != kCount;          // a fill pass (tested or replayed)
+    constexpr bool kRep = kMode == kReplay;           // the fill replays the count's hit bits
     constexpr bool kAgg = (kMode == kCount) && kUni;  // mirrored counts summed in LDS
-    constexpr bool kPerm = (kMode == kFill);          // candidate ids staged in LDS
+    constexpr bool kPerm = kFillM;                    // candidate ids staged in LDS
     // unicomp fill: the lanes that hit each staged candidate collected as a
     // mask in LDS, its mirrored entries written after the tile with one
     // global slot reservation per candidate
-    constexpr bool kMirAgg = (kMode == kFill) && kUni;
+    constexpr bool kMirAgg = kFillM && kUni;
     // hit bits: recorded by the count pass and read back by the fill pass of
     // the same FP64 search (the fill then stages no coordinates and tests
     // nothing). The FP32 pre-test's count spills registers with them (about
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     constexpr bool kBits = !kBand && NS == 0 && D >= static_cast<int>(kHitBitsMinDim);
     // staged coordinates; the fused fill reuses the slot after the last
     // tile for its write-out table (row destination, row id, length)
-    constexpr size_t kStageBytes = sizeof(CT) * TS * D;
+    constexpr size_t kStageBytes = kRep ? 16 : sizeof(CT) * TS * D;
     constexpr size_t kOutBytes = NS > 0 ? 64 * (8 + 4 + 4) : 0;
     __shared__ __align__(16) unsigned char sx_all[kWaves][kStageBytes > kOutBytes ? kStageBytes : kOutBytes];
     __shared__ uint32_t sc_all[kWaves][TS];
@@ -120,7 +122,10 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
     const uint32_t chunk = t.chunk0 + blockIdx.x * kWaves + wave;
     const uint32_t nch = *t.nchunks_dev;
     if (chunk < (t.chunk_end < nch ? t.chunk_end : nch)) {  // uniform across the wave
-        const bool bits_on = kBits && t.bits != nullptr;
+        // hit bits: recorded by the count, read by the replay (a tested fill
+        // takes none)
+        const bool bits_on = kBits && kMode != kFill && t.bits != nullptr;
+        if (kRep && !bits_on) return;  // a replay needs the bits (the host launches none without)
         // segment table of the chunk, 64 rows per register load; the first
         // load is issued before anything else (it needs only the chunk index)
         const uint2 *segs = t.segs + static_cast<size_t>(chunk) * t.rows_per_chunk;
@@ -141,17 +146,19 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         uint32_t *wrow = a.out_j;
         uint32_t wlim = 0;
         if (active) {
+            if (!kRep) {  // a replay tests nothing
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                xp[j] = a.Xq[static_cast<size_t>(j) * a.nqs + p];
-                if (kBand)
-                    yp[j] = static_cast<CT>(a.Yq[static_cast<size_t>(j) * a.nqs + p]);
-                else
-                    yp[j] = static_cast<CT>(xp[j]);
+                for (int j = 0; j < D; ++j) {
+                    xp[j] = a.Xq[static_cast<size_t>(j) * a.nqs + p];
+                    if (kBand)
+                        yp[j] = static_cast<CT>(a.Yq[static_cast<size_t>(j) * a.nqs + p]);
+                    else
+                        yp[j] = static_cast<CT>(xp[j]);
+                }
             }
             c0p = t.cxq[p];
             if (kUni) p_cell_start = a.starts[a.cell_of[p]];
-            if (kMode == kFill) {
+            if (kFillM) {
                 my_row = a.offc[p] - a.out_base;
                 perm_p = a.permq[p];
                 if (NS > 0) row_len = static_cast<uint32_t>(a.offc[p + 1] - a.offc[p]);
@@ -272,14 +279,23 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
         // step for the rare mirrored hits)
         constexpr int kUnroll = D <= 3 ? 4 : 2;
         // fill with hit bits: the set bits of the run's words, in order
+        // (all the run's words loaded first: one memory latency per run)
         auto replay = [&](uint32_t T0, uint32_t i0, uint32_t i1, uint64_t wb) {
             const uint32_t ns = i1 - i0;
-            for (uint32_t k = 0; 32 * k < ns; ++k) {
-                uint32_t w = t.bits[(wb + k) * 64 + static_cast<uint64_t>(lane)];
+            constexpr int kWords = TS / 32;
+            uint32_t wv[kWords];
+#pragma unroll
+            for (int k = 0; k < kWords; ++k)
+                wv[k] = static_cast<uint32_t>(32 * k) < ns
+                            ? t.bits[(wb + static_cast<uint64_t>(k)) * 64 + static_cast<uint64_t>(lane)]
+                            : 0u;
+#pragma unroll
+            for (int k = 0; k < kWords; ++k) {
+                uint32_t w = wv[k];
                 while (w) {
                     const uint32_t b = static_cast<uint32_t>(__builtin_clz(w));
                     w &= ~(0x80000000u >> b);
-                    const uint32_t i = i0 + 32 * k + b;
+                    const uint32_t i = i0 + 32 * static_cast<uint32_t>(k) + b;
                     emit(true, i, T0 + i, saux[i]);
                 }
             }
@@ -294,7 +310,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
                     return test(i, q);
             };
             if (i0 >= i1) return;
-            if (kMode == kFill && kB) {
+            if constexpr (kRep) {
                 replay(T0, i0, i1, wb);
                 return;
             }
@@ -517,7 +533,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             // (the registers cost waves per SIMD).
             for (uint32_t i = lane; i < len; i += 64) {
                 const size_t q = cur.T0 + i;
-                if (!(kMode == kFill && bits_on)) {
+                if (!kRep) {
 #pragma unroll
                     for (int j = 0; j < D; ++j)
                         sx[i * D + j] = kBand ? static_cast<CT>(a.Y[static_cast<size_t>(j) * a.n + q])
@@ -532,7 +548,7 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             const Tile nxt = advance(cur);
             wave_sync_lds();
             if (active) evaluate_tile(std::false_type{}, cur.T0, len, cur.own_row, wb);
-            if (!kBand && D >= kFusedMinD && !(kMode == kFill && bits_on)) {
+            if (!kBand && D >= kFusedMinD && !kRep) {
                 if (__builtin_amdgcn_readfirstlane(*sband)) {
                     *sband = 0u;
                     if (active) evaluate_tile(std::true_type{}, cur.T0, len, cur.own_row, wb);
@@ -580,9 +596,9 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             cur = nxt;
         }
         if (kMode == kCount && active) a.own_cnt[p] = own;
-        if (kMode == kFill && NS == 0 && active && (own != n_own || my_row + n_own > a.out_cap))
+        if (kFillM && NS == 0 && active && (own != n_own || my_row + n_own > a.out_cap))
             atomicOr(a.overflow, 1u);  // count and fill disagree, or the row is past the buffer
-        if (kMode == kFill && NS > 0 && !kUni) {
+        if (kFillM && NS > 0 && !kUni) {
             // the row of p is complete: sort it in registers; a row longer
             // than the LDS slot is in out_j for the row-sort kernels
             constexpr int kNs = NS <= 0 ? 1 : (NS <= 16 ? 16 : (NS <= 32 ? 32 : 64));  // sort width >= NS
@@ -707,7 +723,7 @@ void launch_tiled_one(const JoinArgs &a, const TileArgs &t, hipStream_t s) {
     const unsigned nb = (span + kWaves - 1) / kWaves;
     if (nb == 0) return;
     KTimer kt_(NS ? (BD ? "tiled_fill_sort_full_fp32band" : "tiled_fill_sort_full_fp64")
-                  : kTiledNames[M * 4 + (U ? 2 : 0) + (BD ? 1 : 0)],
+                  : kTiledNames[(M == kCount ? 0 : 4) + (U ? 2 : 0) + (BD ? 1 : 0)],
                s);
     k_join_tiled<D, U, M, BD, NS><<<nb, kThreads, 0, s>>>(a, t);
     SJ_LAUNCH_CHECK();
@@ -716,6 +732,17 @@ void launch_tiled_one(const JoinArgs &a, const TileArgs &t, hipStream_t s) {
 template <int D>
 void launch_tiled_d(const JoinArgs &a, const TileArgs &t, int unicomp, int mode, int band,
                     hipStream_t s, uint32_t fused_sort) {
+    if (mode == kReplay) {
+        if (band || fused_sort) throw Error(SJ_EINVAL, "tiled join: a replayed fill is FP64 without a fused sort");
+        if constexpr (D >= static_cast<int>(kHitBitsMinDim)) {
+            if (unicomp)
+                launch_tiled_one<D, true, kReplay, false, 0>(a, t, s);
+            else
+                launch_tiled_one<D, false, kReplay, false, 0>(a, t, s);
+            return;
+        }
+        throw Error(SJ_EINVAL, "tiled join: no hit bits below their dimension");
+    }
     const int sel = (mode == kFill ? 4 : 0) + (unicomp ? 2 : 0) + (band ? 1 : 0);
     if (sel == 4 && fused_sort == 16) return launch_tiled_one<D, false, kFill, false, 16>(a, t, s);
     if (sel == 4 && fused_sort == 24) return launch_tiled_one<D, false, kFill, false, 24>(a, t, s);

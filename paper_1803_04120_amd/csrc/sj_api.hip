@@ -780,7 +780,7 @@ void fill_rows(sj_index &ix, uint64_t i0, uint64_t i1, uint64_t base, uint64_t c
             tt.bits = ix.hitbits.ptr;
             tt.cbase = ix.cbase.ptr;
         }
-        sj::launch_join_tiled(a, tt, ix.d, mode, sj::kFill, ix.band_used, s, ns);
+        sj::launch_join_tiled(a, tt, ix.d, mode, replay ? sj::kReplay : sj::kFill, ix.band_used, s, ns);
         if (replay) {
             // read once: the memory goes back to the pool when the call ends
             ix.hitbits.release();

@@ -88,7 +88,10 @@ struct JoinArgs {
     const uint64_t *off_orig;
     uint2 *pairs;
 };
-enum JoinMode { kCount = 0, kFill = 1 };
+// kReplay: the fill pass of a search whose count recorded hit bits (it
+// stages no coordinates and tests nothing; grid-row kernel, FP64, from
+// kHitBitsMinDim dimensions on)
+enum JoinMode { kCount = 0, kFill = 1, kReplay = 2 };
 
 // Grid-row tiled join (k_tile.hip): chunks of <= 64 cell-ordered points of
 // one grid row, candidate rows staged in LDS.
