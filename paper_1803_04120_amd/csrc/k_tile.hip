@@ -322,8 +322,11 @@ __global__ __launch_bounds__(kThreads) void k_join_tiled(JoinArgs a, TileArgs t)
             uint32_t hw = 0, ts = 0;
             uint32_t *const wrow_bits = kB ? t.bits + wb * 64 + static_cast<uint64_t>(lane) : nullptr;
             uint32_t i = i0;
+            // from 4-D on the loop runs a per-lane trip count against a
+            // wave-uniform step (one compare per step); below, the plain
+            // bound is faster (2-D full count: 46.7 against 61.6 us)
             const uint32_t nit = (i1 - i0) / kUnroll;
-            for (uint32_t it = 0; it < nit; ++it, i += kUnroll) {
+            for (uint32_t it = 0; D >= 4 ? it < nit : i + kUnroll <= i1; ++it, i += kUnroll) {
                 bool h[kUnroll];
                 uint32_t id[kUnroll];
 #pragma unroll
