@@ -147,7 +147,7 @@ class Workload:
             lens = np.diff(off.astype(np.int64))
             info.append(dict(tag=j["tag"], n=j["n"], d=j["d"], eps=j["eps"], pairs=P, cells=st["cells"],
                              evals=st["evals"], band_rechecks=st["band_rechecks"],
-                             hit_bit_bytes=st["hit_bit_bytes"],
+                             hit_bit_bytes=st["hit_bit_bytes"], precision_used=st["precision_used"],
                              max_cell=st["max_cell_points"], max_row=st["max_row_pairs"],
                              unicomp=unicomp, row_classes=row_classes(lens)))
         self.info = info
@@ -242,6 +242,11 @@ def launched_in(name, i, fill_unicomp):
     """Whether join i launches kernel `name` (which fill and row sorts run)."""
     d = i["d"]
     fused = d <= 3 and not fill_unicomp
+    # an FP32 pre-test request runs the FP64 kernels where the library
+    # chose them (from 6-D on)
+    if name.startswith("tiled_") and name.endswith(("fp64", "fp32band")):
+        if name.endswith("fp32band") != (i.get("precision_used", 0) == 1):
+            return False
     if name.startswith("tiled_count"):
         return ("unicomp" in name) == bool(i["unicomp"])
     if name.startswith("tiled_fill_sort"):

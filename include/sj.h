@@ -51,7 +51,9 @@ extern "C" {
 
 /* ---- options ---------------------------------------------------------- */
 #define SJ_FP64      0    /* distances in binary64 */
-#define SJ_FP32_BAND 1    /* binary32 pre-test, binary64 re-decision inside the band */
+#define SJ_FP32_BAND 1    /* binary32 pre-test, binary64 re-decision inside the band; on the grid-row
+                             kernel up to 5-D only: from 6-D on the binary64 path is faster and runs
+                             instead (same pairs; sj_stats.precision_used says which ran) */
 
 typedef struct sj_join_opts {
     int32_t  unicomp;              /* 1: evaluate each unordered pair of adjacent

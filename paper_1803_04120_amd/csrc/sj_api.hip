@@ -644,7 +644,14 @@ void join_count(sj_index &ix, const sj_join_opts &o, hipStream_t s) {
     ix.stats.max_row_pairs = 0;
     ix.stats.unicomp_used = o.unicomp ? 1u : 0u;
     ix.band_used = 0;
-    if (o.precision == SJ_FP32_BAND && ix.n > 0)
+    // The FP32 pre-test runs up to 5-D. From 6-D on the grid-row kernel's FP64
+    // path (fused-square filter, hit bits) is the faster one and runs instead
+    // (same pairs; precision_used says which ran): 10M uniform points,
+    // count + fill, 6-D at 32 and 256 neighbours 52.4 / 170.0 ms with the
+    // pre-test against 45.8 / 133.3 ms without; at 3..5-D the pre-test is
+    // 2-7% faster.
+    constexpr uint32_t kBandMaxDimTiled = 5;
+    if (o.precision == SJ_FP32_BAND && ix.n > 0 && !(use_tiled() && ix.d > kBandMaxDimTiled))
         ix.band_used = band_thresholds(ix.d, ix.eps, ix.extent, &ix.lo, &ix.hi) ? 1 : 0;
     ix.stats.precision_used = ix.band_used ? SJ_FP32_BAND : SJ_FP64;
     if (ix.n == 0) {

@@ -226,16 +226,22 @@ def test_hit_bits_replay_matches_recompute(sj, d, uni, prec, monkeypatch):
     assert_same(got0, want, f"no hit bits d={d} uni={uni} {prec}")
 
 
-def test_fp32_band_takes_no_hit_bits(sj):
-    """The FP32 pre-test path records no hit bits (its count would spill
-    registers) and still matches the oracle."""
-    _say("fp32 band without hit bits")
-    pts = datagen.uniform(7919, 6, seed=3006)
-    want = ref.pairs(pts, 22.0)
-    got = gpu_pairs(sj, pts, 22.0, precision="fp32_band")
-    st = sj.last_run_stats()
-    assert st["hit_bit_bytes"] == 0 and st["precision_used"] == 1
-    assert_same(got, want, "fp32 band 6-D")
+def test_fp32_band_request_by_dimension(sj):
+    """An FP32 pre-test request runs the pre-test up to 5-D (without hit
+    bits: its count would spill registers with them) and the faster FP64
+    path from 6-D on; precision_used says which, and both give the oracle's
+    pairs."""
+    for d, n, eps in ((5, 9001, 16.0), (6, 7919, 22.0)):
+        _say(f"fp32 band request d={d}")
+        pts = datagen.uniform(n, d, seed=3000 + d)
+        want = ref.pairs(pts, eps)
+        got = gpu_pairs(sj, pts, eps, precision="fp32_band")
+        st = sj.last_run_stats()
+        assert_same(got, want, f"fp32 band request d={d}")
+        if d <= 5:
+            assert st["precision_used"] == 1 and st["hit_bit_bytes"] == 0
+        else:
+            assert st["precision_used"] == 0 and st["hit_bit_bytes"] > 0
 
 
 def test_pairs_at_exact_eps_and_next_float(sj):
