@@ -366,7 +366,9 @@ def sweep_leg(sj, _lib, torch, wl, steps, unicomp=True, precision="fp64", label=
     if mod:
         dom = max(mod, key=lambda k: mod[k][1])
         r, hbm, valu = roofline_of(dom, *mod[dom])
-        r["traffic"] = measured_traffic(dom, wl.name)
+        # the profiles are of the FP64 runs: a request for the FP32 pre-test
+        # runs other launches of the same kernels
+        r["traffic"] = measured_traffic(dom, wl.name) if precision == "fp64" else None
         res["roofline"] = r
         res["hbm_roofline"], res["valu_roofline"] = hbm, valu
     log(f"[bench] {label or wl.name} {precision} unicomp={unicomp}: {res['pairs_per_s']:.4g} pairs/s, "
