@@ -160,12 +160,14 @@ def test_empty_and_single(sj):
         np.testing.assert_array_equal(out, [[0, 0]])
 
 
-@pytest.mark.parametrize("n", [1, 63, 64, 65, 1024, 1025, 3000, 16385, 17000])
-def test_identical_points_one_cell(sj, n):
+@pytest.mark.parametrize("n,d", [(1, 3), (63, 3), (64, 3), (65, 3), (1024, 3), (1025, 3), (3000, 3), (16385, 3),
+                                 (17000, 3), (65, 6), (1025, 6), (3000, 6)])
+def test_identical_points_one_cell(sj, n, d):
     """All points equal: one cell, every row has n entries (exercises every
-    row-sort size class, including rows longer than a workgroup's LDS)."""
-    _say(f"identical points n={n}")
-    x = torch.full((n, 3), 7.25, dtype=torch.float64, device="cuda")
+    row-sort size class, including rows longer than a workgroup's LDS; in
+    6-D windows of many tiles with hit bits)."""
+    _say(f"identical points n={n} d={d}")
+    x = torch.full((n, d), 7.25, dtype=torch.float64, device="cuda")
     for uni in (True, False):
         got = sj.selfjoin(x, 0.5, unicomp=uni)
         assert got.shape[0] == n * n
@@ -267,11 +269,16 @@ def test_pairs_at_exact_eps_and_next_float(sj):
             assert_same(got, want, f"exact-eps d={d} {prec}")
 
 
-def test_eps_covers_everything(sj):
-    _say("eps larger than the data extent")
-    pts = datagen.uniform(2500, 3, seed=8)
+@pytest.mark.parametrize("d", [3, 6])
+def test_eps_covers_everything(sj, d):
+    """eps beyond the extent: every pair, every candidate a hit (in 6-D every
+    recorded hit bit set)."""
+    _say(f"eps larger than the data extent d={d}")
+    pts = datagen.uniform(2500, d, seed=8)
     got = gpu_pairs(sj, pts, 1000.0)
     assert got.shape[0] == 2500 * 2500
+    k = np.arange(2500 * 2500, dtype=np.int64)
+    assert np.array_equal(got[:, 0], k // 2500) and np.array_equal(got[:, 1], k % 2500)
 
 
 def test_duplicates_and_far_outlier(sj):
