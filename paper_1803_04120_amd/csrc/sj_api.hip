@@ -924,6 +924,12 @@ int join_batched_cells(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
         if (std::strcmp(e, "runs") == 0) whole_fill = false;
         if (std::strcmp(e, "whole") == 0) whole_fill = tiled && ix.opts.unicomp;
     }
+    // per-run fills test again (the hit bits serve the whole fill only):
+    // their memory goes back to the pool before the runs' buffers are taken
+    if (!whole_fill) {
+        ix.hitbits.release();
+        ix.bits_uni = -1;
+    }
     ix.stats.fill_unicomp = whole_fill ? 1u : 0u;  // else every point writes its own row
     const bool fused = tiled && !whole_fill && use_fused_sort(ix.d);
     const uint32_t ns = fused ? fused_slot(ix) : 0;
@@ -1052,6 +1058,8 @@ int join_batched_cells(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
 int join_batched_rows(sj_index &ix, sj_run_cb cb, void *user, hipStream_t s) {
     const double t0 = now_ms();
     const uint64_t n = ix.n, P = ix.pairs;
+    ix.hitbits.release();  // ranges of i test again; the bits serve only the whole fill
+    ix.bits_uni = -1;
     if (n == 0 || P == 0) {
         ix.stats.batches = 0;
         return 0;
