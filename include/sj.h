@@ -129,6 +129,12 @@ void sj_destroy_index(sj_index *idx);
  * unicomp when opts->unicomp): computes every result row's length and the
  * row offsets, and returns the number of pairs P in *total_pairs. It must
  * precede sj_join_fill on the same index; opts is remembered for the fill.
+ * From 5-D on (binary64, grid-row kernel) it also records every tested
+ * candidate's outcome for the fill ("hit bits", sj_stats.hit_bit_bytes), in
+ * device memory the index holds until a whole-result fill has read them, the
+ * next count, or sj_destroy_index; it takes them only when they fit in 40% of
+ * the device memory that is free or cached by the library's pool
+ * (SJ_HIT_BITS=0 in the environment: never).
  */
 int sj_join_count(sj_index *idx, const sj_join_opts *opts, void *stream,
                   uint64_t *total_pairs);
