@@ -27,7 +27,14 @@
 // window is symmetric (q is in p's window exactly when p is in q's), so each
 // pair within eps is still evaluated exactly once.
 //
-// Pair test, counters and emission are those of the per-point kernel.
+// Pair test, counters and emission are those of the per-point kernel, with
+// two additions of this kernel. From 4-D on the FP64 test sums the squared
+// differences with fused multiply-adds and decides directly only outside a
+// band around eps^2 that bounds that sum's distance from the predicate's
+// left-to-right sum; a tile with a candidate inside the band is passed again
+// for those candidates with the exact sum. From 5-D on the count pass stores
+// every tested candidate's outcome as a bit (hit bits) and the fill of the
+// same search (kReplay) emits from the bits instead of testing again.
 //
 // The distance join of a query set R with S (Section II: the self-join is
 // its case R = S) runs the same kernel with the full search: the queries are
