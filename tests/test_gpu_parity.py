@@ -210,6 +210,24 @@ def test_fused_filter_straddling_pairs(sj, d):
             assert sj.last_run_stats()["band_rechecks"] >= found
 
 
+@pytest.mark.parametrize("d", [4, 6])
+@pytest.mark.parametrize("scale,eps", [(2e-160, 1.5e-160), (1e151, 3.3e150)])
+def test_fused_filter_extreme_eps(sj, d, scale, eps):
+    """eps^2 below 2^-900 (subnormal squares) or above 2^1000: the fused-square
+    filter's band cannot be trusted there, so every candidate goes to the
+    exact sum; the pair set must still be the oracle's."""
+    _say(f"extreme eps d={d} scale={scale:g} eps={eps:g}")
+    g = np.random.default_rng(d)
+    pts = g.uniform(0.0, 1.0, size=(1500, d)) * scale
+    want = ref.pairs(pts, eps)
+    assert 1500 < want.shape[0] < 1500 * 1500  # neither only the self pairs nor every pair
+    for uni in (True, False):
+        got = gpu_pairs(sj, pts, eps, unicomp=uni, precision="fp64")
+        assert_same(got, want, f"extreme eps d={d} scale={scale:g} uni={uni}")
+        st = sj.last_run_stats()
+        assert st["band_rechecks"] == st["evals"]  # every candidate to the exact sum
+
+
 @pytest.mark.parametrize("d,uni,prec", [(5, True, "fp64"), (6, False, "fp64"), (8, True, "fp64")])
 def test_hit_bits_replay_matches_recompute(sj, d, uni, prec, monkeypatch):
     """From 5-D on the count pass records hit bits and the fill replays
